@@ -1,0 +1,122 @@
+"""Pins for the oracle's per-mode solve against closed forms and invariants.
+
+* steady channel: the parabolic profile and linear pressure lie in the
+  quadratic/linear spaces, so the discrete solution is exact to rounding
+  (section 3.2 makes the same observation);
+* oscillatory channel and pipe: third-order L2 velocity convergence
+  (Eq. int_error; section 3.4 reports it for the pipe with curved
+  boundary nodes);
+* conjugation symmetry u(-w, conj f) = conj u(w, f), linearity, and zero net
+  boundary flux of the discrete solution (the constant pressure is a test
+  function)."""
+import numpy as np
+import pytest
+
+from oracle import exact
+from oracle.assemble import boundary_loads
+from oracle.solve import case_setup, solve_modes, system_matrix, constrained_dofs, system_rhs
+from workloads import cases
+
+
+def test_steady_channel_exact():
+    c = cases.channel_case()
+    asm, loads, wall, dirn, g = case_setup(c)
+    u, p, res, _ = solve_modes(asm, loads, wall, dirn, c["omega"][:1], c["rho"], c["mu"],
+                               c["traction"][:1], g[:1])
+    P = c["traction"][0, 0]
+    X = asm["node_xyz"]
+    ue = exact.channel_velocity(X[:, 1] - 0.5, 0.0, P, c["mu"], c["rho"], 4.0, 0.5)
+    pe = exact.channel_pressure(X[: asm["nv"], 0], P, 4.0)
+    assert np.abs(u[0, :, 0] - ue).max() < 1e-12 * np.abs(ue).max()
+    assert np.abs(u[0, :, 1]).max() < 1e-12 * np.abs(ue).max()
+    assert np.abs(p[0] - pe).max() < 1e-12 * np.abs(pe).max()
+    assert res[0] < 1e-14
+
+
+def _channel_errors(ny, W):
+    c = cases.channel_case(nx=4 * ny, ny=ny, n_harm=1)
+    H, mu, rho = 0.5, c["mu"], c["rho"]
+    w = W * (mu / rho) / H**2
+    c["omega"] = np.array([w])
+    c["traction"] = np.array([[1.0 + 0j]])
+    asm, loads, wall, dirn, g = case_setup(c)
+    u, p, _, _ = solve_modes(asm, loads, wall, dirn, c["omega"], rho, mu, c["traction"], g)
+    fu = lambda x: np.stack([exact.channel_velocity(x[:, 1] - H, w, 1.0, mu, rho, 4.0, H),
+                             0 * x[:, 0]], 1)
+    fp = lambda x: exact.channel_pressure(x[:, 0], 1.0, 4.0)
+    return exact.l2_error(c["mesh"], asm, u[0], fu, p[0], fp)
+
+
+def test_channel_womersley_third_order():
+    errs = [_channel_errors(ny, 10 * np.pi) for ny in (4, 8, 16)]
+    eu = np.array([e[0] for e in errs])
+    rates = np.log2(eu[:-1] / eu[1:])
+    assert rates[-1] > 2.7, rates
+
+
+def _pipe_errors(nr, curved):
+    c = cases.pipe_case(h=1.0 / nr, length=2.0, n_harm=1, curved=curved)
+    asm, loads, wall, dirn, g = case_setup(c)
+    u, p, _, _ = solve_modes(asm, loads, wall, dirn, c["omega"], c["rho"], c["mu"],
+                             c["traction"], g)
+    out = []
+    for s in range(2):
+        w, Q = c["omega"][s], c["inlet_amp"][s]
+        fu = lambda x: np.stack([0 * x[:, 0], 0 * x[:, 0], exact.pipe_velocity(
+            np.minimum(np.hypot(x[:, 0], x[:, 1]), 1.0), w, Q, c["mu"], c["rho"], 1.0)], 1)
+        out.append(exact.l2_error(c["mesh"], asm, u[s], fu)[0])
+    return np.array(out)
+
+
+def test_pipe_curved_third_order():
+    """Womersley pipe (W = 8 pi at k=1) with boundary midside nodes on the
+    cylinder converges at about third order; straight walls do not."""
+    e = np.array([_pipe_errors(nr, True) for nr in (2, 3, 4)])
+    h = 1.0 / np.array([2, 3, 4])
+    rate = np.log(e[-2] / e[-1]) / np.log(h[-2] / h[-1])
+    # steady mode: asymptotic third order; W = 8 pi still resolves its
+    # Stokes layer (thickness ~ R/sqrt(W) = 0.2) with only a few cells
+    assert rate[0] > 3.0 and rate[1] > 2.4, rate
+    hs = np.array([1.0 / 3, 1.0 / 4])
+    es3 = np.array([_pipe_errors(nr, False) for nr in (3, 4)])
+    rate_s = np.log(es3[0] / es3[1]) / np.log(hs[0] / hs[1])
+    assert np.all(rate_s < 2.2) and np.all(rate > rate_s + 0.4), (rate, rate_s)
+
+
+def test_conjugation_symmetry_and_linearity():
+    c = cases.pipe_case(h=0.5, length=2.0, n_harm=2)
+    asm, loads, wall, dirn, g = case_setup(c)
+    w = c["omega"][1]
+    om = np.array([w, -w])
+    gg = np.stack([g[1], np.conj(g[1])])
+    u, p, _, _ = solve_modes(asm, loads, wall, dirn, om, c["rho"], c["mu"],
+                             np.zeros((2, 0), complex), gg)
+    assert np.abs(u[1] - np.conj(u[0])).max() < 1e-12 * np.abs(u[0]).max()
+    assert np.abs(p[1] - np.conj(p[0])).max() < 1e-12 * np.abs(p[0]).max()
+    a, b = 0.3 - 1.1j, -2.0 + 0.5j
+    g3 = np.stack([g[1], g[2] * 0 + 1j * g[1], a * g[1] + b * 1j * g[1]])
+    u3, p3, _, _ = solve_modes(asm, loads, wall, dirn, np.array([w, w, w]), c["rho"], c["mu"],
+                               np.zeros((3, 0), complex), g3)
+    assert np.abs(u3[2] - (a * u3[0] + b * u3[1])).max() < 1e-12 * np.abs(u3[2]).max()
+
+
+def test_zero_net_boundary_flux():
+    c = cases.pipe_case(h=0.5, length=2.0, n_harm=2)
+    asm, loads, wall, dirn, g = case_setup(c)
+    u, p, _, _ = solve_modes(asm, loads, wall, dirn, c["omega"], c["rho"], c["mu"],
+                             c["traction"], g)
+    lo = boundary_loads(c["mesh"], asm, [1, 2, 3])  # int M_A n per tag
+    for s in range(3):
+        fl = np.array([np.sum(lo[t] * u[s]) for t in range(3)])
+        assert abs(fl.sum()) < 1e-12 * abs(fl[0])
+        assert abs(fl[0]) > 0.5 * abs(c["inlet_amp"][s])
+
+
+def test_channel_traction_sign():
+    """A positive inlet pressure drives flow in +x (h = -P n, n = -e_x)."""
+    c = cases.channel_case(n_harm=1)
+    c["traction"] = np.array([[1.0 + 0j], [0j]])
+    asm, loads, wall, dirn, g = case_setup(c)
+    u, _, _, _ = solve_modes(asm, loads, wall, dirn, c["omega"][:1], c["rho"], c["mu"],
+                             c["traction"][:1], g[:1])
+    assert u[0, :, 0].real.max() > 0 and u[0, :, 0].real.min() >= -1e-14
