@@ -1,0 +1,225 @@
+/*
+ * scvs.h -- C ABI of the MI355X (gfx950) spectral complex-valued Stokes library.
+ *
+ * The method (Meng, Bhattacharjee & Esmaily, arXiv 2009.06725) turns a
+ * time-periodic creeping flow into independent Fourier modes (section 2.1,
+ * Eqs. vaptransform and stokes_complex). For every mode w_k it solves the
+ * complex Taylor-Hood (quadratic velocity, linear pressure) saddle-point
+ * system of section 2.3 (Eqs. linear_sys_def and LS_construction)
+ *     [ I_d (x) (mu Ks + j w rho M)   G ] [u]   [f_u]
+ *     [ G^T                           0 ] [p] = [f_p]
+ * and reconstructs the fields in time (section 2.4, Eq. sol_reconstruct).
+ *
+ * Conventions used by every entry point:
+ *  - Status codes: 0 = success, negative = error (see SCVS_E_*). On error
+ *    scvs_last_error() returns a thread-local message. No entry point throws
+ *    or aborts across the ABI. Validation errors write no output.
+ *  - Pointers documented "host" are read or written synchronously. Pointers
+ *    documented "device" must be device memory of the context's device; the
+ *    caller owns them (the library never frees them). Work on device buffers
+ *    is ordered on the context's stream; entry points that return host data
+ *    synchronize that stream.
+ *  - Complex numbers are (re, im) pairs of double ("c128").
+ *  - Numbering (section 2.3, Eq. shape_fun, with this library's reading):
+ *    quadratic node A < nv is vertex A; node nv + e is the midside node of
+ *    edge e, where edges are the unique vertex pairs {a<b} of all cells
+ *    sorted lexicographically. Cell-local node order: the d+1 vertices, then
+ *    edges (0,1),(1,2),(0,2) and in 3D (0,3),(1,3),(2,3).
+ *  - Unknown layout of one system ("DOF vector", length ndof = d*n2 + nv):
+ *    velocity of node A, component c at index d*A + c, then pressure of
+ *    vertex v at index d*n2 + v.
+ *  - Dirichlet (wall and prescribed-inflow) unknowns stay in the numbering;
+ *    their rows and columns of the system are identity and their value is
+ *    the prescribed one.
+ */
+#ifndef SCVS_H
+#define SCVS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SCVS_OK 0
+#define SCVS_E_INVALID (-1)   /* bad argument (null, negative size, out-of-range index) */
+#define SCVS_E_MESH (-2)      /* malformed mesh (degenerate cell, node index range) */
+#define SCVS_E_NOMEM (-3)     /* device or host allocation failed */
+#define SCVS_E_HIP (-4)       /* a HIP runtime call failed */
+#define SCVS_E_STATE (-5)     /* call out of order (e.g. solve before assemble) */
+#define SCVS_E_CAPACITY (-6)  /* a fixed internal capacity was exceeded */
+
+/* Boundary-condition kinds per boundary tag (section 2.1, Eq. steady_stokes). */
+#define SCVS_BC_FREE 0      /* zero traction */
+#define SCVS_BC_WALL 1      /* u = 0 (no slip) */
+#define SCVS_BC_DIRICHLET 2 /* u = g, g supplied per system at the Dirichlet nodes */
+#define SCVS_BC_TRACTION 3  /* normal-pressure traction h = -P n, P supplied per system */
+
+/* Precedence where tags meet: WALL over DIRICHLET over traction/free. */
+
+typedef struct scvs_ctx_s* scvs_ctx;
+typedef struct scvs_mesh_s* scvs_mesh;
+
+/* Thread-local message of the last failed call on this thread ("" if none). */
+const char* scvs_last_error(void);
+
+/* Library version string (static storage). */
+const char* scvs_version(void);
+
+/* Create a context on HIP device `device`. `stream` is a hipStream_t (may be
+ * NULL for the null stream); the library launches all work on it and does not
+ * take ownership. */
+int scvs_ctx_create(int device, void* stream, scvs_ctx* out);
+int scvs_ctx_destroy(scvs_ctx ctx);
+
+/* ---- a1: mesh ingest, numbering, sparsity (section 2.3, Eq. shape_fun) ----
+ * dim 2 (triangles) or 3 (tets). Host inputs, copied:
+ *   xyz    double[nv][dim]    vertex coordinates
+ *   cells  int32[nc][dim+1]   vertex indices (any orientation)
+ *   bfaces int32[nf][dim]     boundary facets, ordered so their normal points
+ *                             out of the domain (2D: domain on the left of
+ *                             a->b; 3D: (b-a)x(c-a) outward)
+ *   btags  int32[nf]          tag per facet (any non-negative integers)
+ * Builds on the device: vertex->cell adjacency, the canonical edge list, the
+ * cell->node map and the sorted CSR pattern S2 of quadratic node pairs that
+ * share a cell. The vertex-vertex pattern C21 is the vertex-column prefix of
+ * each S2 row, and the transpose pattern C12 equals the S2 rows of vertices.
+ * Errors: SCVS_E_INVALID (null/negative), SCVS_E_MESH (index out of range),
+ * SCVS_E_CAPACITY (a row needs more than 4096 candidate entries). */
+int scvs_mesh_create(scvs_ctx ctx, int dim, int64_t nv, const double* xyz, int64_t nc,
+                     const int32_t* cells, int64_t nf, const int32_t* bfaces,
+                     const int32_t* btags, scvs_mesh* out);
+int scvs_mesh_destroy(scvs_mesh mesh);
+
+typedef struct {
+  int32_t dim;
+  int64_t nv, nc, nf, ne, n2; /* vertices, cells, facets, edges, quadratic nodes */
+  int64_t ndof;               /* dim*n2 + nv complex unknowns per system */
+  int64_t nnz_s2, nnz_c21;    /* pattern sizes */
+  int64_t ndir;               /* number of DIRICHLET (non-wall) nodes, after set_bc */
+  int32_t ntraction;          /* number of TRACTION tags, after set_bc */
+  int32_t assembled;          /* 1 after scvs_assemble */
+} scvs_mesh_info_t;
+int scvs_mesh_info(scvs_mesh mesh, scvs_mesh_info_t* info);
+
+/* Curved boundary (section 3.1: inserted boundary nodes are projected onto the
+ * curved surface). `n` edges given by their two vertex indices (any order)
+ * and the position of their midside node (host, double[n][dim]). Must be
+ * called before scvs_assemble. Errors: SCVS_E_INVALID if a pair is not an edge. */
+int scvs_mesh_set_midside(scvs_mesh mesh, int64_t n, const int32_t* edge_vertices,
+                          const double* xyz);
+
+/* Boundary conditions: kind per tag (SCVS_BC_*); tags not listed are FREE.
+ * Computes the Dirichlet node sets and, per TRACTION tag (in ascending tag
+ * order), n^tau_A = int_{Gamma_tau} M_A n dGamma. May be called again. */
+int scvs_mesh_set_bc(scvs_mesh mesh, int n, const int32_t* tags, const int32_t* kinds);
+
+/* ---- a2: element assembly (section 2.3, Eq. LS_construction) ----
+ * Assembles the mode-independent matrices
+ *   Ks_AB = int grad M_A . grad M_B,  M_AB = int M_A M_B   (S2 order)
+ *   G^c_Av = -int d_c M_A N_v                              (C21 order)
+ * by degree-5 Grundmann-Moeller quadrature on (possibly curved, quadratic)
+ * cells, the dense element contraction on FP64 matrix cores, and a
+ * deterministic per-slot sum in ascending cell order. rho, mu > 0 are stored
+ * for the solves. Requires set_bc first (the preconditioner diagonals use the
+ * Dirichlet set). */
+int scvs_assemble(scvs_mesh mesh, double rho, double mu);
+
+/* Host copies of mesh data for tests. Sizes from scvs_mesh_info:
+ *  SCVS_X_EDGES    int32[ne][2]      SCVS_X_C2N     int32[nc][nn]
+ *  SCVS_X_ROWPTR   int64[n2+1]       SCVS_X_COL     int32[nnz_s2]
+ *  SCVS_X_KS       double[nnz_s2]    SCVS_X_M       double[nnz_s2]
+ *  SCVS_X_G        double[dim][nnz_c21]  (C21 = vertex-column prefix of S2 rows)
+ *  SCVS_X_MP       double[nv]        lumped pressure mass int N_v
+ *  SCVS_X_DIRNODES int32[ndir]       ascending DIRICHLET node ids
+ *  SCVS_X_DMASK    int32[n2]         0 free, 1 wall, 2 Dirichlet
+ *  SCVS_X_LOADS    double[ntraction][n2][dim]
+ *  SCVS_X_NODEXYZ  double[n2][dim]   node coordinates (vertices, then midside) */
+#define SCVS_X_EDGES 0
+#define SCVS_X_C2N 1
+#define SCVS_X_ROWPTR 2
+#define SCVS_X_COL 3
+#define SCVS_X_KS 4
+#define SCVS_X_M 5
+#define SCVS_X_G 6
+#define SCVS_X_MP 7
+#define SCVS_X_DIRNODES 8
+#define SCVS_X_DMASK 9
+#define SCVS_X_LOADS 10
+#define SCVS_X_NODEXYZ 11
+int scvs_mesh_export(scvs_mesh mesh, int which, void* out_host);
+
+/* ---- a4: multi-system complex SpMV (section 2.3, Eq. linear_sys_def) ----
+ * y_s = A(w_s) x_s for nsys systems sharing the mesh, with A the constrained
+ * system matrix (Dirichlet rows identity, Dirichlet columns dropped).
+ * omega: host double[nsys]; x, y: device c128[nsys][ndof]. */
+int scvs_spmv(scvs_mesh mesh, int64_t nsys, const double* omega, const void* x, void* y);
+
+/* ---- a3: right-hand sides (section 2.3, Eq. LS_construction, B_A) ----
+ * f_s = [sum_tau (-P_s,tau) n^tau - A_FC g_s ; g_s on Dirichlet rows ; -G^T g_s]
+ * traction: host c128[nsys][ntraction]; g: device c128[nsys][ndir][dim] (may be
+ * NULL when ndir == 0); f: device c128[nsys][ndof]. */
+int scvs_rhs(scvs_mesh mesh, int64_t nsys, const double* omega, const double* traction,
+             const void* g, void* f);
+
+/* ---- a5/a6: block-preconditioned restarted GMRES (section 2.3; section 3.1) ----
+ * Right-preconditioned GMRES(m) with classical Gram-Schmidt applied twice,
+ * complex Givens rotations and restarts on the true residual. Preconditioner:
+ * block upper-triangular [[A_v, G], [0, -S]] with A_v^-1 a Chebyshev-Jacobi
+ * polynomial of the real-shifted velocity block mu Ks + |w| rho M and
+ * S^-1 = mu Mp^-1 + j w rho L^-1 (L^-1 a Chebyshev-Jacobi polynomial of
+ * G^T diag(M)^-1 G on the free velocity rows). */
+typedef struct {
+  double rtol;        /* stop when ||f - A x||_2 <= rtol ||f||_2 (true residual) */
+  int32_t restart;    /* Krylov dimension m per cycle, 1..64 */
+  int32_t max_iters;  /* cap on Arnoldi steps per system */
+  int32_t cheb_vel;   /* Chebyshev degree of the velocity block, >= 1 */
+  int32_t cheb_pres;  /* Chebyshev degree of the pressure Laplacian, >= 1 */
+  double cheb_ratio;  /* assumed lambda_max / lambda_min of the Jacobi-scaled blocks */
+  int32_t max_batch;  /* systems solved together (0 = as many as fit) */
+  int32_t use_graph;  /* replay each restart cycle from a captured hipGraph */
+  int32_t verbose;    /* print per-cycle residuals to stderr */
+} scvs_solve_opts;
+
+/* Fill `o` with the defaults (rtol 1e-10, m 30, 20000 iterations, degrees 10/10,
+ * ratio 30, batch 0, graphs on). */
+void scvs_solve_opts_default(scvs_solve_opts* o);
+
+typedef struct {
+  int32_t status;       /* 0 converged, 1 iteration cap, 2 breakdown without convergence, 3 non-finite */
+  int32_t iterations;   /* Arnoldi steps */
+  int32_t restarts;     /* completed cycles */
+  double rel_residual;  /* final ||f - A x|| / ||f|| */
+} scvs_report;
+
+/* Solve nsys mode systems on one mesh (section 2.4, step 3).
+ *   omega     host double[nsys]            w_s (any sign; 0 = steady Stokes)
+ *   traction  host c128[nsys][ntraction]   normal pressure per traction tag
+ *   g         device c128[nsys][ndir][dim] Dirichlet data (NULL if ndir == 0)
+ *   x0        device c128[nsys][ndof] initial guesses, or NULL for zero (the
+ *             Dirichlet entries are overwritten with g)
+ *   u_out     device c128[nsys][n2][dim]; p_out device c128[nsys][nv]
+ *   rep       host scvs_report[nsys] (may be NULL)
+ * Non-convergence is reported per system, not as a call error. */
+int scvs_solve(scvs_mesh mesh, int64_t nsys, const double* omega, const double* traction,
+               const void* g, const void* x0, void* u_out, void* p_out,
+               const scvs_solve_opts* opts, scvs_report* rep);
+
+/* ---- a10: time synthesis (section 2.4, step 4, Eq. sol_reconstruct) ----
+ * out[n][i] = sum_k c_k Re(modes[k][i] exp(j omega_k t_n)), c_k = 1 if
+ * omega_k == 0 else 2 (real fields from the one-sided coefficients of
+ * Eq. SCVS_bc). omega: host double[nk] (>= 0); modes: device c128[nk][nvals];
+ * times: host double[nt]; out: device double[nt][nvals]. nk <= 256. */
+int scvs_synthesize(scvs_ctx ctx, int64_t nk, const double* omega, const void* modes,
+                    int64_t nvals, int64_t nt, const double* times, void* out);
+
+/* Test hook: runs one FP64 16x16x4 matrix-core instruction on A[i][k] = a[i*4+k],
+ * B[k][j] = b[k*16+j] (host double[64] each) and returns D = A B (host
+ * double[256], row-major) as laid out by the library's lane mapping. */
+int scvs_probe_mfma(scvs_ctx ctx, const double* a, const double* b, double* d);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SCVS_H */

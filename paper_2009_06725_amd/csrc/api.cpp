@@ -1,0 +1,328 @@
+// C ABI of the SCVS library: validation, object lifetime, error reporting.
+#include <cmath>
+#include <memory>
+
+#include "internal.hpp"
+
+using scvs::DBuf;
+using scvs::Error;
+using scvs::fail;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+template <class F>
+int guarded(F&& f) {
+  try {
+    g_last_error.clear();
+    f();
+    return SCVS_OK;
+  } catch (const Error& e) {
+    g_last_error = e.msg;
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    g_last_error = "host allocation failed";
+    return SCVS_E_NOMEM;
+  } catch (...) {
+    g_last_error = "unexpected internal error";
+    return SCVS_E_INVALID;
+  }
+}
+
+void use_device(scvs_ctx c) { SCVS_HIP(hipSetDevice(c->device)); }
+
+void require_ready(scvs_mesh m) {
+  SCVS_REQUIRE(m, SCVS_E_INVALID, "mesh is null");
+  SCVS_REQUIRE(m->bc_set, SCVS_E_STATE, "boundary conditions not set (call scvs_mesh_set_bc)");
+  SCVS_REQUIRE(m->assembled, SCVS_E_STATE, "matrices not assembled (call scvs_assemble)");
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* scvs_last_error(void) { return g_last_error.c_str(); }
+
+const char* scvs_version(void) { return "scvs-gfx950 0.1"; }
+
+int scvs_ctx_create(int device, void* stream, scvs_ctx* out) {
+  return guarded([&] {
+    SCVS_REQUIRE(out, SCVS_E_INVALID, "out is null");
+    int n = 0;
+    SCVS_HIP(hipGetDeviceCount(&n));
+    SCVS_REQUIRE(device >= 0 && device < n, SCVS_E_INVALID, "device index out of range");
+    SCVS_HIP(hipSetDevice(device));
+    auto* c = new scvs_ctx_s();
+    c->device = device;
+    c->stream = (hipStream_t)stream;
+    // The legacy null stream cannot be captured; graphs are recorded on a
+    // private stream (nothing executes during capture) and launched on c->stream.
+    if (hipStreamCreateWithFlags(&c->capture, hipStreamNonBlocking) != hipSuccess) {
+      (void)hipGetLastError();
+      delete c;
+      fail(SCVS_E_HIP, "hipStreamCreateWithFlags failed");
+    }
+    *out = c;
+  });
+}
+
+int scvs_ctx_destroy(scvs_ctx ctx) {
+  return guarded([&] {
+    if (ctx && ctx->capture) (void)hipStreamDestroy(ctx->capture);
+    delete ctx;
+  });
+}
+
+int scvs_mesh_create(scvs_ctx ctx, int dim, int64_t nv, const double* xyz, int64_t nc, const int32_t* cells,
+                     int64_t nf, const int32_t* bfaces, const int32_t* btags, scvs_mesh* out) {
+  return guarded([&] {
+    SCVS_REQUIRE(ctx && out, SCVS_E_INVALID, "ctx or out is null");
+    SCVS_REQUIRE(dim == 2 || dim == 3, SCVS_E_INVALID, "dim must be 2 or 3");
+    SCVS_REQUIRE(nv > 0 && nc > 0 && nf >= 0, SCVS_E_INVALID, "counts must be positive (nf >= 0)");
+    SCVS_REQUIRE(nv < INT32_MAX && nc < INT32_MAX, SCVS_E_INVALID, "counts exceed 32-bit indices");
+    SCVS_REQUIRE(xyz && cells, SCVS_E_INVALID, "xyz or cells is null");
+    SCVS_REQUIRE(nf == 0 || (bfaces && btags), SCVS_E_INVALID, "bfaces or btags is null");
+    const int nvl = dim + 1;
+    for (int64_t i = 0; i < nv * dim; ++i)
+      SCVS_REQUIRE(std::isfinite(xyz[i]), SCVS_E_MESH, "non-finite vertex coordinate");
+    for (int64_t c = 0; c < nc; ++c) {
+      const int32_t* v = cells + c * nvl;
+      for (int k = 0; k < nvl; ++k) {
+        SCVS_REQUIRE(v[k] >= 0 && v[k] < nv, SCVS_E_MESH, "cell vertex index out of range");
+        for (int l = 0; l < k; ++l) SCVS_REQUIRE(v[k] != v[l], SCVS_E_MESH, "cell repeats a vertex");
+      }
+      double J[3][3] = {};
+      for (int r = 0; r < dim; ++r)
+        for (int k = 0; k < dim; ++k) J[r][k] = xyz[(int64_t)v[k + 1] * dim + r] - xyz[(int64_t)v[0] * dim + r];
+      double det = dim == 2 ? J[0][0] * J[1][1] - J[0][1] * J[1][0]
+                            : J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
+                                  J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+                                  J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+      SCVS_REQUIRE(det != 0.0, SCVS_E_MESH, "degenerate cell (zero volume)");
+    }
+    for (int64_t i = 0; i < nf * dim; ++i)
+      SCVS_REQUIRE(bfaces[i] >= 0 && bfaces[i] < nv, SCVS_E_MESH, "facet vertex index out of range");
+    for (int64_t i = 0; i < nf; ++i) SCVS_REQUIRE(btags[i] >= 0, SCVS_E_INVALID, "negative facet tag");
+    use_device(ctx);
+    hipStream_t s = ctx->stream;
+    auto m = std::make_unique<scvs_mesh_s>();
+    m->ctx = ctx;
+    m->dim = dim;
+    m->nvl = nvl;
+    m->nn = nvl * (nvl + 1) / 2;
+    m->nv = nv;
+    m->nc = nc;
+    m->nf = nf;
+    m->xyz.upload(xyz, nv * dim, s);
+    m->cells.upload(cells, nc * nvl, s);
+    m->bfaces.upload(bfaces, nf * dim, s);
+    m->btags.upload(btags, nf, s);
+    scvs::mesh_build(m.get(), s);
+    SCVS_REQUIRE(m->n2 < INT32_MAX, SCVS_E_CAPACITY, "more than 2^31 quadratic nodes");
+    *out = m.release();
+  });
+}
+
+int scvs_mesh_destroy(scvs_mesh mesh) {
+  return guarded([&] {
+    if (mesh) {
+      use_device(mesh->ctx);
+      SCVS_HIP(hipStreamSynchronize(mesh->ctx->stream));
+    }
+    delete mesh;
+  });
+}
+
+int scvs_mesh_info(scvs_mesh m, scvs_mesh_info_t* info) {
+  return guarded([&] {
+    SCVS_REQUIRE(m && info, SCVS_E_INVALID, "mesh or info is null");
+    info->dim = m->dim;
+    info->nv = m->nv;
+    info->nc = m->nc;
+    info->nf = m->nf;
+    info->ne = m->ne;
+    info->n2 = m->n2;
+    info->ndof = m->dim * m->n2 + m->nv;
+    info->nnz_s2 = m->nnz;
+    info->nnz_c21 = m->nnz21;
+    info->ndir = m->ndir;
+    info->ntraction = (int32_t)m->traction_tags.size();
+    info->assembled = m->assembled ? 1 : 0;
+  });
+}
+
+int scvs_mesh_set_midside(scvs_mesh m, int64_t n, const int32_t* ev, const double* xyz) {
+  return guarded([&] {
+    SCVS_REQUIRE(m, SCVS_E_INVALID, "mesh is null");
+    SCVS_REQUIRE(n >= 0 && (n == 0 || (ev && xyz)), SCVS_E_INVALID, "bad midside arguments");
+    for (int64_t i = 0; i < 2 * n; ++i)
+      SCVS_REQUIRE(ev[i] >= 0 && ev[i] < m->nv, SCVS_E_INVALID, "midside edge vertex out of range");
+    for (int64_t i = 0; i < n * m->dim; ++i)
+      SCVS_REQUIRE(std::isfinite(xyz[i]), SCVS_E_INVALID, "non-finite midside coordinate");
+    if (n == 0) return;
+    use_device(m->ctx);
+    scvs::mesh_set_midside(m, n, ev, xyz, m->ctx->stream);
+    m->assembled = false;
+  });
+}
+
+int scvs_mesh_set_bc(scvs_mesh m, int n, const int32_t* tags, const int32_t* kinds) {
+  return guarded([&] {
+    SCVS_REQUIRE(m, SCVS_E_INVALID, "mesh is null");
+    SCVS_REQUIRE(n >= 0 && (n == 0 || (tags && kinds)), SCVS_E_INVALID, "bad boundary-condition arguments");
+    for (int i = 0; i < n; ++i) {
+      SCVS_REQUIRE(kinds[i] >= SCVS_BC_FREE && kinds[i] <= SCVS_BC_TRACTION, SCVS_E_INVALID,
+                   "unknown boundary-condition kind");
+      for (int k = 0; k < i; ++k) SCVS_REQUIRE(tags[k] != tags[i], SCVS_E_INVALID, "tag listed twice");
+    }
+    use_device(m->ctx);
+    m->bc_tags.assign(tags, tags + n);
+    m->bc_kinds.assign(kinds, kinds + n);
+    scvs::mesh_boundary(m, m->ctx->stream);
+    if (m->assembled) scvs::mesh_precond_setup(m, m->ctx->stream);
+  });
+}
+
+int scvs_assemble(scvs_mesh m, double rho, double mu) {
+  return guarded([&] {
+    SCVS_REQUIRE(m, SCVS_E_INVALID, "mesh is null");
+    SCVS_REQUIRE(rho > 0.0 && mu > 0.0 && std::isfinite(rho) && std::isfinite(mu), SCVS_E_INVALID,
+                 "rho and mu must be positive and finite");
+    use_device(m->ctx);
+    scvs::assemble_mesh(m, m->ctx->stream);
+    m->rho = rho;
+    m->mu = mu;
+    m->assembled = true;
+    if (m->bc_set) scvs::mesh_precond_setup(m, m->ctx->stream);
+  });
+}
+
+int scvs_mesh_export(scvs_mesh m, int which, void* out) {
+  return guarded([&] {
+    SCVS_REQUIRE(m && out, SCVS_E_INVALID, "mesh or out is null");
+    use_device(m->ctx);
+    hipStream_t s = m->ctx->stream;
+    const int D = m->dim;
+    auto need_asm = [&] { SCVS_REQUIRE(m->assembled, SCVS_E_STATE, "matrices not assembled"); };
+    auto need_bc = [&] { SCVS_REQUIRE(m->bc_set, SCVS_E_STATE, "boundary conditions not set"); };
+    switch (which) {
+      case SCVS_X_EDGES: scvs::download((int32_t*)out, m->edges.p, 2 * m->ne, s); break;
+      case SCVS_X_C2N: scvs::download((int32_t*)out, m->c2n.p, m->nc * m->nn, s); break;
+      case SCVS_X_ROWPTR: scvs::download((int64_t*)out, m->rowptr.p, m->n2 + 1, s); break;
+      case SCVS_X_COL: scvs::download((int32_t*)out, m->col.p, m->nnz, s); break;
+      case SCVS_X_KS: need_asm(); scvs::download((double*)out, m->Ks.p, m->nnz, s); break;
+      case SCVS_X_M: need_asm(); scvs::download((double*)out, m->M.p, m->nnz, s); break;
+      case SCVS_X_G: need_asm(); scvs::download((double*)out, m->G.p, D * m->nnz21, s); break;
+      case SCVS_X_MP: need_asm(); scvs::download((double*)out, m->Mp.p, m->nv, s); break;
+      case SCVS_X_DIRNODES: need_bc(); scvs::download((int32_t*)out, m->dirnodes.p, m->ndir, s); break;
+      case SCVS_X_DMASK: need_bc(); scvs::download((int32_t*)out, m->dmask.p, m->n2, s); break;
+      case SCVS_X_LOADS:
+        need_bc();
+        scvs::download((double*)out, m->loads.p, m->traction_tags.size() * m->n2 * D, s);
+        break;
+      case SCVS_X_NODEXYZ: {
+        std::vector<double> h(m->nv * D), e(m->ne * D);
+        scvs::download(h.data(), m->xyz.p, h.size(), s);
+        scvs::download(e.data(), m->exyz.p, e.size(), s);
+        memcpy(out, h.data(), h.size() * sizeof(double));
+        memcpy((double*)out + h.size(), e.data(), e.size() * sizeof(double));
+        break;
+      }
+      default: fail(SCVS_E_INVALID, "unknown export selector");
+    }
+  });
+}
+
+int scvs_spmv(scvs_mesh m, int64_t nsys, const double* omega, const void* x, void* y) {
+  return guarded([&] {
+    require_ready(m);
+    SCVS_REQUIRE(nsys > 0 && omega && x && y, SCVS_E_INVALID, "bad spmv arguments");
+    SCVS_REQUIRE(nsys <= 4096, SCVS_E_INVALID, "at most 4096 systems per call");
+    for (int64_t k = 0; k < nsys; ++k) SCVS_REQUIRE(std::isfinite(omega[k]), SCVS_E_INVALID, "non-finite omega");
+    use_device(m->ctx);
+    hipStream_t s = m->ctx->stream;
+    const int64_t ndof = m->dim * m->n2 + m->nv;
+    DBuf<double> om;
+    DBuf<int> act;
+    std::vector<int> a(nsys);
+    for (int64_t k = 0; k < nsys; ++k) a[k] = (int)k;
+    om.upload(omega, nsys, s);
+    act.upload(a.data(), nsys, s);
+    scvs::Batch b;
+    b.nact = (int)nsys;
+    b.act = act;
+    b.omega = om;
+    scvs::spmv_full(m, b, scvs::VArg{(double2*)x, ndof}, scvs::VArg{(double2*)y, ndof}, scvs::SPMV_APPLY, true,
+                    scvs::VArg{}, nullptr, s);
+    SCVS_HIP(hipStreamSynchronize(s));
+  });
+}
+
+int scvs_rhs(scvs_mesh m, int64_t nsys, const double* omega, const double* traction, const void* g, void* f) {
+  return guarded([&] {
+    require_ready(m);
+    SCVS_REQUIRE(nsys > 0 && nsys <= 4096 && omega && f, SCVS_E_INVALID, "bad rhs arguments");
+    SCVS_REQUIRE(m->traction_tags.empty() || traction, SCVS_E_INVALID, "traction is null");
+    SCVS_REQUIRE(m->ndir == 0 || g, SCVS_E_INVALID, "g is null but the mesh has Dirichlet nodes");
+    use_device(m->ctx);
+    scvs::rhs_systems(m, nsys, omega, traction, m->ndir ? g : nullptr, f);
+  });
+}
+
+void scvs_solve_opts_default(scvs_solve_opts* o) {
+  if (!o) return;
+  o->rtol = 1e-10;
+  o->restart = 30;
+  o->max_iters = 20000;
+  o->cheb_vel = 10;
+  o->cheb_pres = 10;
+  o->cheb_ratio = 30.0;
+  o->max_batch = 0;
+  o->use_graph = 1;
+  o->verbose = 0;
+}
+
+int scvs_solve(scvs_mesh m, int64_t nsys, const double* omega, const double* traction, const void* g,
+               const void* x0, void* u_out, void* p_out, const scvs_solve_opts* opts, scvs_report* rep) {
+  return guarded([&] {
+    require_ready(m);
+    SCVS_REQUIRE(nsys > 0 && omega && u_out && p_out, SCVS_E_INVALID, "bad solve arguments");
+    SCVS_REQUIRE(m->traction_tags.empty() || traction, SCVS_E_INVALID, "traction is null");
+    SCVS_REQUIRE(m->ndir == 0 || g, SCVS_E_INVALID, "g is null but the mesh has Dirichlet nodes");
+    scvs_solve_opts o;
+    if (opts)
+      o = *opts;
+    else
+      scvs_solve_opts_default(&o);
+    SCVS_REQUIRE(o.rtol > 0.0 && o.restart >= 1 && o.restart <= SCVS_MMAX && o.max_iters >= 1 &&
+                     o.cheb_vel >= 1 && o.cheb_pres >= 1 && o.cheb_ratio > 1.0 && o.max_batch >= 0,
+                 SCVS_E_INVALID, "bad solve options");
+    for (int64_t k = 0; k < nsys; ++k) SCVS_REQUIRE(std::isfinite(omega[k]), SCVS_E_INVALID, "non-finite omega");
+    use_device(m->ctx);
+    scvs::solve_systems(m, nsys, omega, traction, m->ndir ? g : nullptr, x0, u_out, p_out, &o, rep);
+  });
+}
+
+int scvs_synthesize(scvs_ctx ctx, int64_t nk, const double* omega, const void* modes, int64_t nvals, int64_t nt,
+                    const double* times, void* out) {
+  return guarded([&] {
+    SCVS_REQUIRE(ctx && omega && modes && out && (nt == 0 || times), SCVS_E_INVALID, "bad synthesis arguments");
+    SCVS_REQUIRE(nk >= 1 && nk <= 256 && nvals >= 0 && nt >= 0, SCVS_E_INVALID, "bad synthesis sizes");
+    for (int64_t k = 0; k < nk; ++k)
+      SCVS_REQUIRE(std::isfinite(omega[k]) && omega[k] >= 0.0, SCVS_E_INVALID, "omega must be finite and >= 0");
+    for (int64_t n = 0; n < nt; ++n) SCVS_REQUIRE(std::isfinite(times[n]), SCVS_E_INVALID, "non-finite time");
+    use_device(ctx);
+    scvs::synthesize(ctx->stream, nk, omega, (const double2*)modes, nvals, nt, times, (double*)out);
+  });
+}
+
+int scvs_probe_mfma(scvs_ctx ctx, const double* a, const double* b, double* d) {
+  return guarded([&] {
+    SCVS_REQUIRE(ctx && a && b && d, SCVS_E_INVALID, "null argument");
+    use_device(ctx);
+    scvs::probe_mfma(a, b, d, ctx->stream);
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,197 @@
+// Internal declarations of the SCVS HIP library (gfx950 only).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/scvs.h"
+
+namespace scvs {
+
+struct Error {
+  int code;
+  std::string msg;
+};
+
+[[noreturn]] void fail(int code, const std::string& msg);
+
+#define SCVS_HIP(call)                                                                \
+  do {                                                                                \
+    hipError_t e_ = (call);                                                           \
+    if (e_ != hipSuccess) {                                                           \
+      (void)hipGetLastError(); /* do not leave a sticky error for later calls */       \
+      ::scvs::fail(SCVS_E_HIP, std::string(#call) + " failed: " + hipGetErrorString(e_)); \
+    }                                                                                 \
+  } while (0)
+
+#define SCVS_REQUIRE(cond, code, msg) \
+  do {                                \
+    if (!(cond)) ::scvs::fail(code, msg); \
+  } while (0)
+
+// Owning device buffer.
+template <class T>
+struct DBuf {
+  T* p = nullptr;
+  size_t n = 0;
+  DBuf() = default;
+  DBuf(const DBuf&) = delete;
+  DBuf& operator=(const DBuf&) = delete;
+  ~DBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+  }
+  void alloc(size_t count) {
+    release();
+    if (count == 0) count = 1;
+    if (hipMalloc(&p, count * sizeof(T)) != hipSuccess) {
+      p = nullptr;
+      fail(SCVS_E_NOMEM, "device allocation of " + std::to_string(count * sizeof(T)) + " bytes failed");
+    }
+    n = count;
+  }
+  void zero(hipStream_t s) { SCVS_HIP(hipMemsetAsync(p, 0, n * sizeof(T), s)); }
+  void upload(const T* h, size_t count, hipStream_t s) {
+    alloc(count);
+    if (count) SCVS_HIP(hipMemcpyAsync(p, h, count * sizeof(T), hipMemcpyHostToDevice, s));
+  }
+  operator T*() const { return p; }
+};
+
+}  // namespace scvs
+
+struct scvs_ctx_s {
+  int device = 0;
+  hipStream_t stream = nullptr;   // caller's stream: all work runs here
+  hipStream_t capture = nullptr;  // private stream used only to record graphs
+};
+
+constexpr int SCVS_MMAX = 64;  // largest Krylov dimension per cycle
+
+struct scvs_mesh_s {
+  scvs_ctx ctx = nullptr;
+  int dim = 0, nvl = 0, nn = 0;  // dim, vertices per cell, quadratic nodes per cell
+  int64_t nv = 0, nc = 0, nf = 0, ne = 0, n2 = 0;
+  int64_t nnz = 0, nnz21 = 0, nnzv = 0;  // S2 slots, vertex-column slots, slots of vertex rows
+  scvs::DBuf<double> xyz, exyz;            // vertex and midside coordinates
+  scvs::DBuf<int32_t> cells, c2n, edges, bfaces, btags, fnodes;
+  scvs::DBuf<int64_t> vc_ptr;  // vertex -> cells (ascending)
+  scvs::DBuf<int32_t> vc;
+  scvs::DBuf<int64_t> vn_ptr;  // vertex a -> sorted neighbours b > a (edge list)
+  scvs::DBuf<int32_t> vn;
+  scvs::DBuf<int64_t> rowptr, rowptr21;
+  scvs::DBuf<int32_t> col, nvc;
+  scvs::DBuf<int64_t> nf_ptr;  // node -> boundary facets (ascending)
+  scvs::DBuf<int32_t> nf_list;
+  // assembled values
+  scvs::DBuf<double> Ks, M, G, Gt, Kd, Md, Mp;
+  // boundary conditions
+  std::vector<int32_t> bc_tags, bc_kinds, traction_tags;
+  scvs::DBuf<int32_t> dmask, dirnodes;
+  scvs::DBuf<double> loads, lpdinv;
+  int64_t ndir = 0;
+  double lp_lmax = 0.0;
+  bool bc_set = false, assembled = false;
+  double rho = 0.0, mu = 0.0;
+};
+
+namespace scvs {
+
+// ---- utilities (util.hip) ----
+// Exclusive scan of counts[n] into out[n+1]; returns the total (synchronizes).
+int64_t exclusive_scan(const int64_t* counts, int64_t* out, int64_t n, hipStream_t s);
+// Exclusive scan of int32 counts.
+int64_t exclusive_scan32(const int32_t* counts, int64_t* out, int64_t n, hipStream_t s);
+// Adjacency lists: for items i in [0,nitems) with nper target ids each, build
+// per-target sorted lists of item indices.
+void build_adjacency(const int32_t* ids, int64_t nitems, int nper, int64_t ntarget,
+                     DBuf<int64_t>& ptr, DBuf<int32_t>& list, hipStream_t s);
+// Launch-error check that is legal while the stream is being captured into a
+// graph (errors of captured launches surface at instantiation or launch).
+inline void launch_check(hipStream_t s) {
+  hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &st) == hipSuccess && st == hipStreamCaptureStatusActive) return;
+  SCVS_HIP(hipGetLastError());
+}
+template <class T>
+void download(T* host, const T* dev, size_t n, hipStream_t s) {
+  if (n) SCVS_HIP(hipMemcpyAsync(host, dev, n * sizeof(T), hipMemcpyDeviceToHost, s));
+  SCVS_HIP(hipStreamSynchronize(s));
+}
+
+// ---- mesh.hip ----
+void mesh_build(scvs_mesh m, hipStream_t s);
+void mesh_boundary(scvs_mesh m, hipStream_t s);
+void mesh_precond_setup(scvs_mesh m, hipStream_t s);
+
+// ---- assemble.hip ----
+void assemble_mesh(scvs_mesh m, hipStream_t s);
+void probe_mfma(const double* a, const double* b, double* d, hipStream_t s);
+// Grundmann-Moeller rule of degree 2s+1 on the n-simplex (barycentric points).
+void gm_rule(int n, int s, std::vector<double>& bary, std::vector<double>& w);
+
+void mesh_set_midside(scvs_mesh m, int64_t n, const int32_t* ev, const double* xyz, hipStream_t s);
+
+// ---- spmv.hip ----
+// A per-slot vector argument: the vector of slot k starts at p + k * st.
+struct VArg {
+  double2* p = nullptr;
+  int64_t st = 0;
+  __host__ __device__ double2* at(int k) const { return p + (int64_t)k * st; }
+};
+// The active systems of one launch.
+struct Batch {
+  int nact = 0;
+  const int* act = nullptr;       // device [nact] slot indices
+  const double* omega = nullptr;  // device [slots] w per slot
+  const double* lv = nullptr;     // device [slots] Chebyshev upper bound, velocity block
+  const double* insc = nullptr;   // device [slots * insc_st] input scale (nullptr = 1)
+  int insc_st = 0, insc_idx = 0;
+};
+enum { SPMV_APPLY = 0, SPMV_RESID = 1, SPMV_RHS = 2 };
+// y = A x (APPLY), y = f - A x (RESID), y = [-sum P n - A x ; x on Dirichlet rows ; -G^T x] (RHS).
+void spmv_full(scvs_mesh m, const Batch& b, VArg x, VArg y, int mode, bool maskcol, VArg f,
+               const double2* trac, hipStream_t s);
+// Block upper-triangular preconditioner z = P^-1 (insc * v); temps per slot.
+struct PrecondArgs {
+  int kv = 10, kp = 10;
+  double ratio = 30.0;
+  VArg vt;  // velocity temps: 3 * d*n2 per slot (r, d0, d1)
+  VArg pt;  // pressure temps: d*n2 + 4*nv per slot (t, r, d0, d1, x)
+};
+void precond_apply(scvs_mesh m, const Batch& b, const PrecondArgs& pa, VArg v, VArg z, hipStream_t s);
+// Gershgorin bound of diag^-1 (mu Ks + |w| rho M) on the free rows, per slot.
+void velocity_bounds(scvs_mesh m, const Batch& b, double* lv_out, hipStream_t s);
+
+// ---- krylov.hip ----
+int solve_systems(scvs_mesh m, int64_t nsys, const double* omega, const double* traction,
+                  const void* g, const void* x0, void* u_out, void* p_out,
+                  const scvs_solve_opts* o, scvs_report* rep);
+void rhs_systems(scvs_mesh m, int64_t nsys, const double* omega, const double* traction,
+                 const void* g, void* f);
+
+// ---- synth.hip ----
+void synthesize(hipStream_t s, int64_t nk, const double* omega, const double2* modes,
+                int64_t nvals, int64_t nt, const double* times, double* out);
+
+}  // namespace scvs
+
+// ---- device helpers ----
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+// conj(a) * b
+__device__ __forceinline__ double2 cmulc(double2 a, double2 b) {
+  return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+}
+__device__ __forceinline__ double2 cscale(double2 a, double s) { return make_double2(a.x * s, a.y * s); }

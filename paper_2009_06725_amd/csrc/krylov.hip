@@ -1,0 +1,680 @@
+// Block-preconditioned restarted GMRES for a batch of mode systems on one mesh.
+//
+// The paper solves each mode's system with GMRES (Saad & Schultz 1986),
+// adapted to complex arithmetic (section 2.3; section 3.1). Here, per system:
+// right preconditioning, Arnoldi by classical Gram-Schmidt with a second pass
+// only when the first one cancels more than 30% of the norm, complex Givens
+// rotations, restart on the recomputed true residual f - A x, and stop when
+// ||f - A x|| <= rtol ||f||.
+//
+// Storage is system-major: every system owns a slot with its basis V[m+1],
+// its solution, right-hand side and temporaries, so that finished systems
+// drop out of a batch without data movement. Dot products reduce within the
+// 64-lane wavefront by shuffles, then across the workgroup in LDS, then over
+// workgroups in a fixed order by the last workgroup to finish (no floating-
+// point atomics: results are bit-reproducible).
+#include <cmath>
+#include <map>
+
+#include "internal.hpp"
+
+namespace scvs {
+namespace {
+
+constexpr int MM = SCVS_MMAX;
+constexpr int PSTRIDE = MM + 2;  // partial sums per (slot, chunk)
+constexpr int RBS = 256;         // reduction block size
+constexpr int JB = 8;            // basis vectors per accumulation group
+
+struct SlotState {
+  double2 H[(MM + 1) * MM];  // column j at H + (MM+1) j
+  double2 sn[MM];
+  double cs[MM];
+  double2 gam[MM + 1];
+  double2 y[MM];
+  double2 h1[MM + 1], h2[MM + 1];
+  double hs[MM + 1];  // scale of stored basis vector i (V_i is kept unnormalized)
+  double nrm0, fnorm, tolabs, beta;
+  int jstop, skip2, nonfinite, lastJ;
+  unsigned int ticket[8];
+};
+
+struct KArgs {
+  const int* act;
+  SlotState* st;
+  double2* part;
+  int nch;
+  int64_t ndof, ld;
+  int m;
+  double2* V;  // slot k, vector i at V + (k*(m+1) + i)*ld
+  double* info;  // per slot: rel, lastJ, nonfinite, beta
+};
+
+__device__ __forceinline__ double2* vec(const KArgs& a, int slot, int i) {
+  return a.V + ((int64_t)slot * (a.m + 1) + i) * a.ld;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Reduce n complex per-thread values over the workgroup; thread k < n gets value k.
+template <int N>
+__device__ __forceinline__ double2 block_sum(const double2 (&acc)[N], double2* sh) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    const double rx = wave_sum(acc[k].x), ry = wave_sum(acc[k].y);
+    if (lane == 0) sh[wave * N + k] = make_double2(rx, ry);
+  }
+  __syncthreads();
+  double2 r = make_double2(0.0, 0.0);
+  if (threadIdx.x < N) {
+#pragma unroll
+    for (int w = 0; w < RBS / 64; ++w) r = cadd(r, sh[w * N + threadIdx.x]);
+  }
+  __syncthreads();
+  return r;
+}
+
+// Returns true in exactly one workgroup per slot: the last one to finish.
+__device__ __forceinline__ bool last_block(unsigned int* ticket, int nblocks) {
+  __shared__ bool is_last;
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned t = atomicAdd(ticket, 1u);
+    is_last = (t == (unsigned)nblocks - 1);
+    if (is_last) *ticket = 0;
+  }
+  __syncthreads();
+  if (is_last) __threadfence();
+  return is_last;
+}
+
+__device__ __forceinline__ void chunk_range(const KArgs& a, int64_t& b0, int64_t& b1) {
+  const int64_t len = (a.ndof + a.nch - 1) / a.nch;
+  b0 = (int64_t)blockIdx.x * len;
+  b1 = b0 + len < a.ndof ? b0 + len : a.ndof;
+}
+
+// Pass 1: h1_i = <hs_i V_i, w>, i <= j, and ||w||^2; pass 2: h2_i = <hs_i V_i, w>.
+template <int PASS>
+__global__ void __launch_bounds__(RBS) k_dots(KArgs a, int j) {
+  __shared__ double2 sh[(RBS / 64) * JB];
+  const int slot = a.act[blockIdx.y];
+  SlotState& st = a.st[slot];
+  if (st.jstop >= 0) return;
+  if (PASS == 2 && st.skip2) return;
+  int64_t b0, b1;
+  chunk_range(a, b0, b1);
+  const double2* __restrict__ w = vec(a, slot, j + 1);
+  double2* part = a.part + ((int64_t)slot * a.nch + blockIdx.x) * PSTRIDE;
+  for (int g0 = 0; g0 <= j; g0 += JB) {
+    double2 acc[JB];
+#pragma unroll
+    for (int k = 0; k < JB; ++k) acc[k] = make_double2(0.0, 0.0);
+    const double2* vb[JB];
+#pragma unroll
+    for (int k = 0; k < JB; ++k) vb[k] = vec(a, slot, (g0 + k <= j) ? g0 + k : 0);
+    for (int64_t n = b0 + threadIdx.x; n < b1; n += RBS) {
+      const double2 wv = w[n];
+#pragma unroll
+      for (int k = 0; k < JB; ++k)
+        if (g0 + k <= j) {
+          const double2 v = vb[k][n];
+          acc[k].x += v.x * wv.x + v.y * wv.y;
+          acc[k].y += v.x * wv.y - v.y * wv.x;
+        }
+    }
+    const double2 r = block_sum<JB>(acc, sh);
+    if (threadIdx.x < JB && g0 + threadIdx.x <= j) part[g0 + threadIdx.x] = r;
+  }
+  if (PASS == 1) {
+    double2 acc1[1] = {make_double2(0.0, 0.0)};
+    for (int64_t n = b0 + threadIdx.x; n < b1; n += RBS) {
+      const double2 wv = w[n];
+      acc1[0].x += wv.x * wv.x + wv.y * wv.y;
+    }
+    const double2 r = block_sum<1>(acc1, sh);
+    if (threadIdx.x == 0) part[MM + 1] = r;
+  }
+  if (!last_block(&st.ticket[PASS - 1], a.nch)) return;
+  const int nv = j + 1 + (PASS == 1 ? 1 : 0);
+  for (int i = threadIdx.x; i < nv; i += RBS) {
+    const int idx = (i <= j) ? i : MM + 1;
+    double2 s = make_double2(0.0, 0.0);
+    for (int c = 0; c < a.nch; ++c) s = cadd(s, a.part[((int64_t)slot * a.nch + c) * PSTRIDE + idx]);
+    if (i <= j) {
+      const double2 h = cscale(s, st.hs[i]);
+      if (PASS == 1)
+        st.h1[i] = h;
+      else
+        st.h2[i] = h;
+    } else {
+      st.nrm0 = sqrt(s.x);
+    }
+  }
+}
+
+// Column j of the Hessenberg matrix is final: apply the earlier rotations,
+// form the new one, update the residual estimate and decide whether the
+// system stops within this cycle.
+__device__ void finalize_column(SlotState& st, int j, double nrm, bool second) {
+  double2* col = st.H + (MM + 1) * j;
+  double hn2 = nrm * nrm;
+  for (int i = 0; i <= j; ++i) {
+    col[i] = second ? cadd(st.h1[i], st.h2[i]) : st.h1[i];
+    hn2 += col[i].x * col[i].x + col[i].y * col[i].y;
+  }
+  col[j + 1] = make_double2(nrm, 0.0);
+  if (!(isfinite(hn2))) {
+    st.nonfinite = 1;
+    st.jstop = j;
+    st.hs[j + 1] = 0.0;
+    return;
+  }
+  for (int i = 0; i < j; ++i) {
+    const double2 a = col[i], b = col[i + 1];
+    const double c = st.cs[i];
+    const double2 s = st.sn[i];
+    col[i] = cadd(cscale(a, c), cmul(s, b));
+    col[i + 1] = csub(cscale(b, c), cmulc(s, a));
+  }
+  const double2 a = col[j];
+  const double b = nrm;
+  const double aa = hypot(a.x, a.y);
+  const double r = hypot(aa, b);
+  double c;
+  double2 s, rr;
+  if (r == 0.0) {
+    c = 1.0;
+    s = make_double2(0.0, 0.0);
+    rr = make_double2(0.0, 0.0);
+  } else if (aa == 0.0) {
+    c = 0.0;
+    s = make_double2(1.0, 0.0);
+    rr = make_double2(b, 0.0);
+  } else {
+    c = aa / r;
+    const double2 ph = make_double2(a.x / aa, a.y / aa);
+    s = cscale(ph, b / r);
+    rr = cscale(ph, r);
+  }
+  st.cs[j] = c;
+  st.sn[j] = s;
+  col[j] = rr;
+  col[j + 1] = make_double2(0.0, 0.0);
+  const double2 g = st.gam[j];
+  st.gam[j] = cscale(g, c);
+  st.gam[j + 1] = make_double2(-(s.x * g.x + s.y * g.y), -(s.x * g.y - s.y * g.x));  // -conj(s) g
+  const double res = hypot(st.gam[j + 1].x, st.gam[j + 1].y);
+  const bool breakdown = nrm <= 1e-13 * sqrt(hn2);
+  if (res <= st.tolabs || breakdown) st.jstop = j + 1;
+  st.hs[j + 1] = (st.jstop < 0 && nrm > 0.0) ? 1.0 / nrm : 0.0;
+}
+
+// w -= sum_i (h_i hs_i) V_i and ||w||^2; the last workgroup finalizes.
+template <int PASS>
+__global__ void __launch_bounds__(RBS) k_update(KArgs a, int j) {
+  __shared__ double2 coef[MM + 1];
+  __shared__ double2 sh[RBS / 64];
+  const int slot = a.act[blockIdx.y];
+  SlotState& st = a.st[slot];
+  if (st.jstop >= 0) return;
+  if (PASS == 2 && st.skip2) return;
+  for (int i = threadIdx.x; i <= j; i += RBS) coef[i] = cscale(PASS == 1 ? st.h1[i] : st.h2[i], st.hs[i]);
+  __syncthreads();
+  int64_t b0, b1;
+  chunk_range(a, b0, b1);
+  double2* __restrict__ w = vec(a, slot, j + 1);
+  const double2* __restrict__ V0 = vec(a, slot, 0);
+  double2 acc[1] = {make_double2(0.0, 0.0)};
+  for (int64_t n = b0 + threadIdx.x; n < b1; n += RBS) {
+    double2 wv = w[n];
+    for (int i = 0; i <= j; ++i) {
+      const double2 v = V0[(int64_t)i * a.ld + n];
+      const double2 c = coef[i];
+      wv.x -= c.x * v.x - c.y * v.y;
+      wv.y -= c.x * v.y + c.y * v.x;
+    }
+    w[n] = wv;
+    acc[0].x += wv.x * wv.x + wv.y * wv.y;
+  }
+  const double2 r = block_sum<1>(acc, sh);
+  double2* part = a.part + ((int64_t)slot * a.nch + blockIdx.x) * PSTRIDE;
+  if (threadIdx.x == 0) part[MM + 1] = r;
+  if (!last_block(&st.ticket[2 + PASS - 1], a.nch)) return;
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int c = 0; c < a.nch; ++c) s += a.part[((int64_t)slot * a.nch + c) * PSTRIDE + MM + 1].x;
+    const double nrm = sqrt(s);
+    if (PASS == 1) {
+      if (nrm >= 0.7 * st.nrm0 || j + 1 > a.m) {
+        st.skip2 = 1;
+        finalize_column(st, j, nrm, false);
+      } else {
+        st.skip2 = 0;
+      }
+    } else {
+      finalize_column(st, j, nrm, true);
+    }
+  }
+}
+
+// Back substitution R y = gamma over the steps of this cycle; y_i *= hs_i.
+__global__ void k_trisolve(KArgs a, int nact) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nact) return;
+  const int slot = a.act[k];
+  SlotState& st = a.st[slot];
+  const int J = st.jstop >= 0 ? st.jstop : a.m;
+  for (int i = J - 1; i >= 0; --i) {
+    double2 s = st.gam[i];
+    for (int l = i + 1; l < J; ++l) s = csub(s, cmul(st.H[(MM + 1) * l + i], st.y[l]));
+    const double2 d = st.H[(MM + 1) * i + i];
+    const double dn = d.x * d.x + d.y * d.y;
+    st.y[i] = dn > 0.0 ? make_double2((s.x * d.x + s.y * d.y) / dn, (s.y * d.x - s.x * d.y) / dn)
+                       : make_double2(0.0, 0.0);
+  }
+  for (int i = 0; i < J; ++i) st.y[i] = cscale(st.y[i], st.hs[i]);
+  st.lastJ = J;
+}
+
+// t = sum_{i<J} y_i V_i
+__global__ void __launch_bounds__(RBS) k_combine(KArgs a, VArg t) {
+  __shared__ double2 y[MM];
+  const int slot = a.act[blockIdx.y];
+  const SlotState& st = a.st[slot];
+  const int J = st.lastJ;
+  for (int i = threadIdx.x; i < J; i += RBS) y[i] = st.y[i];
+  __syncthreads();
+  int64_t b0, b1;
+  chunk_range(a, b0, b1);
+  const double2* __restrict__ V0 = vec(a, slot, 0);
+  double2* __restrict__ ts = t.at(slot);
+  for (int64_t n = b0 + threadIdx.x; n < b1; n += RBS) {
+    double2 s = make_double2(0.0, 0.0);
+    for (int i = 0; i < J; ++i) {
+      const double2 v = V0[(int64_t)i * a.ld + n];
+      s.x += y[i].x * v.x - y[i].y * v.y;
+      s.y += y[i].x * v.y + y[i].y * v.x;
+    }
+    ts[n] = s;
+  }
+}
+
+__global__ void k_axpy(KArgs a, VArg x, VArg z) {
+  const int slot = a.act[blockIdx.y];
+  double2* xs = x.at(slot);
+  const double2* zs = z.at(slot);
+  for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < a.ndof; n += (int64_t)gridDim.x * blockDim.x)
+    xs[n] = cadd(xs[n], zs[n]);
+}
+
+// ||x||: KIND 0 sets fnorm/tolabs from the right-hand side; KIND 1 starts a
+// cycle from the residual stored in V_0.
+template <int KIND>
+__global__ void __launch_bounds__(RBS) k_norm(KArgs a, VArg x, double rtol) {
+  __shared__ double2 sh[RBS / 64];
+  const int slot = a.act[blockIdx.y];
+  SlotState& st = a.st[slot];
+  int64_t b0, b1;
+  chunk_range(a, b0, b1);
+  const double2* __restrict__ xs = KIND == 0 ? x.at(slot) : vec(a, slot, 0);
+  double2 acc[1] = {make_double2(0.0, 0.0)};
+  for (int64_t n = b0 + threadIdx.x; n < b1; n += RBS) {
+    const double2 v = xs[n];
+    acc[0].x += v.x * v.x + v.y * v.y;
+  }
+  const double2 r = block_sum<1>(acc, sh);
+  double2* part = a.part + ((int64_t)slot * a.nch + blockIdx.x) * PSTRIDE;
+  if (threadIdx.x == 0) part[MM + 1] = r;
+  if (!last_block(&st.ticket[4 + KIND], a.nch)) return;
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int c = 0; c < a.nch; ++c) s += a.part[((int64_t)slot * a.nch + c) * PSTRIDE + MM + 1].x;
+    const double nrm = sqrt(s);
+    if (KIND == 0) {
+      st.fnorm = nrm;
+      st.tolabs = rtol * nrm;
+      st.nonfinite = isfinite(nrm) ? 0 : 1;
+    } else {
+      st.beta = nrm;
+      st.gam[0] = make_double2(nrm, 0.0);
+      st.hs[0] = nrm > 0.0 ? 1.0 / nrm : 0.0;
+      st.jstop = (nrm <= st.tolabs || !isfinite(nrm)) ? 0 : -1;
+      st.skip2 = 1;
+      if (!isfinite(nrm)) st.nonfinite = 1;
+      double* inf = a.info + 4 * slot;
+      inf[0] = st.fnorm > 0.0 ? nrm / st.fnorm : nrm;
+      inf[1] = st.lastJ;
+      inf[2] = st.nonfinite;
+      inf[3] = nrm;
+    }
+  }
+}
+
+// x = x0 (or 0) with the Dirichlet data written into the constrained rows.
+template <int D>
+__global__ void k_init_x(VArg x, const double2* __restrict__ x0, int64_t x0st, const double2* __restrict__ g,
+                         int64_t gst, const int32_t* __restrict__ dmask, const int32_t* __restrict__ dirnodes,
+                         int64_t ndir, int64_t n2, int64_t ndof, const int* act, int first) {
+  const int slot = act[blockIdx.y];
+  const int sys = first + blockIdx.y;
+  double2* xs = x.at(slot);
+  // Entries of Dirichlet (kind 2) nodes are written only by the second loop
+  // when data is given, so the two loops never write the same element.
+  for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < ndof; n += (int64_t)gridDim.x * blockDim.x) {
+    double2 v = x0 ? x0[(int64_t)sys * x0st + n] : make_double2(0.0, 0.0);
+    const int32_t dm = n < D * n2 ? dmask[n / D] : 0;
+    if (dm == 2 && g) continue;
+    if (dm != 0) v = make_double2(0.0, 0.0);
+    xs[n] = v;
+  }
+  if (!g) return;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < ndir * D;
+       i += (int64_t)gridDim.x * blockDim.x)
+    xs[(int64_t)dirnodes[i / D] * D + (i % D)] = g[(int64_t)sys * gst + i];
+}
+
+__global__ void k_init_state(SlotState* st, const int* act, int nact) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nact) return;
+  SlotState& s = st[act[k]];
+  for (int i = 0; i < 8; ++i) s.ticket[i] = 0;
+  s.jstop = -1;
+  s.skip2 = 1;
+  s.nonfinite = 0;
+  s.lastJ = 0;
+  for (int i = 0; i <= MM; ++i) s.hs[i] = 0.0;
+}
+
+__global__ void k_copy_out(const VArg x, const int* act, int first, int nact, int64_t n2, int D, int64_t nv,
+                           double2* __restrict__ u, double2* __restrict__ p) {
+  const int k = blockIdx.y;
+  const int slot = act[k];
+  const int64_t sys = first + k;
+  const double2* xs = x.at(slot);
+  const int64_t DN = (int64_t)D * n2;
+  for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < DN + nv; n += (int64_t)gridDim.x * blockDim.x) {
+    if (n < DN)
+      u[sys * DN + n] = xs[n];
+    else
+      p[sys * nv + (n - DN)] = xs[n];
+  }
+}
+
+// Device workspace for a batch of `slots` systems.
+struct Pool {
+  int slots = 0, m = 0, nch = 0;
+  int64_t ld = 0, DN = 0, nv = 0;
+  DBuf<double2> V, W, vt, pt, part, trac;
+  DBuf<SlotState> st;
+  DBuf<double> omega, lv, info;
+  DBuf<int> act, act_all;
+  VArg Z() const { return VArg{W.p, 4 * ld}; }
+  VArg X() const { return VArg{W.p + ld, 4 * ld}; }
+  VArg F() const { return VArg{W.p + 2 * ld, 4 * ld}; }
+  VArg T() const { return VArg{W.p + 3 * ld, 4 * ld}; }
+};
+
+size_t slot_bytes(int64_t ld, int m, int64_t DN, int64_t nv, int nch) {
+  return sizeof(double2) * ((size_t)(m + 1 + 4) * ld + 3 * DN + DN + 4 * nv + (size_t)nch * PSTRIDE) +
+         sizeof(SlotState) + 64;
+}
+
+int choose_nch(int nact, int64_t ndof) {
+  int nch = (2048 + nact - 1) / nact;
+  const int64_t maxc = (ndof + RBS - 1) / RBS;
+  if (nch > maxc) nch = (int)maxc;
+  return nch < 1 ? 1 : nch;
+}
+
+KArgs kargs(Pool& P, int64_t ndof, int nch) {
+  KArgs a;
+  a.act = P.act;
+  a.st = P.st;
+  a.part = P.part;
+  a.nch = nch;
+  a.ndof = ndof;
+  a.ld = P.ld;
+  a.m = P.m;
+  a.V = P.V;
+  a.info = P.info;
+  return a;
+}
+
+// One restart cycle for the active slots, then the new true residual.
+void run_cycle(scvs_mesh m, Pool& P, const Batch& b, const PrecondArgs& pa, int64_t ndof, double rtol,
+               hipStream_t s) {
+  const int nact = b.nact;
+  const int nch = choose_nch(nact, ndof);
+  KArgs a = kargs(P, ndof, nch);
+  const dim3 gr((unsigned)nch, (unsigned)nact);
+  const VArg Vv{P.V.p, (int64_t)(P.m + 1) * P.ld};
+  for (int j = 0; j < P.m; ++j) {
+    Batch bj = b;
+    bj.insc = reinterpret_cast<const double*>(P.st.p) + offsetof(SlotState, hs) / sizeof(double) + j;
+    bj.insc_st = sizeof(SlotState) / sizeof(double);
+    bj.insc_idx = 0;
+    VArg vj{Vv.p + (int64_t)j * P.ld, Vv.st};
+    VArg vn{Vv.p + (int64_t)(j + 1) * P.ld, Vv.st};
+    precond_apply(m, bj, pa, vj, P.Z(), s);
+    spmv_full(m, b, P.Z(), vn, SPMV_APPLY, false, VArg{}, nullptr, s);
+    k_dots<1><<<gr, RBS, 0, s>>>(a, j);
+    k_update<1><<<gr, RBS, 0, s>>>(a, j);
+    k_dots<2><<<gr, RBS, 0, s>>>(a, j);
+    k_update<2><<<gr, RBS, 0, s>>>(a, j);
+    launch_check(s);
+  }
+  k_trisolve<<<(nact + 63) / 64, 64, 0, s>>>(a, nact);
+  k_combine<<<gr, RBS, 0, s>>>(a, P.T());
+  precond_apply(m, b, pa, P.T(), P.Z(), s);
+  k_axpy<<<dim3(256, nact), 256, 0, s>>>(a, P.X(), P.Z());
+  spmv_full(m, b, P.X(), Vv, SPMV_RESID, true, P.F(), nullptr, s);
+  k_norm<1><<<gr, RBS, 0, s>>>(a, VArg{}, rtol);
+  launch_check(s);
+}
+
+}  // namespace
+
+void rhs_systems(scvs_mesh m, int64_t nsys, const double* omega, const double* traction, const void* g, void* f) {
+  hipStream_t s = m->ctx->stream;
+  const int D = m->dim;
+  const int64_t ndof = D * m->n2 + m->nv;
+  const int ntr = (int)m->traction_tags.size();
+  DBuf<double> om;
+  DBuf<double2> tr, xg;
+  DBuf<int> act;
+  std::vector<int> acth(nsys);
+  for (int64_t k = 0; k < nsys; ++k) acth[k] = (int)k;
+  om.upload(omega, nsys, s);
+  tr.alloc((size_t)nsys * std::max(ntr, 1));
+  if (ntr) SCVS_HIP(hipMemcpyAsync(tr.p, traction, sizeof(double2) * nsys * ntr, hipMemcpyHostToDevice, s));
+  act.upload(acth.data(), nsys, s);
+  xg.alloc((size_t)nsys * ndof);
+  const dim3 gi(256, (unsigned)nsys);
+  if (D == 2)
+    k_init_x<2><<<gi, 256, 0, s>>>(VArg{xg.p, ndof}, nullptr, 0, (const double2*)g, m->ndir * D, m->dmask,
+                                   m->dirnodes, m->ndir, m->n2, ndof, act, 0);
+  else
+    k_init_x<3><<<gi, 256, 0, s>>>(VArg{xg.p, ndof}, nullptr, 0, (const double2*)g, m->ndir * D, m->dmask,
+                                   m->dirnodes, m->ndir, m->n2, ndof, act, 0);
+  launch_check(s);
+  Batch b;
+  b.nact = (int)nsys;
+  b.act = act;
+  b.omega = om;
+  spmv_full(m, b, VArg{xg.p, ndof}, VArg{(double2*)f, ndof}, SPMV_RHS, false, VArg{}, tr, s);
+  SCVS_HIP(hipStreamSynchronize(s));
+}
+
+int solve_systems(scvs_mesh m, int64_t nsys, const double* omega, const double* traction, const void* g,
+                  const void* x0, void* u_out, void* p_out, const scvs_solve_opts* o, scvs_report* rep) {
+  hipStream_t s = m->ctx->stream;
+  const int D = m->dim;
+  const int64_t ndof = D * m->n2 + m->nv;
+  const int64_t DN = D * m->n2;
+  const int ntr = (int)m->traction_tags.size();
+  const int mk = o->restart;
+  Pool P;
+  P.m = mk;
+  P.ld = (ndof + 63) / 64 * 64;
+  P.DN = DN;
+  P.nv = m->nv;
+  // batch size from free memory (keep 10% spare)
+  size_t fr = 0, tot = 0;
+  SCVS_HIP(hipMemGetInfo(&fr, &tot));
+  const int nch_max = choose_nch(1, ndof);
+  const size_t per = slot_bytes(P.ld, mk, DN, m->nv, nch_max);
+  int64_t fit = (int64_t)((double)fr * 0.9 / (double)per);
+  SCVS_REQUIRE(fit >= 1, SCVS_E_NOMEM, "not enough device memory for one system's Krylov workspace");
+  int B = (int)std::min<int64_t>(nsys, fit);
+  if (o->max_batch > 0) B = std::min(B, o->max_batch);
+  P.slots = B;
+  P.V.alloc((size_t)B * (mk + 1) * P.ld);
+  P.W.alloc((size_t)B * 4 * P.ld);
+  P.vt.alloc((size_t)B * 3 * DN);
+  P.pt.alloc((size_t)B * (DN + 4 * m->nv));
+  P.part.alloc((size_t)B * nch_max * PSTRIDE);
+  P.st.alloc(B);
+  P.omega.alloc(B);
+  P.lv.alloc(B);
+  P.info.alloc(4 * B);
+  P.act.alloc(B);
+  P.act_all.alloc(B);
+  P.trac.alloc((size_t)B * std::max(ntr, 1));
+  PrecondArgs pa;
+  pa.kv = o->cheb_vel;
+  pa.kp = o->cheb_pres;
+  pa.ratio = o->cheb_ratio;
+  pa.vt = VArg{P.vt.p, 3 * DN};
+  pa.pt = VArg{P.pt.p, DN + 4 * m->nv};
+  std::vector<int> all(B);
+  for (int k = 0; k < B; ++k) all[k] = k;
+  SCVS_HIP(hipMemcpyAsync(P.act_all.p, all.data(), sizeof(int) * B, hipMemcpyHostToDevice, s));
+  int rc = SCVS_OK;
+  for (int64_t first = 0; first < nsys; first += B) {
+    const int nb = (int)std::min<int64_t>(B, nsys - first);
+    SCVS_HIP(hipMemcpyAsync(P.omega.p, omega + first, sizeof(double) * nb, hipMemcpyHostToDevice, s));
+    if (ntr)
+      SCVS_HIP(hipMemcpyAsync(P.trac.p, traction + 2 * first * ntr, sizeof(double2) * nb * ntr,
+                              hipMemcpyHostToDevice, s));
+    SCVS_HIP(hipMemsetAsync(P.lv.p, 0, sizeof(double) * nb, s));
+    Batch b;
+    b.nact = nb;
+    b.act = P.act_all;
+    b.omega = P.omega;
+    b.lv = P.lv;
+    k_init_state<<<(nb + 63) / 64, 64, 0, s>>>(P.st, P.act_all, nb);
+    const int nch0 = choose_nch(nb, ndof);
+    KArgs a0 = kargs(P, ndof, nch0);
+    a0.act = P.act_all;
+    const dim3 g0((unsigned)nch0, (unsigned)nb);
+    // right-hand sides: F = RHS(x_g), then x = x0 with Dirichlet data
+    const dim3 gi(256, (unsigned)nb);
+    const double2* gp = (const double2*)g;
+    const double2* x0p = (const double2*)x0;
+    if (D == 2) {
+      k_init_x<2><<<gi, 256, 0, s>>>(P.T(), nullptr, 0, gp, m->ndir * D, m->dmask, m->dirnodes, m->ndir, m->n2,
+                                     ndof, P.act_all, (int)first);
+      k_init_x<2><<<gi, 256, 0, s>>>(P.X(), x0p, ndof, gp, m->ndir * D, m->dmask, m->dirnodes, m->ndir, m->n2,
+                                     ndof, P.act_all, (int)first);
+    } else {
+      k_init_x<3><<<gi, 256, 0, s>>>(P.T(), nullptr, 0, gp, m->ndir * D, m->dmask, m->dirnodes, m->ndir, m->n2,
+                                     ndof, P.act_all, (int)first);
+      k_init_x<3><<<gi, 256, 0, s>>>(P.X(), x0p, ndof, gp, m->ndir * D, m->dmask, m->dirnodes, m->ndir, m->n2,
+                                     ndof, P.act_all, (int)first);
+    }
+    launch_check(s);
+    spmv_full(m, b, P.T(), P.F(), SPMV_RHS, false, VArg{}, P.trac, s);
+    k_norm<0><<<g0, RBS, 0, s>>>(a0, P.F(), o->rtol);
+    velocity_bounds(m, b, P.lv, s);
+    spmv_full(m, b, P.X(), VArg{P.V.p, (int64_t)(mk + 1) * P.ld}, SPMV_RESID, true, P.F(), nullptr, s);
+    k_norm<1><<<g0, RBS, 0, s>>>(a0, VArg{}, o->rtol);
+    launch_check(s);
+    std::vector<double> info(4 * nb);
+    std::vector<int> iters(nb, 0), cycles(nb, 0), done(nb, 0);
+    std::map<int, std::pair<hipGraph_t, hipGraphExec_t>> graphs;
+    std::vector<int> act_prev;
+    for (;;) {
+      download(info.data(), P.info.p, 4 * nb, s);
+      std::vector<int> act;
+      for (int k = 0; k < nb; ++k) {
+        if (done[k]) continue;
+        if (cycles[k] > 0) iters[k] += (int)info[4 * k + 1];
+        const double rel = info[4 * k];
+        if (rel <= o->rtol || info[4 * k + 2] != 0.0 || !std::isfinite(rel) || iters[k] >= o->max_iters) {
+          done[k] = 1;
+          continue;
+        }
+        act.push_back(k);
+      }
+      if (o->verbose) {
+        fprintf(stderr, "[scvs] batch@%lld active %zu:", (long long)first, act.size());
+        for (int k = 0; k < nb && k < 24; ++k) fprintf(stderr, " %.2e", info[4 * k]);
+        fprintf(stderr, "\n");
+      }
+      if (act.empty()) break;
+      if (act != act_prev) {
+        SCVS_HIP(hipMemcpyAsync(P.act.p, act.data(), sizeof(int) * act.size(), hipMemcpyHostToDevice, s));
+        act_prev = act;
+      }
+      Batch bc = b;
+      bc.nact = (int)act.size();
+      bc.act = P.act;
+      const int na = bc.nact;
+      if (o->use_graph) {
+        auto it = graphs.find(na);
+        if (it == graphs.end()) {
+          hipGraph_t gph;
+          hipGraphExec_t ex;
+          hipStream_t cs = m->ctx->capture;
+          SCVS_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+          try {
+            run_cycle(m, P, bc, pa, ndof, o->rtol, cs);
+          } catch (...) {
+            hipGraph_t bad = nullptr;
+            (void)hipStreamEndCapture(cs, &bad);
+            if (bad) (void)hipGraphDestroy(bad);
+            (void)hipGetLastError();
+            throw;
+          }
+          SCVS_HIP(hipStreamEndCapture(cs, &gph));
+          SCVS_HIP(hipGraphInstantiate(&ex, gph, nullptr, nullptr, 0));
+          it = graphs.emplace(na, std::make_pair(gph, ex)).first;
+        }
+        SCVS_HIP(hipGraphLaunch(it->second.second, s));
+        SCVS_HIP(hipGetLastError());
+      } else {
+        run_cycle(m, P, bc, pa, ndof, o->rtol, s);
+      }
+      for (int k : act) cycles[k]++;
+    }
+    for (auto& kv : graphs) {
+      (void)hipGraphExecDestroy(kv.second.second);
+      (void)hipGraphDestroy(kv.second.first);
+    }
+    const dim3 gc(256, (unsigned)nb);
+    k_copy_out<<<gc, 256, 0, s>>>(P.X(), P.act_all, (int)first, nb, m->n2, D, m->nv, (double2*)u_out,
+                                  (double2*)p_out);
+    launch_check(s);
+    SCVS_HIP(hipStreamSynchronize(s));
+    if (rep) {
+      for (int k = 0; k < nb; ++k) {
+        scvs_report& r = rep[first + k];
+        const double rel = info[4 * k];
+        r.iterations = iters[k];
+        r.restarts = cycles[k];
+        r.rel_residual = rel;
+        r.status = (info[4 * k + 2] != 0.0 || !std::isfinite(rel)) ? 3 : (rel <= o->rtol ? 0 : 1);
+      }
+    }
+  }
+  return rc;
+}
+
+}  // namespace scvs

@@ -1,0 +1,262 @@
+"""ctypes binding of libscvs (the gfx950 HIP library declared in include/scvs.h).
+
+Argument marshalling only: every computation runs in the library's kernels.
+PyTorch provides device memory (complex128 / float64 / int tensors on a HIP
+device) and the stream the library launches on. If the built library is
+missing this module raises on import instead of falling back to anything.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libscvs.so")
+
+BC_FREE, BC_WALL, BC_DIRICHLET, BC_TRACTION = 0, 1, 2, 3
+X_EDGES, X_C2N, X_ROWPTR, X_COL, X_KS, X_M, X_G, X_MP, X_DIRNODES, X_DMASK, X_LOADS, X_NODEXYZ = range(12)
+
+EXPORTED = [
+    "scvs_last_error", "scvs_version", "scvs_ctx_create", "scvs_ctx_destroy", "scvs_mesh_create",
+    "scvs_mesh_destroy", "scvs_mesh_info", "scvs_mesh_set_midside", "scvs_mesh_set_bc", "scvs_assemble",
+    "scvs_mesh_export", "scvs_spmv", "scvs_rhs", "scvs_solve_opts_default", "scvs_solve",
+    "scvs_synthesize", "scvs_probe_mfma",
+]
+
+
+class ScvsError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"scvs error {code}: {msg}")
+        self.code = code
+
+
+class MeshInfo(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("nv", C.c_int64), ("nc", C.c_int64), ("nf", C.c_int64),
+                ("ne", C.c_int64), ("n2", C.c_int64), ("ndof", C.c_int64), ("nnz_s2", C.c_int64),
+                ("nnz_c21", C.c_int64), ("ndir", C.c_int64), ("ntraction", C.c_int32),
+                ("assembled", C.c_int32)]
+
+
+class SolveOpts(C.Structure):
+    _fields_ = [("rtol", C.c_double), ("restart", C.c_int32), ("max_iters", C.c_int32),
+                ("cheb_vel", C.c_int32), ("cheb_pres", C.c_int32), ("cheb_ratio", C.c_double),
+                ("max_batch", C.c_int32), ("use_graph", C.c_int32), ("verbose", C.c_int32)]
+
+
+class Report(C.Structure):
+    _fields_ = [("status", C.c_int32), ("iterations", C.c_int32), ("restarts", C.c_int32),
+                ("rel_residual", C.c_double)]
+
+
+_lib = None
+
+
+def lib() -> C.CDLL:
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built; run paper_2009_06725_amd/build.py")
+        L = C.CDLL(LIB_PATH)
+        vp, i64, i32, dp = C.c_void_p, C.c_int64, C.c_int32, C.POINTER(C.c_double)
+        L.scvs_last_error.restype = C.c_char_p
+        L.scvs_version.restype = C.c_char_p
+        L.scvs_ctx_create.argtypes = [C.c_int, vp, C.POINTER(vp)]
+        L.scvs_ctx_destroy.argtypes = [vp]
+        L.scvs_mesh_create.argtypes = [vp, C.c_int, i64, vp, i64, vp, i64, vp, vp, C.POINTER(vp)]
+        L.scvs_mesh_destroy.argtypes = [vp]
+        L.scvs_mesh_info.argtypes = [vp, C.POINTER(MeshInfo)]
+        L.scvs_mesh_set_midside.argtypes = [vp, i64, vp, vp]
+        L.scvs_mesh_set_bc.argtypes = [vp, C.c_int, vp, vp]
+        L.scvs_assemble.argtypes = [vp, C.c_double, C.c_double]
+        L.scvs_mesh_export.argtypes = [vp, C.c_int, vp]
+        L.scvs_spmv.argtypes = [vp, i64, vp, vp, vp]
+        L.scvs_rhs.argtypes = [vp, i64, vp, vp, vp, vp]
+        L.scvs_solve_opts_default.argtypes = [C.POINTER(SolveOpts)]
+        L.scvs_solve_opts_default.restype = None
+        L.scvs_solve.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, C.POINTER(SolveOpts), C.POINTER(Report)]
+        L.scvs_synthesize.argtypes = [vp, i64, vp, vp, i64, i64, vp, vp]
+        L.scvs_probe_mfma.argtypes = [vp, vp, vp, vp]
+        for name in EXPORTED:
+            if name not in ("scvs_last_error", "scvs_version", "scvs_solve_opts_default"):
+                getattr(L, name).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _check(code: int):
+    if code != 0:
+        raise ScvsError(code, lib().scvs_last_error().decode())
+
+
+def _host(a, dtype):
+    a = np.ascontiguousarray(a, dtype=dtype)
+    return a, a.ctypes.data_as(C.c_void_p)
+
+
+def _dev(t, dtype_name: str):
+    """Device pointer of a contiguous torch tensor of the expected dtype."""
+    import torch
+    assert isinstance(t, torch.Tensor) and t.is_cuda, "expected a device tensor"
+    assert t.is_contiguous(), "expected a contiguous tensor"
+    assert str(t.dtype) == dtype_name, f"expected {dtype_name}, got {t.dtype}"
+    return C.c_void_p(t.data_ptr())
+
+
+def default_opts(**kw) -> SolveOpts:
+    o = SolveOpts()
+    lib().scvs_solve_opts_default(C.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+class Context:
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        self.device = device
+        self.stream = stream
+        h = C.c_void_p()
+        _check(lib().scvs_ctx_create(device, C.c_void_p(stream.cuda_stream), C.byref(h)))
+        self.h = h
+
+    def close(self):
+        if self.h:
+            _check(lib().scvs_ctx_destroy(self.h))
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Mesh:
+    """A simplex mesh on the device with its quadratic numbering and patterns."""
+
+    def __init__(self, ctx: Context, dim: int, xyz, cells, bfaces, btags):
+        self.ctx = ctx
+        xyz, px = _host(xyz, np.float64)
+        cells, pc = _host(cells, np.int32)
+        bfaces, pf = _host(bfaces, np.int32)
+        btags, pt = _host(btags, np.int32)
+        h = C.c_void_p()
+        _check(lib().scvs_mesh_create(ctx.h, dim, xyz.shape[0], px, cells.shape[0], pc,
+                                      bfaces.shape[0], pf, pt, C.byref(h)))
+        self.h = h
+
+    @classmethod
+    def from_workload(cls, ctx: Context, mesh) -> "Mesh":
+        m = cls(ctx, mesh.dim, mesh.xyz, mesh.cells, mesh.bfaces, mesh.btags)
+        if mesh.curved_edges.shape[0]:
+            m.set_midside(mesh.curved_edges, mesh.curved_xyz)
+        return m
+
+    def close(self):
+        if getattr(self, "h", None):
+            _check(lib().scvs_mesh_destroy(self.h))
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def info(self) -> MeshInfo:
+        i = MeshInfo()
+        _check(lib().scvs_mesh_info(self.h, C.byref(i)))
+        return i
+
+    def set_midside(self, edge_vertices, xyz):
+        ev, pe = _host(edge_vertices, np.int32)
+        x, px = _host(xyz, np.float64)
+        _check(lib().scvs_mesh_set_midside(self.h, ev.shape[0], pe, px))
+
+    def set_bc(self, bc: dict):
+        tags, pt = _host(list(bc.keys()), np.int32)
+        kinds, pk = _host(list(bc.values()), np.int32)
+        _check(lib().scvs_mesh_set_bc(self.h, tags.size, pt, pk))
+
+    def assemble(self, rho: float, mu: float):
+        _check(lib().scvs_assemble(self.h, rho, mu))
+
+    def export(self, which: int) -> np.ndarray:
+        i = self.info
+        d = i.dim
+        nn = (d + 1) * (d + 2) // 2
+        spec = {X_EDGES: (np.int32, (i.ne, 2)), X_C2N: (np.int32, (i.nc, nn)),
+                X_ROWPTR: (np.int64, (i.n2 + 1,)), X_COL: (np.int32, (i.nnz_s2,)),
+                X_KS: (np.float64, (i.nnz_s2,)), X_M: (np.float64, (i.nnz_s2,)),
+                X_G: (np.float64, (d, i.nnz_c21)), X_MP: (np.float64, (i.nv,)),
+                X_DIRNODES: (np.int32, (i.ndir,)), X_DMASK: (np.int32, (i.n2,)),
+                X_LOADS: (np.float64, (i.ntraction, i.n2, d)), X_NODEXYZ: (np.float64, (i.n2, d))}
+        dt, shape = spec[which]
+        out = np.zeros(max(1, int(np.prod(shape))), dt)
+        _check(lib().scvs_mesh_export(self.h, which, out.ctypes.data_as(C.c_void_p)))
+        return out[: int(np.prod(shape))].reshape(shape)
+
+    def spmv(self, omega, x, y):
+        om, po = _host(omega, np.float64)
+        _check(lib().scvs_spmv(self.h, om.size, po, _dev(x, "torch.complex128"), _dev(y, "torch.complex128")))
+
+    def rhs(self, omega, traction, g, f):
+        om, po = _host(omega, np.float64)
+        tr, pt = _host(np.asarray(traction, np.complex128).view(np.float64), np.float64)
+        pg = _dev(g, "torch.complex128") if g is not None else None
+        _check(lib().scvs_rhs(self.h, om.size, po, pt, pg, _dev(f, "torch.complex128")))
+
+    def solve(self, omega, traction, g=None, x0=None, u=None, p=None, opts: SolveOpts | None = None):
+        """Solve all systems; returns (u [nsys,n2,d], p [nsys,nv], list of Report)."""
+        import torch
+        i = self.info
+        om, po = _host(omega, np.float64)
+        ns = om.size
+        tr = np.asarray(traction, np.complex128)
+        if i.ntraction and tr.size == ns * i.ntraction:
+            tr = tr.reshape(ns, i.ntraction)
+        tr, pt = _host(tr.view(np.float64), np.float64)
+        dev = torch.device("cuda", self.ctx.device)
+        if u is None:
+            u = torch.empty((ns, i.n2, i.dim), dtype=torch.complex128, device=dev)
+        if p is None:
+            p = torch.empty((ns, i.nv), dtype=torch.complex128, device=dev)
+        pg = _dev(g, "torch.complex128") if g is not None else None
+        px = _dev(x0, "torch.complex128") if x0 is not None else None
+        reps = (Report * ns)()
+        o = opts if opts is not None else default_opts()
+        _check(lib().scvs_solve(self.h, ns, po, pt, pg, px, _dev(u, "torch.complex128"),
+                                _dev(p, "torch.complex128"), C.byref(o), reps))
+        return u, p, list(reps)
+
+
+def synthesize(ctx: Context, omega, modes, times, out=None):
+    """Real time samples [nt, nvals] from complex modes [nk, nvals] (device)."""
+    import torch
+    om, po = _host(omega, np.float64)
+    tm, pt = _host(times, np.float64)
+    nk = om.size
+    nvals = modes.numel() // nk
+    if out is None:
+        out = torch.empty((tm.size, nvals), dtype=torch.float64, device=modes.device)
+    _check(lib().scvs_synthesize(ctx.h, nk, po, _dev(modes, "torch.complex128"), nvals, tm.size, pt,
+                                 _dev(out, "torch.float64")))
+    return out
+
+
+def probe_mfma(ctx: Context, a: np.ndarray, b: np.ndarray) -> np.ndarray:
+    a, pa = _host(a, np.float64)
+    b, pb = _host(b, np.float64)
+    d = np.zeros(256)
+    _check(lib().scvs_probe_mfma(ctx.h, pa, pb, d.ctypes.data_as(C.c_void_p)))
+    return d.reshape(16, 16)
+
+
+def version() -> str:
+    return lib().scvs_version().decode()

@@ -1,0 +1,207 @@
+"""GPU parity: the HIP library against the FP64 CPU oracle, through the C ABI.
+
+Integer work (numbering, patterns, Dirichlet sets) must match bit for bit;
+floating point within the stated tolerances. Sizes are small enough for the
+oracle's LU but span many workgroups and ragged tails."""
+import numpy as np
+import pytest
+
+from oracle.assemble import assemble, boundary_loads, bc_nodes
+from oracle.solve import case_setup, solve_modes, system_matrix, constrained_dofs, system_rhs, constrained_matrix
+from oracle.synth import synthesize as oracle_synth
+from workloads import cases
+
+from helpers import gpu_mesh, gpu_dirichlet, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2009_06725_amd import scvs
+    print("[gpu] context on", torch.cuda.get_device_name(0), flush=True)
+    return scvs.Context(0)
+
+
+CASES = {
+    "channel": lambda: cases.channel_case(),
+    "channel_fine": lambda: cases.channel_case(nx=49, ny=9, n_harm=3),
+    "pipe": lambda: cases.pipe_case(h=0.5, length=2.0, n_harm=4),
+    "pipe_straight": lambda: cases.pipe_case(h=0.6, length=1.5, n_harm=2, curved=False),
+}
+
+
+@pytest.fixture(scope="module", params=list(CASES))
+def setup(request, ctx):
+    print(f"[gpu] case {request.param}", flush=True)
+    c = CASES[request.param]()
+    asm, loads, wall, dirn, g = case_setup(c)
+    m = gpu_mesh(ctx, c)
+    return dict(name=request.param, case=c, asm=asm, loads=loads, wall=wall, dirn=dirn, g=g, m=m)
+
+
+def test_mfma_lane_layout(ctx):
+    from paper_2009_06725_amd import scvs
+    rng = np.random.default_rng(0)
+    a = rng.standard_normal((16, 4))
+    b = rng.standard_normal((4, 16))
+    d = scvs.probe_mfma(ctx, a.ravel(), b.ravel())
+    assert np.allclose(d, a @ b, rtol=1e-14, atol=1e-14)
+
+
+def test_numbering_and_pattern_bitexact(setup):
+    from paper_2009_06725_amd import scvs
+    asm, m = setup["asm"], setup["m"]
+    info = m.info
+    assert info.n2 == asm["n2"] and info.ne == asm["edges"].shape[0]
+    assert np.array_equal(m.export(scvs.X_EDGES), asm["edges"])
+    assert np.array_equal(m.export(scvs.X_C2N), asm["c2n"])
+    rp, col = asm["S2"]
+    assert np.array_equal(m.export(scvs.X_ROWPTR), rp)
+    assert np.array_equal(m.export(scvs.X_COL), col)
+    assert info.nnz_c21 == asm["C21"][1].size
+
+
+def test_boundary_sets_bitexact(setup):
+    from paper_2009_06725_amd import scvs
+    m, wall, dirn = setup["m"], setup["wall"], setup["dirn"]
+    assert np.array_equal(m.export(scvs.X_DIRNODES), dirn)
+    dm = m.export(scvs.X_DMASK)
+    ref = np.zeros_like(dm)
+    ref[dirn] = 2
+    ref[wall] = 1
+    assert np.array_equal(dm, ref)
+
+
+def test_assembly_values(setup):
+    from paper_2009_06725_amd import scvs
+    asm, m = setup["asm"], setup["m"]
+    for key, which in (("Ks", scvs.X_KS), ("M", scvs.X_M), ("G", scvs.X_G), ("Mp", scvs.X_MP)):
+        got, ref = m.export(which), asm[key]
+        scale = np.abs(ref).max()
+        assert np.abs(got - ref).max() <= 1e-13 * scale, key
+    assert np.abs(m.export(scvs.X_NODEXYZ) - asm["node_xyz"]).max() < 1e-15
+
+
+def test_traction_loads(setup):
+    from paper_2009_06725_amd import scvs
+    c, asm, m = setup["case"], setup["asm"], setup["m"]
+    ttags = sorted(t for t, k in c["bc"].items() if k == 3)
+    got = m.export(scvs.X_LOADS)
+    ref = setup["loads"]
+    assert got.shape == ref.shape
+    if ref.size:
+        assert np.abs(got - ref).max() <= 1e-14 * max(1.0, np.abs(ref).max())
+
+
+def _oracle_rhs_and_matrix(setup, s, omega):
+    c, asm = setup["case"], setup["asm"]
+    A = system_matrix(asm, omega, c["rho"], c["mu"])
+    cidx, cval = constrained_dofs(asm, setup["wall"], setup["dirn"], setup["g"][s])
+    f = system_rhs(asm, setup["loads"], c["traction"][s], cidx, cval, A)
+    return f, constrained_matrix(A, cidx)
+
+
+def test_rhs(setup):
+    c, m = setup["case"], setup["m"]
+    info = m.info
+    ns = len(c["omega"])
+    g = gpu_dirichlet(m, c, torch)
+    f = torch.zeros((ns, info.ndof), dtype=torch.complex128, device="cuda")
+    m.rhs(c["omega"], c["traction"], g, f)
+    fh = f.cpu().numpy()
+    for s in range(ns):
+        fr, _ = _oracle_rhs_and_matrix(setup, s, float(c["omega"][s]))
+        assert np.abs(fh[s] - fr).max() <= 1e-12 * np.abs(fr).max(), s
+
+
+def test_spmv_multisystem(setup):
+    c, m = setup["case"], setup["m"]
+    info = m.info
+    rng = np.random.default_rng(3)
+    om = np.array([0.0, 2 * np.pi, -7.5, 40.0, 1e-3, 3.0, 0.5])
+    x = rng.standard_normal((om.size, info.ndof)) + 1j * rng.standard_normal((om.size, info.ndof))
+    xd = torch.from_numpy(x).to("cuda")
+    yd = torch.zeros_like(xd)
+    m.spmv(om, xd, yd)
+    y = yd.cpu().numpy()
+    for s, w in enumerate(om):
+        _, Ac = _oracle_rhs_and_matrix(setup, 0, float(w))
+        ref = Ac @ x[s]
+        assert np.abs(y[s] - ref).max() <= 1e-13 * np.abs(ref).max(), s
+
+
+def test_solve_matches_lu(setup):
+    from paper_2009_06725_amd import scvs
+    c, asm, m = setup["case"], setup["asm"], setup["m"]
+    u_o, p_o, _, _ = solve_modes(asm, setup["loads"], setup["wall"], setup["dirn"], c["omega"], c["rho"],
+                                 c["mu"], c["traction"], setup["g"])
+    g = gpu_dirichlet(m, c, torch)
+    opts = scvs.default_opts(rtol=1e-13, max_iters=20000)
+    u, p, rep = m.solve(c["omega"], c["traction"], g, opts=opts)
+    u, p = u.cpu().numpy(), p.cpu().numpy()
+    print("[gpu]", setup["name"], "iterations", [r.iterations for r in rep],
+          "res", ["%.1e" % r.rel_residual for r in rep], flush=True)
+    for s in range(len(c["omega"])):
+        assert rep[s].status == 0, (s, rep[s].status, rep[s].rel_residual)
+        eu, ep = rel_l2(asm, u[s], u_o[s], p[s], p_o[s])
+        assert eu <= 1e-10 and ep <= 1e-10, (s, eu, ep)
+
+
+def test_solve_conjugation_symmetry(setup):
+    """Solving at -w with conjugate data gives the conjugate solution."""
+    from paper_2009_06725_amd import scvs
+    c, asm, m = setup["case"], setup["asm"], setup["m"]
+    w = float(c["omega"][1])
+    g = gpu_dirichlet(m, c, torch)
+    gg = None if g is None else torch.stack([g[1], torch.conj(g[1]).resolve_conj()])
+    tr = np.stack([c["traction"][1], np.conj(c["traction"][1])])
+    opts = scvs.default_opts(rtol=1e-13)
+    u, p, rep = m.solve(np.array([w, -w]), tr, gg, opts=opts)
+    u, p = u.cpu().numpy(), p.cpu().numpy()
+    eu, ep = rel_l2(asm, u[1], np.conj(u[0]), p[1], np.conj(p[0]))
+    assert eu <= 1e-10 and ep <= 1e-10
+
+
+def test_batch_equals_single(setup):
+    from paper_2009_06725_amd import scvs
+    c, asm, m = setup["case"], setup["asm"], setup["m"]
+    g = gpu_dirichlet(m, c, torch)
+    opts = scvs.default_opts(rtol=1e-12)
+    ub, pb, _ = m.solve(c["omega"], c["traction"], g, opts=opts)
+    opts1 = scvs.default_opts(rtol=1e-12, max_batch=1, use_graph=0)
+    u1, p1, _ = m.solve(c["omega"], c["traction"], g, opts=opts1)
+    for s in range(len(c["omega"])):
+        eu, ep = rel_l2(asm, ub[s].cpu().numpy(), u1[s].cpu().numpy(), pb[s].cpu().numpy(), p1[s].cpu().numpy())
+        assert eu <= 1e-9 and ep <= 1e-9
+
+
+def test_synthesis(ctx):
+    from paper_2009_06725_amd import scvs
+    rng = np.random.default_rng(9)
+    for nk, nv, nt in [(9, 1105 * 2, 33), (17, 5000, 7), (70, 333, 40), (1, 10, 1)]:
+        modes = rng.standard_normal((nk, nv)) + 1j * rng.standard_normal((nk, nv))
+        om = 2 * np.pi * np.arange(nk) / 1.3
+        t = np.sort(rng.uniform(0, 2.6, nt))
+        out = scvs.synthesize(ctx, om, torch.from_numpy(modes).to("cuda"), t).cpu().numpy()
+        ref = oracle_synth(modes, om, t)
+        assert np.abs(out - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+def test_validation_errors(ctx):
+    from paper_2009_06725_amd import scvs
+    c = cases.channel_case()
+    mesh = c["mesh"]
+    bad = mesh.cells.copy()
+    bad[3, 1] = mesh.nv + 5
+    with pytest.raises(scvs.ScvsError):
+        scvs.Mesh(ctx, 2, mesh.xyz, bad, mesh.bfaces, mesh.btags)
+    m = scvs.Mesh(ctx, 2, mesh.xyz, mesh.cells, mesh.bfaces, mesh.btags)
+    with pytest.raises(scvs.ScvsError):  # solve before assembly
+        m.solve(np.zeros(1), np.zeros((1, 1)))
+    with pytest.raises(scvs.ScvsError):
+        m.set_bc({1: 7})
