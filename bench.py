@@ -1,0 +1,207 @@
+"""Benchmark of the spectral Stokes hot path on one MI355X.
+
+Workload (N=1): straight pipe R=1, L=10 with ~200k curved quadratic tets
+(~0.88M complex unknowns per mode), Womersley flow-rate inlet with 16 seeded
+harmonics plus the mean: 17 mode systems per step.
+
+One step = assembly of the mode-independent matrices on the resident mesh
++ per-mode right-hand sides + batched block-preconditioned GMRES for all 17
+modes to the relative residual `--rtol` + time synthesis of velocity and
+pressure at 64 instants. During the timed steps every library kernel launch
+is bracketed by HIP events on the stream it runs on; the dominant kernel's
+algorithmic bytes per launch divided by its mean launch time gives the
+roofline entry. The CPU baseline times the oracle (sparse LU of one mode) on
+a short pipe segment of the same mesh size h and scales it to the full
+problem linearly in unknowns (optimistic for the CPU: LU fill grows faster).
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+from workloads import cases  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_pipe200k.json")
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--tets", type=int, default=200000)
+    ap.add_argument("--harmonics", type=int, default=16)
+    ap.add_argument("--rtol", type=float, default=1e-10)
+    ap.add_argument("--restart", type=int, default=60)
+    ap.add_argument("--cheb-vel", type=int, default=10)
+    ap.add_argument("--cheb-pres", type=int, default=20)
+    ap.add_argument("--ntimes", type=int, default=64)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--verbose", action="store_true")
+    return ap.parse_args()
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("spmv.hip", "krylov.hip"):
+        with open(os.path.join(ROOT, "paper_2009_06725_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def stored_traffic(kernel: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or
+    None when absent or taken on different kernel sources."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel") != kernel or t.get("source_hash") != kernel_source_hash():
+        return None
+    return t.get("bytes_per_launch")
+
+
+def cpu_baseline(h: float, full_ndof: int):
+    """The oracle (assembly + SuperLU) on one mode of a pipe segment with the
+    same mesh size h and length 0.3; mode-solves/s scaled by unknowns."""
+    from oracle.solve import case_setup, solve_modes
+    c = cases.pipe_case(h=h, length=0.3, n_harm=1)
+    t0 = time.perf_counter()
+    asm, loads, wall, dirn, g = case_setup(c)
+    _, _, res, _ = solve_modes(asm, loads, wall, dirn, c["omega"][1:2], c["rho"], c["mu"], c["traction"][1:2], g[1:2])
+    dt = time.perf_counter() - t0
+    ndof = 3 * asm["n2"] + asm["nv"]
+    return {"value": (1.0 / dt) * ndof / full_ndof, "unit": "mode-solves/s", "cores": 1, "kind": "oracle",
+            "sample": f"one mode (W=8pi) of a pipe segment L=0.3 with the same h ({c['mesh'].nc} tets, "
+                      f"{ndof} unknowns): assembly + SuperLU in {dt:.1f}s on one core; rate scaled by "
+                      f"{ndof}/{full_ndof} unknowns (linear, optimistic for LU)",
+            "sample_seconds": dt, "sample_rel_residual": float(res[0])}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; multi-GPU runs are not part of it",
+                          "n_gpus": args.gpus}), flush=True)
+        sys.exit(2)
+    import torch
+    from paper_2009_06725_amd import scvs
+
+    case = cases.pipe_case(n_tets=args.tets, n_harm=args.harmonics)
+    mesh = case["mesh"]
+    h = float(mesh.name.split("_h")[1].split("_")[0])
+    log(f"mesh {mesh.name}: {mesh.nc} tets, {mesh.nv} vertices")
+    ctx = scvs.Context(0)
+    t0 = time.perf_counter()
+    m = scvs.Mesh.from_workload(ctx, mesh)
+    m.set_bc(case["bc"])
+    m.assemble(case["rho"], case["mu"])
+    torch.cuda.synchronize()
+    t_ingest = time.perf_counter() - t0
+    info = m.info
+    ns = len(case["omega"])
+    nodes = m.export(scvs.X_DIRNODES)
+    xyz = m.export(scvs.X_NODEXYZ)[nodes]
+    g = np.zeros((ns, nodes.size, 3), np.complex128)
+    for s, w in enumerate(case["omega"]):
+        g[s] = case["inlet_amp"][s] * case["inlet"](xyz, float(w))
+    g = torch.from_numpy(g).to("cuda")
+    u = torch.empty((ns, info.n2, 3), dtype=torch.complex128, device="cuda")
+    p = torch.empty((ns, info.nv), dtype=torch.complex128, device="cuda")
+    times = np.arange(args.ntimes) * case["period"] / args.ntimes
+    ut = torch.empty((args.ntimes, info.n2 * 3), dtype=torch.float64, device="cuda")
+    pt = torch.empty((args.ntimes, info.nv), dtype=torch.float64, device="cuda")
+    opts = scvs.default_opts(rtol=args.rtol, restart=args.restart, cheb_vel=args.cheb_vel,
+                             cheb_pres=args.cheb_pres, verbose=1 if args.verbose else 0)
+    log(f"n2={info.n2} ndof={info.ndof} nnz_s2={info.nnz_s2} ingest+assembly {t_ingest:.2f}s")
+
+    def step():
+        m.assemble(case["rho"], case["mu"])
+        _, _, rep = m.solve(case["omega"], case["traction"], g, u=u, p=p, opts=opts)
+        scvs.synthesize(ctx, case["omega"], u, times, out=ut)
+        scvs.synthesize(ctx, case["omega"], p, times, out=pt)
+        return rep
+
+    for i in range(args.warmup):
+        t0 = time.perf_counter()
+        rep = step()
+        torch.cuda.synchronize()
+        log(f"warmup {i}: {time.perf_counter() - t0:.2f}s iterations {[r.iterations for r in rep]}")
+    ctx.profile(True)
+    ctx.profile_read()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reps = []
+    for i in range(args.steps):
+        reps.append(step())
+        torch.cuda.synchronize()
+        log(f"step {i} done at {time.perf_counter() - t0:.2f}s")
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    stats = ctx.profile_read()
+    ctx.profile(False)
+    rep = reps[-1]
+    iters = [r.iterations for r in rep]
+    conv = all(r.status == 0 for r in rep)
+
+    def roof(name):
+        n, ms, by = stats[name]
+        per = by / n
+        avg_s = ms / n / 1e3
+        gbs = per / avg_s / 1e9
+        tr = stored_traffic(name)
+        return {"kernel": name, "bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": gbs / HBM_PEAK_GBS, "traffic": tr, "bytes_per_launch": per,
+                "avg_launch_us": avg_s * 1e6, "launches": n,
+                "share_of_kernel_time": ms / sum(v[1] for v in stats.values())}
+
+    dominant = max(stats, key=lambda k: stats[k][1])
+    kernels = {k: {"launches": v[0], "ms": round(v[1], 3), "GB/s": round(v[2] / (v[1] / 1e3) / 1e9, 1) if v[1] else None}
+               for k, v in sorted(stats.items(), key=lambda kv: -kv[1][1])}
+    out = {
+        "metric": "mode-solves/s",
+        "value": ns * args.steps / dt,
+        "unit": "mode-solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1000.0 * dt / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c128",
+        "data": "synthetic",
+        "config": {"workload": f"pipe R=1 L=10, {mesh.nc} curved P2/P1 tets, {ns} modes (16 harmonics + mean)",
+                   "ndof": int(info.ndof), "modes": ns, "rtol": args.rtol, "restart": args.restart,
+                   "cheb_vel": args.cheb_vel, "cheb_pres": args.cheb_pres, "ntimes": args.ntimes},
+        "dof_modes_per_s": info.ndof * ns * args.steps / dt,
+        "roofline": roof(dominant),
+        "spmv_roofline": roof("k_full_apply"),
+        "converged": conv,
+        "iterations": iters,
+        "kernels": kernels,
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        out["cpu_baseline"] = cpu_baseline(h, int(info.ndof))
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

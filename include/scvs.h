@@ -182,7 +182,7 @@ typedef struct {
   int32_t verbose;    /* print per-cycle residuals to stderr */
 } scvs_solve_opts;
 
-/* Fill `o` with the defaults (rtol 1e-10, m 30, 20000 iterations, degrees 10/10,
+/* Fill `o` with the defaults (rtol 1e-10, m 60, 20000 iterations, degrees 10/20,
  * ratio 30, batch 0, graphs on). */
 void scvs_solve_opts_default(scvs_solve_opts* o);
 
@@ -213,6 +213,24 @@ int scvs_solve(scvs_mesh mesh, int64_t nsys, const double* omega, const double* 
  * times: host double[nt]; out: device double[nt][nvals]. nk <= 256. */
 int scvs_synthesize(scvs_ctx ctx, int64_t nk, const double* omega, const void* modes,
                     int64_t nvals, int64_t nt, const double* times, void* out);
+
+/* ---- measurement ----
+ * When profiling is on, solves run without graph replay and every kernel
+ * launch is bracketed by HIP events recorded on the context stream (the
+ * stream the kernels run on). Per kernel class the library accumulates the
+ * number of launches, the summed event time and the algorithmic bytes that
+ * class moves per launch by construction (matrix arrays read once, each
+ * vector element read or written once; formulas in the source of each
+ * launcher). scvs_profile_read copies up to `max` entries to `out` (host),
+ * sets *n, and clears the statistics. */
+typedef struct {
+  char name[40];
+  int64_t launches;
+  double total_ms;  /* summed launch durations */
+  double bytes;     /* summed algorithmic bytes */
+} scvs_kernel_stat;
+int scvs_profile_enable(scvs_ctx ctx, int on);
+int scvs_profile_read(scvs_ctx ctx, int max, scvs_kernel_stat* out, int* n);
 
 /* Test hook: runs one FP64 16x16x4 matrix-core instruction on A[i][k] = a[i*4+k],
  * B[k][j] = b[k*16+j] (host double[64] each) and returns D = A B (host

@@ -273,10 +273,10 @@ int scvs_rhs(scvs_mesh m, int64_t nsys, const double* omega, const double* tract
 void scvs_solve_opts_default(scvs_solve_opts* o) {
   if (!o) return;
   o->rtol = 1e-10;
-  o->restart = 30;
+  o->restart = 60;
   o->max_iters = 20000;
   o->cheb_vel = 10;
-  o->cheb_pres = 10;
+  o->cheb_pres = 20;
   o->cheb_ratio = 30.0;
   o->max_batch = 0;
   o->use_graph = 1;
@@ -314,6 +314,35 @@ int scvs_synthesize(scvs_ctx ctx, int64_t nk, const double* omega, const void* m
     for (int64_t n = 0; n < nt; ++n) SCVS_REQUIRE(std::isfinite(times[n]), SCVS_E_INVALID, "non-finite time");
     use_device(ctx);
     scvs::synthesize(ctx->stream, nk, omega, (const double2*)modes, nvals, nt, times, (double*)out);
+  });
+}
+
+int scvs_profile_enable(scvs_ctx ctx, int on) {
+  return guarded([&] {
+    SCVS_REQUIRE(ctx, SCVS_E_INVALID, "ctx is null");
+    use_device(ctx);
+    ctx->prof.resolve();
+    ctx->prof.on = on != 0;
+  });
+}
+
+int scvs_profile_read(scvs_ctx ctx, int max, scvs_kernel_stat* out, int* n) {
+  return guarded([&] {
+    SCVS_REQUIRE(ctx && n && max >= 0 && (max == 0 || out), SCVS_E_INVALID, "bad profile arguments");
+    use_device(ctx);
+    ctx->prof.resolve();
+    int k = 0;
+    for (auto& kv : ctx->prof.stats) {
+      if (k >= max) break;
+      scvs_kernel_stat& o = out[k++];
+      memset(o.name, 0, sizeof(o.name));
+      strncpy(o.name, kv.first.c_str(), sizeof(o.name) - 1);
+      o.launches = kv.second.launches;
+      o.total_ms = kv.second.ms;
+      o.bytes = kv.second.bytes;
+    }
+    *n = k;
+    ctx->prof.stats.clear();
   });
 }
 

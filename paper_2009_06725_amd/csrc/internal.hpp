@@ -68,10 +68,45 @@ struct DBuf {
 
 }  // namespace scvs
 
+namespace scvs {
+// Event-based per-kernel timing on the launching stream (see scvs_profile_*).
+struct Profiler {
+  struct Stat {
+    int64_t launches = 0;
+    double ms = 0.0, bytes = 0.0;
+  };
+  struct Pending {
+    std::string name;
+    hipEvent_t a, b;
+    double bytes;
+  };
+  bool on = false;
+  std::vector<hipEvent_t> pool;
+  size_t used = 0;
+  std::vector<Pending> pending;
+  std::vector<std::pair<std::string, Stat>> stats;
+  hipEvent_t get();
+  void resolve();  // synchronizes, folds pending pairs into stats
+  ~Profiler();
+};
+// Brackets one launch with events when profiling is on.
+class ProfScope {
+ public:
+  ProfScope(Profiler* p, hipStream_t s, const char* name, double bytes);
+  ~ProfScope();
+
+ private:
+  Profiler* p_;
+  hipStream_t s_;
+  size_t idx_ = (size_t)-1;
+};
+}  // namespace scvs
+
 struct scvs_ctx_s {
   int device = 0;
   hipStream_t stream = nullptr;   // caller's stream: all work runs here
   hipStream_t capture = nullptr;  // private stream used only to record graphs
+  scvs::Profiler prof;
 };
 
 constexpr int SCVS_MMAX = 64;  // largest Krylov dimension per cycle
@@ -97,6 +132,11 @@ struct scvs_mesh_s {
   std::vector<int32_t> bc_tags, bc_kinds, traction_tags;
   scvs::DBuf<int32_t> dmask, dirnodes;
   scvs::DBuf<double> loads, lpdinv;
+  // pressure Laplacian G_F^T diag(M)^-1 G_F (vertex rows) for the Schur block
+  scvs::DBuf<int64_t> lp_ptr;
+  scvs::DBuf<int32_t> lp_col;
+  scvs::DBuf<double> lp_val;
+  int64_t nnzl = 0;
   int64_t ndir = 0;
   double lp_lmax = 0.0;
   bool bc_set = false, assembled = false;
@@ -114,6 +154,10 @@ int64_t exclusive_scan32(const int32_t* counts, int64_t* out, int64_t n, hipStre
 // per-target sorted lists of item indices.
 void build_adjacency(const int32_t* ids, int64_t nitems, int nper, int64_t ntarget,
                      DBuf<int64_t>& ptr, DBuf<int32_t>& list, hipStream_t s);
+inline bool capturing(hipStream_t s) {
+  hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+  return hipStreamIsCapturing(s, &st) == hipSuccess && st == hipStreamCaptureStatusActive;
+}
 // Launch-error check that is legal while the stream is being captured into a
 // graph (errors of captured launches surface at instantiation or launch).
 inline void launch_check(hipStream_t s) {
@@ -164,8 +208,8 @@ void spmv_full(scvs_mesh m, const Batch& b, VArg x, VArg y, int mode, bool maskc
 struct PrecondArgs {
   int kv = 10, kp = 10;
   double ratio = 30.0;
-  VArg vt;  // velocity temps: 3 * d*n2 per slot (r, d0, d1)
-  VArg pt;  // pressure temps: d*n2 + 4*nv per slot (t, r, d0, d1, x)
+  VArg vt;  // velocity temps: 4 * d*n2 per slot (b, three rotating iterates)
+  VArg pt;  // pressure temps: 4*nv per slot (r, d0, d1, x)
 };
 void precond_apply(scvs_mesh m, const Batch& b, const PrecondArgs& pa, VArg v, VArg z, hipStream_t s);
 // Gershgorin bound of diag^-1 (mu Ks + |w| rho M) on the free rows, per slot.

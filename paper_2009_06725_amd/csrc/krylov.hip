@@ -422,7 +422,7 @@ struct Pool {
 };
 
 size_t slot_bytes(int64_t ld, int m, int64_t DN, int64_t nv, int nch) {
-  return sizeof(double2) * ((size_t)(m + 1 + 4) * ld + 3 * DN + DN + 4 * nv + (size_t)nch * PSTRIDE) +
+  return sizeof(double2) * ((size_t)(m + 1 + 4) * ld + 4 * DN + 4 * nv + (size_t)nch * PSTRIDE) +
          sizeof(SlotState) + 64;
 }
 
@@ -455,6 +455,8 @@ void run_cycle(scvs_mesh m, Pool& P, const Batch& b, const PrecondArgs& pa, int6
   KArgs a = kargs(P, ndof, nch);
   const dim3 gr((unsigned)nch, (unsigned)nact);
   const VArg Vv{P.V.p, (int64_t)(P.m + 1) * P.ld};
+  Profiler* prof = &m->ctx->prof;
+  const double vec = (double)ndof * 16.0 * nact;  // one vector of every active system
   for (int j = 0; j < P.m; ++j) {
     Batch bj = b;
     bj.insc = reinterpret_cast<const double*>(P.st.p) + offsetof(SlotState, hs) / sizeof(double) + j;
@@ -464,18 +466,42 @@ void run_cycle(scvs_mesh m, Pool& P, const Batch& b, const PrecondArgs& pa, int6
     VArg vn{Vv.p + (int64_t)(j + 1) * P.ld, Vv.st};
     precond_apply(m, bj, pa, vj, P.Z(), s);
     spmv_full(m, b, P.Z(), vn, SPMV_APPLY, false, VArg{}, nullptr, s);
-    k_dots<1><<<gr, RBS, 0, s>>>(a, j);
-    k_update<1><<<gr, RBS, 0, s>>>(a, j);
-    k_dots<2><<<gr, RBS, 0, s>>>(a, j);
-    k_update<2><<<gr, RBS, 0, s>>>(a, j);
+    {
+      ProfScope ps(prof, s, "k_dots1", vec * (j + 2));  // V_0..V_j and w once
+      k_dots<1><<<gr, RBS, 0, s>>>(a, j);
+    }
+    {
+      ProfScope ps(prof, s, "k_update1", vec * (j + 3));  // V_0..V_j and w read, w written
+      k_update<1><<<gr, RBS, 0, s>>>(a, j);
+    }
+    {
+      ProfScope ps(prof, s, "k_dots2", vec * (j + 2));
+      k_dots<2><<<gr, RBS, 0, s>>>(a, j);
+    }
+    {
+      ProfScope ps(prof, s, "k_update2", vec * (j + 3));
+      k_update<2><<<gr, RBS, 0, s>>>(a, j);
+    }
     launch_check(s);
   }
-  k_trisolve<<<(nact + 63) / 64, 64, 0, s>>>(a, nact);
-  k_combine<<<gr, RBS, 0, s>>>(a, P.T());
+  {
+    ProfScope ps(prof, s, "k_trisolve", 0.0);
+    k_trisolve<<<(nact + 63) / 64, 64, 0, s>>>(a, nact);
+  }
+  {
+    ProfScope ps(prof, s, "k_combine", vec * (P.m + 1));
+    k_combine<<<gr, RBS, 0, s>>>(a, P.T());
+  }
   precond_apply(m, b, pa, P.T(), P.Z(), s);
-  k_axpy<<<dim3(256, nact), 256, 0, s>>>(a, P.X(), P.Z());
+  {
+    ProfScope ps(prof, s, "k_axpy", vec * 3);
+    k_axpy<<<dim3(256, nact), 256, 0, s>>>(a, P.X(), P.Z());
+  }
   spmv_full(m, b, P.X(), Vv, SPMV_RESID, true, P.F(), nullptr, s);
-  k_norm<1><<<gr, RBS, 0, s>>>(a, VArg{}, rtol);
+  {
+    ProfScope ps(prof, s, "k_norm", vec);
+    k_norm<1><<<gr, RBS, 0, s>>>(a, VArg{}, rtol);
+  }
   launch_check(s);
 }
 
@@ -537,8 +563,8 @@ int solve_systems(scvs_mesh m, int64_t nsys, const double* omega, const double* 
   P.slots = B;
   P.V.alloc((size_t)B * (mk + 1) * P.ld);
   P.W.alloc((size_t)B * 4 * P.ld);
-  P.vt.alloc((size_t)B * 3 * DN);
-  P.pt.alloc((size_t)B * (DN + 4 * m->nv));
+  P.vt.alloc((size_t)B * 4 * DN);
+  P.pt.alloc((size_t)B * 4 * m->nv);
   P.part.alloc((size_t)B * nch_max * PSTRIDE);
   P.st.alloc(B);
   P.omega.alloc(B);
@@ -551,8 +577,8 @@ int solve_systems(scvs_mesh m, int64_t nsys, const double* omega, const double* 
   pa.kv = o->cheb_vel;
   pa.kp = o->cheb_pres;
   pa.ratio = o->cheb_ratio;
-  pa.vt = VArg{P.vt.p, 3 * DN};
-  pa.pt = VArg{P.pt.p, DN + 4 * m->nv};
+  pa.vt = VArg{P.vt.p, 4 * DN};
+  pa.pt = VArg{P.pt.p, 4 * m->nv};
   std::vector<int> all(B);
   for (int k = 0; k < B; ++k) all[k] = k;
   SCVS_HIP(hipMemcpyAsync(P.act_all.p, all.data(), sizeof(int) * B, hipMemcpyHostToDevice, s));
@@ -602,6 +628,7 @@ int solve_systems(scvs_mesh m, int64_t nsys, const double* omega, const double* 
     std::vector<int> act_prev;
     for (;;) {
       download(info.data(), P.info.p, 4 * nb, s);
+      m->ctx->prof.resolve();
       std::vector<int> act;
       for (int k = 0; k < nb; ++k) {
         if (done[k]) continue;
@@ -627,7 +654,7 @@ int solve_systems(scvs_mesh m, int64_t nsys, const double* omega, const double* 
       bc.nact = (int)act.size();
       bc.act = P.act;
       const int na = bc.nact;
-      if (o->use_graph) {
+      if (o->use_graph && !m->ctx->prof.on) {
         auto it = graphs.find(na);
         if (it == graphs.end()) {
           hipGraph_t gph;

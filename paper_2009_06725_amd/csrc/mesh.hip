@@ -359,40 +359,93 @@ __global__ void k_loads_gather(const int64_t* __restrict__ nf_ptr, const int32_t
   for (int k = 0; k < D; ++k) loads[A * D + k] = acc[k];
 }
 
-// Pressure-Laplacian data for the Schur block of the preconditioner:
-// L = G_F^T diag(M)^-1 G_F on the free velocity rows. gs[A][c] = sum |G^c_Av|.
-template <int D>
-__global__ void k_gabs(const int64_t* __restrict__ rowptr21, const double* __restrict__ G, int64_t nnz21,
-                       const int32_t* __restrict__ dmask, int64_t n2, double* __restrict__ gs) {
-  int64_t A = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (A >= n2) return;
-#pragma unroll
-  for (int c = 0; c < D; ++c) {
-    double s = 0.0;
-    if (dmask[A] == 0)
-      for (int64_t j = rowptr21[A]; j < rowptr21[A + 1]; ++j) s += fabs(G[c * nnz21 + j]);
-    gs[A * D + c] = s;
+// Pressure Laplacian of the Schur block, L = G_F^T diag(M)^-1 G_F with G_F the
+// rows of G at free velocity nodes. Row v couples the vertices u of the C21 rows
+// of the free nodes A in the S2 row of v (a distance-2 vertex pattern).
+__global__ void __launch_bounds__(ROW_BS) k_lp_rows(const int64_t* __restrict__ rowptr,
+                                                    const int32_t* __restrict__ col,
+                                                    const int32_t* __restrict__ nvcnt,
+                                                    const int32_t* __restrict__ dmask, int32_t* __restrict__ cnt,
+                                                    const int64_t* __restrict__ lp_ptr,
+                                                    int32_t* __restrict__ lp_col, int* err) {
+  __shared__ int32_t sh[ROW_CAP];
+  __shared__ int scan[2 * ROW_BS];
+  __shared__ int ncand;
+  const int64_t v = blockIdx.x;
+  if (threadIdx.x == 0) ncand = 0;
+  __syncthreads();
+  for (int64_t j = rowptr[v] + threadIdx.x; j < rowptr[v + 1]; j += ROW_BS) {
+    const int32_t A = col[j];
+    if (dmask[A] != 0) continue;
+    const int nA = nvcnt[A];
+    const int pos = atomicAdd(&ncand, nA);
+    for (int q = 0; q < nA; ++q)
+      if (pos + q < ROW_CAP) sh[pos + q] = col[rowptr[A] + q];
   }
+  __syncthreads();
+  const int n = ncand;
+  if (n > ROW_CAP) {
+    if (threadIdx.x == 0) atomicOr(err, 1);
+    return;
+  }
+  int low;
+  const int u = wave_sort_unique(sh, n, lp_col ? lp_col + lp_ptr[v] : nullptr, INT_MAX, &low, scan);
+  if (!lp_col && threadIdx.x == 0) cnt[v] = u;
 }
 
+// L[v][u] = sum over free A in the S2 row of v (ascending) of sum_c G^c_Av G^c_Au / M_AA.
 template <int D>
-__global__ void k_lpdiag(const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
-                         const double* __restrict__ Gt, int64_t nnzv, const double* __restrict__ Md,
-                         const int32_t* __restrict__ dmask, const double* __restrict__ gs, int64_t nv,
-                         double* __restrict__ lpdinv, double* __restrict__ ratio) {
-  int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void k_lp_vals(const int64_t* __restrict__ lp_ptr, const int32_t* __restrict__ lp_col, int64_t nnzl,
+                          int64_t nv, const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+                          const int32_t* __restrict__ nvcnt, const int64_t* __restrict__ rowptr21,
+                          const double* __restrict__ G, const double* __restrict__ Gt, int64_t nnz21, int64_t nnzv,
+                          const double* __restrict__ Md, const int32_t* __restrict__ dmask,
+                          double* __restrict__ lp_val) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nnzl) return;
+  int64_t lo = 0, hi = nv;
+  while (hi - lo > 1) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (lp_ptr[mid] <= k)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  const int64_t v = lo;
+  const int32_t u = lp_col[k];
+  double sum = 0.0;
+  for (int64_t j = rowptr[v]; j < rowptr[v + 1]; ++j) {
+    const int32_t A = col[j];
+    if (dmask[A] != 0) continue;
+    int64_t a = rowptr[A], b = a + nvcnt[A];
+    const int64_t base = a;
+    while (a < b) {
+      const int64_t mid = (a + b) >> 1;
+      if (col[mid] < u)
+        a = mid + 1;
+      else
+        b = mid;
+    }
+    if (a < base + nvcnt[A] && col[a] == u) {
+      const int64_t q = a - base;
+      double s = 0.0;
+#pragma unroll
+      for (int c = 0; c < D; ++c) s += Gt[c * nnzv + j] * G[c * nnz21 + rowptr21[A] + q];
+      sum += s / Md[A];
+    }
+  }
+  lp_val[k] = sum;
+}
+
+__global__ void k_lp_diag(const int64_t* __restrict__ lp_ptr, const int32_t* __restrict__ lp_col,
+                          const double* __restrict__ lp_val, int64_t nv, double* __restrict__ lpdinv,
+                          double* __restrict__ ratio) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= nv) return;
   double dg = 0.0, ra = 0.0;
-  for (int64_t j = rowptr[v]; j < rowptr[v + 1]; ++j) {
-    int32_t B = col[j];
-    if (dmask[B] != 0) continue;
-    double im = 1.0 / Md[B];
-#pragma unroll
-    for (int c = 0; c < D; ++c) {
-      double g = Gt[c * nnzv + j];
-      dg += g * g * im;
-      ra += fabs(g) * gs[(int64_t)B * D + c] * im;
-    }
+  for (int64_t k = lp_ptr[v]; k < lp_ptr[v + 1]; ++k) {
+    ra += fabs(lp_val[k]);
+    if (lp_col[k] == (int32_t)v) dg = lp_val[k];
   }
   lpdinv[v] = dg > 0.0 ? 1.0 / dg : 0.0;
   ratio[v] = dg > 0.0 ? ra / dg : 0.0;
@@ -563,19 +616,34 @@ void mesh_boundary(scvs_mesh m, hipStream_t s) {
 
 void mesh_precond_setup(scvs_mesh m, hipStream_t s) {
   const int D = m->dim;
-  DBuf<double> gs, ratio;
-  gs.alloc(m->n2 * D);
+  DBuf<int> err;
+  err.alloc(1);
+  err.zero(s);
+  DBuf<int32_t> cnt;
+  cnt.alloc(m->nv);
+  k_lp_rows<<<(unsigned)m->nv, ROW_BS, 0, s>>>(m->rowptr, m->col, m->nvc, m->dmask, cnt, nullptr, nullptr, err);
+  SCVS_HIP(hipGetLastError());
+  check_err(err, s, "pressure Laplacian pattern");
+  m->lp_ptr.alloc(m->nv + 1);
+  m->nnzl = exclusive_scan32(cnt, m->lp_ptr, m->nv, s);
+  m->lp_col.alloc(m->nnzl);
+  m->lp_val.alloc(m->nnzl);
+  k_lp_rows<<<(unsigned)m->nv, ROW_BS, 0, s>>>(m->rowptr, m->col, m->nvc, m->dmask, nullptr, m->lp_ptr, m->lp_col,
+                                               err);
+  SCVS_HIP(hipGetLastError());
+  if (D == 2)
+    k_lp_vals<2><<<nblk(m->nnzl), 256, 0, s>>>(m->lp_ptr, m->lp_col, m->nnzl, m->nv, m->rowptr, m->col, m->nvc,
+                                              m->rowptr21, m->G, m->Gt, m->nnz21, m->nnzv, m->Md, m->dmask,
+                                              m->lp_val);
+  else
+    k_lp_vals<3><<<nblk(m->nnzl), 256, 0, s>>>(m->lp_ptr, m->lp_col, m->nnzl, m->nv, m->rowptr, m->col, m->nvc,
+                                              m->rowptr21, m->G, m->Gt, m->nnz21, m->nnzv, m->Md, m->dmask,
+                                              m->lp_val);
+  SCVS_HIP(hipGetLastError());
+  DBuf<double> ratio;
   ratio.alloc(m->nv);
   m->lpdinv.alloc(m->nv);
-  if (D == 2) {
-    k_gabs<2><<<nblk(m->n2), 256, 0, s>>>(m->rowptr21, m->G, m->nnz21, m->dmask, m->n2, gs);
-    k_lpdiag<2><<<nblk(m->nv), 256, 0, s>>>(m->rowptr, m->col, m->Gt, m->nnzv, m->Md, m->dmask, gs, m->nv,
-                                            m->lpdinv, ratio);
-  } else {
-    k_gabs<3><<<nblk(m->n2), 256, 0, s>>>(m->rowptr21, m->G, m->nnz21, m->dmask, m->n2, gs);
-    k_lpdiag<3><<<nblk(m->nv), 256, 0, s>>>(m->rowptr, m->col, m->Gt, m->nnzv, m->Md, m->dmask, gs, m->nv,
-                                            m->lpdinv, ratio);
-  }
+  k_lp_diag<<<nblk(m->nv), 256, 0, s>>>(m->lp_ptr, m->lp_col, m->lp_val, m->nv, m->lpdinv, ratio);
   SCVS_HIP(hipGetLastError());
   DBuf<unsigned long long> mx;
   mx.alloc(1);

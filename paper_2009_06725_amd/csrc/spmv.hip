@@ -16,22 +16,33 @@ namespace {
 
 struct LaneMap {
   int G;     // (system, component) pairs per row
-  int Geff;  // lanes used per row group (a multiple of D)
-  int R;     // rows per wavefront
+  int W;     // lanes per row group (a power of two, <= 64)
+  int UL;    // pair lanes used per pass (a multiple of D, <= W)
+  int R;     // rows per wavefront (64 / W)
   int iters; // passes over the pairs
 };
 
+// Rows are handled by groups of W lanes (a power of two, so shuffles can stay
+// inside a group); the group's lanes cover the (system, component) pairs.
 LaneMap lane_map(int nact, int D) {
-  const int G = nact * D, UL = (64 / D) * D;
-  if (G <= UL) return {G, G, UL / G, 1};
-  return {G, UL, 1, (G + UL - 1) / UL};
+  const int G = nact * D;
+  if (G <= 32) {
+    int W = 1;
+    while (W < G) W <<= 1;
+    return {G, W, G, 64 / W, 1};
+  }
+  const int UL = (64 / D) * D;
+  return {G, 64, UL, 1, (G + UL - 1) / UL};
 }
 
 struct MeshArgs {
-  int64_t n2, nv, nnz21, nnzv;
+  int64_t n2, nv, nnz21, nnzv, nnz, nnzl;
   const int64_t *rowptr, *rowptr21;
   const int32_t *col, *nvc, *dmask;
   const double *Ks, *M, *G, *Gt, *Kd, *Md, *Mp, *lpdinv;
+  const int64_t* lp_ptr;
+  const int32_t* lp_col;
+  const double* lp_val;
   double mu, rho, lpmax;
 };
 
@@ -41,6 +52,8 @@ MeshArgs mesh_args(scvs_mesh m) {
   a.nv = m->nv;
   a.nnz21 = m->nnz21;
   a.nnzv = m->nnzv;
+  a.nnz = m->nnz;
+  a.nnzl = m->nnzl;
   a.rowptr = m->rowptr;
   a.rowptr21 = m->rowptr21;
   a.col = m->col;
@@ -54,6 +67,9 @@ MeshArgs mesh_args(scvs_mesh m) {
   a.Md = m->Md;
   a.Mp = m->Mp;
   a.lpdinv = m->lpdinv;
+  a.lp_ptr = m->lp_ptr;
+  a.lp_col = m->lp_col;
+  a.lp_val = m->lp_val;
   a.mu = m->mu;
   a.rho = m->rho;
   a.lpmax = m->lp_lmax;
@@ -62,17 +78,20 @@ MeshArgs mesh_args(scvs_mesh m) {
 
 struct Lane {
   int64_t row;
-  int p0;
+  int li;     // lane within the row group
+  int p0;     // first pair of this lane
   bool rowok;
+  bool pairok0;
 };
 
 __device__ __forceinline__ Lane lane_of(const LaneMap& lm, int64_t nrows) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int rs = lane / lm.Geff;
   Lane L;
-  L.p0 = lane % lm.Geff;
-  L.row = ((int64_t)blockIdx.x * 4 + wave) * lm.R + rs;
-  L.rowok = (rs < lm.R) && (L.row < nrows);
+  L.li = lane & (lm.W - 1);
+  L.p0 = L.li;
+  L.row = ((int64_t)blockIdx.x * 4 + wave) * lm.R + lane / lm.W;
+  L.rowok = L.row < nrows;
+  L.pairok0 = L.li < lm.UL;
   return L;
 }
 
@@ -92,60 +111,113 @@ __device__ __forceinline__ double2 sum_components(double2 v) {
   return r;
 }
 
+// Walk slots [j0, j1) of an S2 row: au += (mu Ks + (ar + j ai) M) x[col][c] (when
+// wantK) and ap += Gt^c x[col][c] (when wantGt). Every lane of the W-lane row
+// group calls this together: the group first loads W slots of (col, Ks, M)
+// lane-parallel (coalesced), then broadcasts them by shuffles and issues eight
+// independent gathers at a time. With MASK, Dirichlet columns are skipped.
+template <int D, bool MASK>
+__device__ __forceinline__ void row_acc(const MeshArgs& ma, int W, int li, int64_t j0, int64_t j1,
+                                        const double2* __restrict__ xs, int c, bool pairok, double ar, double ai,
+                                        bool wantK, bool wantGt, double2& au, double2& ap) {
+  constexpr int U = 8;
+  for (int64_t jb = j0; jb < j1; jb += W) {
+    const int n = (int)min((int64_t)W, j1 - jb);
+    int32_t mc = 0;
+    double mk = 0.0, mm = 0.0;
+    if (li < n) {
+      mc = ma.col[jb + li];
+      mk = ma.Ks[jb + li];
+      mm = ma.M[jb + li];
+      if (MASK && ma.dmask[mc] != 0) mc = -1;
+    }
+    for (int t = 0; t < n; t += U) {
+      int32_t B[U];
+      double k[U], m[U];
+      double2 xv[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        B[u] = __shfl(mc, t + u < n ? t + u : 0, W);
+        k[u] = __shfl(mk, t + u < n ? t + u : 0, W);
+        m[u] = __shfl(mm, t + u < n ? t + u : 0, W);
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        xv[u] = (pairok && t + u < n && B[u] >= 0) ? xs[(int64_t)B[u] * D + c] : make_double2(0.0, 0.0);
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if (wantK) {
+          const double kr = ma.mu * k[u] + ar * m[u], ki = ai * m[u];
+          au.x += kr * xv[u].x - ki * xv[u].y;
+          au.y += kr * xv[u].y + ki * xv[u].x;
+        }
+        if (wantGt && pairok && t + u < n) {
+          const double g = ma.Gt[(int64_t)c * ma.nnzv + jb + t + u];
+          ap.x += g * xv[u].x;
+          ap.y += g * xv[u].y;
+        }
+      }
+    }
+  }
+}
+
+// acc += s * sum_{jj < nvc} G^c[row prefix] p[col] over the vertex-column prefix of a row.
+template <int D>
+__device__ __forceinline__ void g_acc(const MeshArgs& ma, int64_t A, int64_t j0, const double2* __restrict__ p,
+                                      int c, double s, double2& acc) {
+  const int nvr = ma.nvc[A];
+  const double* __restrict__ Gc = ma.G + (int64_t)c * ma.nnz21 + ma.rowptr21[A];
+  const int32_t* __restrict__ cl = ma.col + j0;
+  int jj = 0;
+  for (; jj + 4 <= nvr; jj += 4) {
+    int32_t B[4];
+    double g[4];
+    double2 pv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) B[u] = cl[jj + u];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      g[u] = Gc[jj + u];
+      pv[u] = p[B[u]];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      acc.x += s * g[u] * pv[u].x;
+      acc.y += s * g[u] * pv[u].y;
+    }
+  }
+  for (; jj < nvr; ++jj) {
+    const double2 pv = p[cl[jj]];
+    acc.x += s * Gc[jj] * pv.x;
+    acc.y += s * Gc[jj] * pv.y;
+  }
+}
+
 template <int D, int MODE, bool MASK>
 __global__ void __launch_bounds__(256) k_full(MeshArgs ma, Batch b, LaneMap lm, VArg x, VArg y, VArg f,
                                               const double* __restrict__ loads, int ntr,
                                               const double2* __restrict__ trac) {
   const Lane L = lane_of(lm, ma.n2);
+  if (!L.rowok) return;  // uniform over the row group
+  const int64_t A = L.row;
+  const int32_t dm = ma.dmask[A];
+  const bool isv = A < ma.nv;
+  const int64_t j0 = ma.rowptr[A], j1 = ma.rowptr[A + 1];
   for (int it = 0; it < lm.iters; ++it) {
-    const int p = L.p0 + it * lm.Geff;
-    const bool ok = L.rowok && p < lm.G;
-    const int si = p / D, c = p % D;
+    const int p = L.li + it * lm.UL;
+    const bool ok = L.pairok0 && p < lm.G;
+    const int si = ok ? p / D : 0, c = ok ? p % D : 0;
+    const int slot = b.act[si];
+    const double sc = in_scale(b, slot);
+    const double2* __restrict__ xs = x.at(slot);
+    const double wr = b.omega[slot] * ma.rho;
     double2 au = make_double2(0.0, 0.0), ap = make_double2(0.0, 0.0);
-    int slot = 0;
-    double sc = 1.0;
-    int32_t dm = 0;
-    const int64_t A = L.row;
+    if (dm == 0 || isv) row_acc<D, MASK>(ma, lm.W, L.li, j0, j1, xs, c, ok, 0.0, wr, dm == 0, isv, au, ap);
     if (ok) {
-      slot = b.act[si];
-      sc = in_scale(b, slot);
-      const double2* __restrict__ xs = x.at(slot);
-      const double wr = b.omega[slot] * ma.rho;
-      dm = ma.dmask[A];
-      const bool isv = A < ma.nv;
-      const int64_t j0 = ma.rowptr[A], j1 = ma.rowptr[A + 1];
-      if (dm == 0 || isv) {
-        for (int64_t j = j0; j < j1; ++j) {
-          const int32_t B = ma.col[j];
-          if (MASK && ma.dmask[B] != 0) continue;
-          const double2 xv = xs[(int64_t)B * D + c];
-          if (dm == 0) {
-            const double kr = ma.mu * ma.Ks[j], mi = wr * ma.M[j];
-            au.x += kr * xv.x - mi * xv.y;
-            au.y += kr * xv.y + mi * xv.x;
-          }
-          if (isv) {
-            const double g = ma.Gt[(int64_t)c * ma.nnzv + j];
-            ap.x += g * xv.x;
-            ap.y += g * xv.y;
-          }
-        }
-      }
-      if (dm == 0) {
-        const int nvr = ma.nvc[A];
-        const int64_t o21 = ma.rowptr21[A];
-        const double2* __restrict__ xp = xs + D * ma.n2;
-        for (int jj = 0; jj < nvr; ++jj) {
-          const double g = ma.G[(int64_t)c * ma.nnz21 + o21 + jj];
-          const double2 pv = xp[ma.col[j0 + jj]];
-          au.x += g * pv.x;
-          au.y += g * pv.y;
-        }
-      }
+      if (dm == 0) g_acc<D>(ma, A, j0, xs + D * ma.n2, c, 1.0, au);
       double2 yu;
       if (dm != 0) {
-        const double2 xv = xs[A * D + c];
-        yu = cscale(xv, sc);
+        yu = cscale(xs[A * D + c], sc);
         if (MODE == SPMV_RESID) yu = csub(f.at(slot)[A * D + c], yu);
       } else {
         au = cscale(au, sc);
@@ -165,12 +237,14 @@ __global__ void __launch_bounds__(256) k_full(MeshArgs ma, Batch b, LaneMap lm, 
       }
       y.at(slot)[A * D + c] = yu;
     }
-    const double2 ps = sum_components<D>(ap);
-    if (ok && A < ma.nv && c == 0) {
-      double2 yp = cscale(ps, sc);
-      if (MODE == SPMV_RESID) yp = csub(f.at(slot)[D * ma.n2 + A], yp);
-      if (MODE == SPMV_RHS) yp = make_double2(-yp.x, -yp.y);
-      y.at(slot)[D * ma.n2 + A] = yp;
+    if (isv) {
+      const double2 ps = sum_components<D>(ap);
+      if (ok && c == 0) {
+        double2 yp = cscale(ps, sc);
+        if (MODE == SPMV_RESID) yp = csub(f.at(slot)[D * ma.n2 + A], yp);
+        if (MODE == SPMV_RHS) yp = make_double2(-yp.x, -yp.y);
+        y.at(slot)[D * ma.n2 + A] = yp;
+      }
     }
   }
 }
@@ -192,91 +266,85 @@ __device__ __forceinline__ void cheb_coef(double lmax, double ratio, int i, doub
   rcur = r;
 }
 
-// Velocity block, first Chebyshev step: t = insc*v_u - G zhat_p on free rows;
-// r = t; d0 = diag^-1 t / theta; z_u = d0.
+// Velocity block, Chebyshev polynomial in diag^-1 A_r with A_r = mu Ks + |w| rho M
+// (same for every component), in three-term form
+//   x_1 = diag^-1 b / theta,
+//   x_{k+1} = x_k + rho_k rho_{k-1} (x_k - x_{k-1}) + (2 rho_k / delta) diag^-1 (b - A_r x_k),
+// with b = insc*v_u - G zhat_p. Temps per slot: b, x_a, x_b, x_c (d*n2 each);
+// the last iterate is written into z. Dirichlet rows stay zero.
+__device__ __forceinline__ double2* vbuf(const VArg& vt, int slot, int64_t DN, int k) {
+  return vt.at(slot) + DN * (1 + (k % 3));
+}
+
 template <int D>
 __global__ void __launch_bounds__(256) k_vinit(MeshArgs ma, Batch b, LaneMap lm, VArg v, VArg z, VArg vt,
-                                               double ratio) {
+                                               double ratio, int kv) {
   const Lane L = lane_of(lm, ma.n2);
   for (int it = 0; it < lm.iters; ++it) {
-    const int p = L.p0 + it * lm.Geff;
-    if (!(L.rowok && p < lm.G)) continue;
+    const int p = L.li + it * lm.UL;
+    if (!(L.rowok && L.pairok0 && p < lm.G)) continue;
     const int si = p / D, c = p % D;
     const int slot = b.act[si];
     const int64_t A = L.row, DN = D * ma.n2;
-    double2* __restrict__ r = vt.at(slot);
-    double2* __restrict__ d0 = r + DN;
+    double2* __restrict__ bb = vt.at(slot);
+    double2* __restrict__ x1 = (kv == 1) ? z.at(slot) : vbuf(vt, slot, DN, 1);
     double2* __restrict__ zs = z.at(slot);
     const int64_t k = A * D + c;
     if (ma.dmask[A] != 0) {
-      r[k] = d0[k] = zs[k] = make_double2(0.0, 0.0);
+      bb[k] = x1[k] = make_double2(0.0, 0.0);
       continue;
     }
     const double sc = in_scale(b, slot);
     double2 t = cscale(v.at(slot)[k], sc);
-    const int nvr = ma.nvc[A];
-    const int64_t o21 = ma.rowptr21[A], j0 = ma.rowptr[A];
-    const double2* __restrict__ zp = zs + DN;
-    for (int jj = 0; jj < nvr; ++jj) {
-      const double g = ma.G[(int64_t)c * ma.nnz21 + o21 + jj];
-      const double2 pv = zp[ma.col[j0 + jj]];
-      t.x -= g * pv.x;
-      t.y -= g * pv.y;
-    }
+    g_acc<D>(ma, A, ma.rowptr[A], zs + DN, c, -1.0, t);
     const double lmax = b.lv[slot];
     const double theta = 0.5 * lmax * (1.0 + 1.0 / ratio);
     const double dinv = 1.0 / (ma.mu * ma.Kd[A] + fabs(b.omega[slot]) * ma.rho * ma.Md[A]);
-    const double2 dd = cscale(t, dinv / theta);
-    r[k] = t;
-    d0[k] = dd;
-    zs[k] = dd;
+    bb[k] = t;
+    x1[k] = cscale(t, dinv / theta);
   }
 }
 
-// Velocity block, Chebyshev step i: r -= A_r d_old; d_new = a d_old + b diag^-1 r; z += d_new.
 template <int D>
 __global__ void __launch_bounds__(256) k_vstep(MeshArgs ma, Batch b, LaneMap lm, VArg z, VArg vt, double ratio,
-                                               int step) {
+                                               int step, int last) {
   const Lane L = lane_of(lm, ma.n2);
+  if (!L.rowok) return;  // uniform over the row group
+  const int64_t A = L.row, DN = D * ma.n2;
+  const bool dir = ma.dmask[A] != 0;
+  const int64_t j0 = ma.rowptr[A], j1 = ma.rowptr[A + 1];
   for (int it = 0; it < lm.iters; ++it) {
-    const int p = L.p0 + it * lm.Geff;
-    if (!(L.rowok && p < lm.G)) continue;
-    const int si = p / D, c = p % D;
+    const int p = L.li + it * lm.UL;
+    const bool ok = L.pairok0 && p < lm.G;
+    const int si = ok ? p / D : 0, c = ok ? p % D : 0;
     const int slot = b.act[si];
-    const int64_t A = L.row, DN = D * ma.n2;
-    double2* __restrict__ r = vt.at(slot);
-    const double2* __restrict__ dold = r + ((step & 1) ? DN : 2 * DN);
-    double2* __restrict__ dnew = r + ((step & 1) ? 2 * DN : DN);
+    const double2* __restrict__ xk = vbuf(vt, slot, DN, step);
+    double2* __restrict__ xn = last ? z.at(slot) : vbuf(vt, slot, DN, step + 1);
     const int64_t k = A * D + c;
-    if (ma.dmask[A] != 0) {
-      dnew[k] = make_double2(0.0, 0.0);
+    if (dir) {
+      if (ok) xn[k] = make_double2(0.0, 0.0);
       continue;
     }
     const double wr = fabs(b.omega[slot]) * ma.rho;
-    double2 q = make_double2(0.0, 0.0);
-    for (int64_t j = ma.rowptr[A]; j < ma.rowptr[A + 1]; ++j) {
-      const double a = ma.mu * ma.Ks[j] + wr * ma.M[j];
-      const double2 dv = dold[(int64_t)ma.col[j] * D + c];
-      q.x += a * dv.x;
-      q.y += a * dv.y;
-    }
+    double2 q = make_double2(0.0, 0.0), unused = make_double2(0.0, 0.0);
+    row_acc<D, false>(ma, lm.W, L.li, j0, j1, xk, c, ok, wr, 0.0, true, false, q, unused);
+    if (!ok) continue;
+    const double2* __restrict__ bb = vt.at(slot);
+    const double2* __restrict__ xm = vbuf(vt, slot, DN, step - 1);
     double rp, rc, delta, theta;
     cheb_coef(b.lv[slot], ratio, step, rp, rc, delta, theta);
     const double dinv = 1.0 / (ma.mu * ma.Kd[A] + wr * ma.Md[A]);
-    const double2 rn = csub(r[k], q);
-    const double2 dk = dold[k];
+    const double2 rk = csub(bb[k], q);
+    const double2 xv = xk[k];
+    const double2 xo = (step == 1) ? make_double2(0.0, 0.0) : xm[k];
     const double ca = rc * rp, cb = 2.0 * rc / delta * dinv;
-    const double2 dn = make_double2(ca * dk.x + cb * rn.x, ca * dk.y + cb * rn.y);
-    r[k] = rn;
-    dnew[k] = dn;
-    double2* __restrict__ zs = z.at(slot);
-    zs[k] = cadd(zs[k], dn);
+    xn[k] = make_double2(xv.x + ca * (xv.x - xo.x) + cb * rk.x, xv.y + ca * (xv.y - xo.y) + cb * rk.y);
   }
 }
 
 // Pressure block, first step (elementwise over vertices): r = insc*v_p,
 // d0 = diag(L)^-1 r / theta, x = d0; with one step the Schur block is final:
-// zhat_p = -(mu Mp^-1 v_p + j w rho x).
+// zhat_p = -(mu Mp^-1 v_p + j w rho x). Temps per slot: r, d0, d1, x (nv each).
 __global__ void k_pinit(MeshArgs ma, int D, Batch b, VArg v, VArg z, VArg pt, double ratio, int kp) {
   const int64_t vv = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (vv >= ma.nv) return;
@@ -284,8 +352,8 @@ __global__ void k_pinit(MeshArgs ma, int D, Batch b, VArg v, VArg z, VArg pt, do
   const int64_t DN = D * ma.n2, nv = ma.nv;
   const double sc = in_scale(b, slot);
   const double2 vp = cscale(v.at(slot)[DN + vv], sc);
-  double2* t = pt.at(slot);
-  double2 *rp = t + DN, *d0 = rp + nv, *xp = rp + 3 * nv;
+  double2* rp = pt.at(slot);
+  double2 *d0 = rp + nv, *xp = rp + 3 * nv;
   const double theta = 0.5 * ma.lpmax * (1.0 + 1.0 / ratio);
   const double2 dd = cscale(vp, ma.lpdinv[vv] / theta);
   rp[vv] = vp;
@@ -297,81 +365,63 @@ __global__ void k_pinit(MeshArgs ma, int D, Batch b, VArg v, VArg z, VArg pt, do
   }
 }
 
-// Pressure Laplacian, first half: t = diag(M)^-1 G_F d_old (zero on Dirichlet rows).
-template <int D>
-__global__ void __launch_bounds__(256) k_lp1(MeshArgs ma, Batch b, LaneMap lm, VArg pt, int step) {
-  const Lane L = lane_of(lm, ma.n2);
-  for (int it = 0; it < lm.iters; ++it) {
-    const int p = L.p0 + it * lm.Geff;
-    if (!(L.rowok && p < lm.G)) continue;
-    const int si = p / D, c = p % D;
-    const int slot = b.act[si];
-    const int64_t A = L.row, DN = D * ma.n2, nv = ma.nv;
-    double2* t = pt.at(slot);
-    const double2* __restrict__ dold = t + DN + ((step & 1) ? nv : 2 * nv);
-    double2 acc = make_double2(0.0, 0.0);
-    if (ma.dmask[A] == 0) {
-      const int nvr = ma.nvc[A];
-      const int64_t o21 = ma.rowptr21[A], j0 = ma.rowptr[A];
-      for (int jj = 0; jj < nvr; ++jj) {
-        const double g = ma.G[(int64_t)c * ma.nnz21 + o21 + jj];
-        const double2 pv = dold[ma.col[j0 + jj]];
-        acc.x += g * pv.x;
-        acc.y += g * pv.y;
-      }
-      acc = cscale(acc, 1.0 / ma.Md[A]);
-    }
-    t[A * D + c] = acc;
-  }
-}
-
-// Pressure Laplacian, second half and Chebyshev step on the vertex rows:
-// q = G^T t; r -= q; d_new = a d_old + b diag(L)^-1 r; x += d_new; on the last
-// step zhat_p = -(mu Mp^-1 v_p + j w rho x).
-template <int D>
-__global__ void __launch_bounds__(256) k_lp2(MeshArgs ma, Batch b, LaneMap lm, VArg v, VArg z, VArg pt,
-                                             double ratio, int step, int last) {
+// Pressure Laplacian Chebyshev step on the assembled L (one lane per system):
+// r -= L d_old; d_new = a d_old + b diag(L)^-1 r; x += d_new; on the last step
+// zhat_p = -(mu Mp^-1 v_p + j w rho x).
+__global__ void __launch_bounds__(256) k_pstep(MeshArgs ma, int D, Batch b, LaneMap lm, VArg v, VArg z, VArg pt,
+                                               double ratio, int step, int last) {
   const Lane L = lane_of(lm, ma.nv);
   for (int it = 0; it < lm.iters; ++it) {
-    const int p = L.p0 + it * lm.Geff;
-    const bool ok = L.rowok && p < lm.G;
-    const int si = p / D, c = p % D;
-    const int64_t A = L.row;
-    int slot = 0;
+    const int p = L.li + it * lm.UL;
+    if (!(L.rowok && L.pairok0 && p < lm.G)) continue;
+    const int slot = b.act[p];
+    const int64_t A = L.row, nv = ma.nv;
+    double2* rp = pt.at(slot);
+    const double2* __restrict__ dold = rp + ((step & 1) ? nv : 2 * nv);
+    double2* dnew = rp + ((step & 1) ? 2 * nv : nv);
+    double2* xp = rp + 3 * nv;
     double2 q = make_double2(0.0, 0.0);
-    if (ok) {
-      slot = b.act[si];
-      const double2* __restrict__ t = pt.at(slot);
-      for (int64_t j = ma.rowptr[A]; j < ma.rowptr[A + 1]; ++j) {
-        const double g = ma.Gt[(int64_t)c * ma.nnzv + j];
-        const double2 tv = t[(int64_t)ma.col[j] * D + c];
-        q.x += g * tv.x;
-        q.y += g * tv.y;
+    const int64_t k0 = ma.lp_ptr[A], k1 = ma.lp_ptr[A + 1];
+    int64_t k = k0;
+    for (; k + 4 <= k1; k += 4) {
+      int32_t u[4];
+      double l[4];
+      double2 dv[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) u[t] = ma.lp_col[k + t];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        l[t] = ma.lp_val[k + t];
+        dv[t] = dold[u[t]];
+      }
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        q.x += l[t] * dv[t].x;
+        q.y += l[t] * dv[t].y;
       }
     }
-    q = sum_components<D>(q);
-    if (ok && c == 0) {
-      const int64_t DN = D * ma.n2, nv = ma.nv;
-      double2* t = pt.at(slot);
-      double2 *rp = t + DN, *xp = rp + 3 * nv;
-      const double2* dold = rp + ((step & 1) ? nv : 2 * nv);
-      double2* dnew = rp + ((step & 1) ? 2 * nv : nv);
-      double rpv, rc, delta, theta;
-      cheb_coef(ma.lpmax, ratio, step, rpv, rc, delta, theta);
-      const double2 rn = csub(rp[A], q);
-      const double ca = rc * rpv, cb = 2.0 * rc / delta * ma.lpdinv[A];
-      const double2 dk = dold[A];
-      const double2 dn = make_double2(ca * dk.x + cb * rn.x, ca * dk.y + cb * rn.y);
-      const double2 xn = cadd(xp[A], dn);
-      rp[A] = rn;
-      dnew[A] = dn;
-      xp[A] = xn;
-      if (last) {
-        const double sc = in_scale(b, slot);
-        const double2 vp = cscale(v.at(slot)[DN + A], sc);
-        const double wr = b.omega[slot] * ma.rho, im = ma.mu / ma.Mp[A];
-        z.at(slot)[DN + A] = make_double2(-(im * vp.x - wr * xn.y), -(im * vp.y + wr * xn.x));
-      }
+    for (; k < k1; ++k) {
+      const double l = ma.lp_val[k];
+      const double2 dv = dold[ma.lp_col[k]];
+      q.x += l * dv.x;
+      q.y += l * dv.y;
+    }
+    double rpv, rc, delta, theta;
+    cheb_coef(ma.lpmax, ratio, step, rpv, rc, delta, theta);
+    const double2 rn = csub(rp[A], q);
+    const double ca = rc * rpv, cb = 2.0 * rc / delta * ma.lpdinv[A];
+    const double2 dk = dold[A];
+    const double2 dn = make_double2(ca * dk.x + cb * rn.x, ca * dk.y + cb * rn.y);
+    const double2 xn = cadd(xp[A], dn);
+    rp[A] = rn;
+    dnew[A] = dn;
+    xp[A] = xn;
+    if (last) {
+      const int64_t DN = D * ma.n2;
+      const double sc = in_scale(b, slot);
+      const double2 vp = cscale(v.at(slot)[DN + A], sc);
+      const double wr = b.omega[slot] * ma.rho, im = ma.mu / ma.Mp[A];
+      z.at(slot)[DN + A] = make_double2(-(im * vp.x - wr * xn.y), -(im * vp.y + wr * xn.x));
     }
   }
 }
@@ -404,11 +454,24 @@ inline unsigned row_blocks(int64_t nrows, const LaneMap& lm) {
   return (unsigned)((nrows + per - 1) / per);
 }
 
+// Algorithmic bytes of one full-operator launch: every matrix array once
+// (S2 col/Ks/M, G on the vertex-column prefix, Gt on vertex rows, row
+// pointers, counts and masks) and, per system, x read once and y written once
+// (plus f read in residual mode).
+double full_bytes(const MeshArgs& ma, int D, int nact, int mode) {
+  const double mat = (double)ma.nnz * 20.0 + (double)ma.nnz21 * (4.0 + 8.0 * D) +
+                     (double)ma.nnzv * 8.0 * D + (double)ma.n2 * 24.0;
+  const double ndof = (double)D * ma.n2 + ma.nv;
+  return mat + nact * ndof * 16.0 * (mode == SPMV_RESID ? 3.0 : 2.0);
+}
+
 template <int D>
-void full_launch(const MeshArgs& ma, const Batch& b, VArg x, VArg y, int mode, bool mask, VArg f,
+void full_launch(Profiler* prof, const MeshArgs& ma, const Batch& b, VArg x, VArg y, int mode, bool mask, VArg f,
                  const double* loads, int ntr, const double2* trac, hipStream_t s) {
   const LaneMap lm = lane_map(b.nact, D);
   const unsigned nb = row_blocks(ma.n2, lm);
+  const char* nm = mode == SPMV_APPLY ? "k_full_apply" : (mode == SPMV_RESID ? "k_full_resid" : "k_full_rhs");
+  ProfScope ps(prof, s, nm, full_bytes(ma, D, b.nact, mode));
   if (mode == SPMV_APPLY && mask)
     k_full<D, SPMV_APPLY, true><<<nb, 256, 0, s>>>(ma, b, lm, x, y, f, loads, ntr, trac);
   else if (mode == SPMV_APPLY)
@@ -421,17 +484,36 @@ void full_launch(const MeshArgs& ma, const Batch& b, VArg x, VArg y, int mode, b
 }
 
 template <int D>
-void precond_launch(const MeshArgs& ma, const Batch& b, const PrecondArgs& pa, VArg v, VArg z, hipStream_t s) {
-  const LaneMap lm = lane_map(b.nact, D);
-  const unsigned nbu = row_blocks(ma.n2, lm), nbp = row_blocks(ma.nv, lm);
+void precond_launch(Profiler* prof, const MeshArgs& ma, const Batch& b, const PrecondArgs& pa, VArg v, VArg z,
+                    hipStream_t s) {
+  const LaneMap lm = lane_map(b.nact, D), lp = lane_map(b.nact, 1);
+  const unsigned nbu = row_blocks(ma.n2, lm), nbp = row_blocks(ma.nv, lp);
+  const double n2 = (double)ma.n2, nv = (double)ma.nv, DN = (double)D * ma.n2, na = b.nact;
   dim3 gp((unsigned)((ma.nv + 255) / 256), (unsigned)b.nact);
-  k_pinit<<<gp, 256, 0, s>>>(ma, D, b, v, z, pa.pt, pa.ratio, pa.kp);
-  for (int i = 1; i < pa.kp; ++i) {
-    k_lp1<D><<<nbu, 256, 0, s>>>(ma, b, lm, pa.pt, i);
-    k_lp2<D><<<nbp, 256, 0, s>>>(ma, b, lm, v, z, pa.pt, pa.ratio, i, i == pa.kp - 1);
+  {
+    // per system: v_p read, r/d0/x written (and z_p when one step); lpdinv, Mp read
+    ProfScope ps(prof, s, "k_pinit", nv * 16.0 + na * nv * 16.0 * 4.0);
+    k_pinit<<<gp, 256, 0, s>>>(ma, D, b, v, z, pa.pt, pa.ratio, pa.kp);
   }
-  k_vinit<D><<<nbu, 256, 0, s>>>(ma, b, lm, v, z, pa.vt, pa.ratio);
-  for (int i = 1; i < pa.kv; ++i) k_vstep<D><<<nbu, 256, 0, s>>>(ma, b, lm, z, pa.vt, pa.ratio, i);
+  // L values and columns, row pointers, diag, Mp; per system d_old gathered,
+  // r read+written, d_new written, x read+written
+  const double pbytes = (double)ma.nnzl * 12.0 + nv * 24.0 + na * nv * 16.0 * 6.0;
+  for (int i = 1; i < pa.kp; ++i) {
+    ProfScope ps(prof, s, "k_pstep", pbytes + (i == pa.kp - 1 ? na * nv * 32.0 : 0.0));
+    k_pstep<<<nbp, 256, 0, s>>>(ma, D, b, lp, v, z, pa.pt, pa.ratio, i, i == pa.kp - 1);
+  }
+  {
+    // vertex-column prefix (col + G), row arrays; per system v_u read, z_p read, b and x_1 written
+    ProfScope ps(prof, s, "k_vinit",
+                 (double)ma.nnz21 * (4.0 + 8.0 * D) + n2 * 40.0 + na * (3.0 * DN + nv) * 16.0);
+    k_vinit<D><<<nbu, 256, 0, s>>>(ma, b, lm, v, z, pa.vt, pa.ratio, pa.kv);
+  }
+  // S2 col/Ks/M, rowptr/dmask/Kd/Md; per system x_k (gathered, read once), b, x_{k-1} read, x_{k+1} written
+  const double vbytes = (double)ma.nnz * 20.0 + n2 * 28.0 + na * 4.0 * DN * 16.0;
+  for (int i = 1; i < pa.kv; ++i) {
+    ProfScope ps(prof, s, "k_vstep", vbytes);
+    k_vstep<D><<<nbu, 256, 0, s>>>(ma, b, lm, z, pa.vt, pa.ratio, i, i == pa.kv - 1);
+  }
   launch_check(s);
 }
 
@@ -442,17 +524,17 @@ void spmv_full(scvs_mesh m, const Batch& b, VArg x, VArg y, int mode, bool maskc
   const MeshArgs ma = mesh_args(m);
   const int ntr = (int)m->traction_tags.size();
   if (m->dim == 2)
-    full_launch<2>(ma, b, x, y, mode, maskcol, f, m->loads, ntr, trac, s);
+    full_launch<2>(&m->ctx->prof, ma, b, x, y, mode, maskcol, f, m->loads, ntr, trac, s);
   else
-    full_launch<3>(ma, b, x, y, mode, maskcol, f, m->loads, ntr, trac, s);
+    full_launch<3>(&m->ctx->prof, ma, b, x, y, mode, maskcol, f, m->loads, ntr, trac, s);
 }
 
 void precond_apply(scvs_mesh m, const Batch& b, const PrecondArgs& pa, VArg v, VArg z, hipStream_t s) {
   const MeshArgs ma = mesh_args(m);
   if (m->dim == 2)
-    precond_launch<2>(ma, b, pa, v, z, s);
+    precond_launch<2>(&m->ctx->prof, ma, b, pa, v, z, s);
   else
-    precond_launch<3>(ma, b, pa, v, z, s);
+    precond_launch<3>(&m->ctx->prof, ma, b, pa, v, z, s);
 }
 
 void velocity_bounds(scvs_mesh m, const Batch& b, double* lv_out, hipStream_t s) {

@@ -5,6 +5,53 @@ namespace scvs {
 
 [[noreturn]] void fail(int code, const std::string& msg) { throw Error{code, msg}; }
 
+hipEvent_t Profiler::get() {
+  if (used == pool.size()) {
+    hipEvent_t e;
+    SCVS_HIP(hipEventCreate(&e));
+    pool.push_back(e);
+  }
+  return pool[used++];
+}
+
+void Profiler::resolve() {
+  if (pending.empty()) return;
+  SCVS_HIP(hipEventSynchronize(pending.back().b));
+  for (auto& pd : pending) {
+    float ms = 0.0f;
+    SCVS_HIP(hipEventElapsedTime(&ms, pd.a, pd.b));
+    auto it = std::find_if(stats.begin(), stats.end(), [&](const auto& kv) { return kv.first == pd.name; });
+    if (it == stats.end()) {
+      stats.push_back({pd.name, Stat{}});
+      it = stats.end() - 1;
+    }
+    it->second.launches += 1;
+    it->second.ms += ms;
+    it->second.bytes += pd.bytes;
+  }
+  pending.clear();
+  used = 0;
+}
+
+Profiler::~Profiler() {
+  for (auto e : pool) (void)hipEventDestroy(e);
+}
+
+ProfScope::ProfScope(Profiler* p, hipStream_t s, const char* name, double bytes) : p_(p), s_(s) {
+  if (!p_ || !p_->on || capturing(s)) {
+    p_ = nullptr;
+    return;
+  }
+  hipEvent_t a = p_->get(), b = p_->get();
+  SCVS_HIP(hipEventRecord(a, s));
+  p_->pending.push_back({name, a, b, bytes});
+  idx_ = p_->pending.size() - 1;
+}
+
+ProfScope::~ProfScope() {
+  if (p_) (void)hipEventRecord(p_->pending[idx_].b, s_);
+}
+
 namespace {
 
 constexpr int SCAN_BS = 256;

@@ -23,7 +23,7 @@ EXPORTED = [
     "scvs_last_error", "scvs_version", "scvs_ctx_create", "scvs_ctx_destroy", "scvs_mesh_create",
     "scvs_mesh_destroy", "scvs_mesh_info", "scvs_mesh_set_midside", "scvs_mesh_set_bc", "scvs_assemble",
     "scvs_mesh_export", "scvs_spmv", "scvs_rhs", "scvs_solve_opts_default", "scvs_solve",
-    "scvs_synthesize", "scvs_probe_mfma",
+    "scvs_synthesize", "scvs_probe_mfma", "scvs_profile_enable", "scvs_profile_read",
 ]
 
 
@@ -44,6 +44,11 @@ class SolveOpts(C.Structure):
     _fields_ = [("rtol", C.c_double), ("restart", C.c_int32), ("max_iters", C.c_int32),
                 ("cheb_vel", C.c_int32), ("cheb_pres", C.c_int32), ("cheb_ratio", C.c_double),
                 ("max_batch", C.c_int32), ("use_graph", C.c_int32), ("verbose", C.c_int32)]
+
+
+class KernelStat(C.Structure):
+    _fields_ = [("name", C.c_char * 40), ("launches", C.c_int64), ("total_ms", C.c_double),
+                ("bytes", C.c_double)]
 
 
 class Report(C.Structure):
@@ -79,6 +84,8 @@ def lib() -> C.CDLL:
         L.scvs_solve.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, C.POINTER(SolveOpts), C.POINTER(Report)]
         L.scvs_synthesize.argtypes = [vp, i64, vp, vp, i64, i64, vp, vp]
         L.scvs_probe_mfma.argtypes = [vp, vp, vp, vp]
+        L.scvs_profile_enable.argtypes = [vp, C.c_int]
+        L.scvs_profile_read.argtypes = [vp, C.c_int, C.POINTER(KernelStat), C.POINTER(C.c_int)]
         for name in EXPORTED:
             if name not in ("scvs_last_error", "scvs_version", "scvs_solve_opts_default"):
                 getattr(L, name).restype = C.c_int
@@ -123,6 +130,17 @@ class Context:
         h = C.c_void_p()
         _check(lib().scvs_ctx_create(device, C.c_void_p(stream.cuda_stream), C.byref(h)))
         self.h = h
+
+    def profile(self, on: bool):
+        """Time every library kernel launch with HIP events on this context's stream."""
+        _check(lib().scvs_profile_enable(self.h, 1 if on else 0))
+
+    def profile_read(self) -> dict:
+        """{kernel class: (launches, total_ms, algorithmic bytes)} since the last read."""
+        buf = (KernelStat * 64)()
+        n = C.c_int()
+        _check(lib().scvs_profile_read(self.h, 64, buf, C.byref(n)))
+        return {buf[i].name.decode(): (buf[i].launches, buf[i].total_ms, buf[i].bytes) for i in range(n.value)}
 
     def close(self):
         if self.h:
