@@ -180,10 +180,16 @@ typedef struct {
   int32_t max_batch;  /* systems solved together (0 = as many as fit) */
   int32_t use_graph;  /* replay each restart cycle from a captured hipGraph */
   int32_t verbose;    /* print per-cycle residuals to stderr */
+  int32_t precision;  /* 0: all FP64. 1: mixed -- inside each restart cycle the operator
+                         product and the velocity-block polynomial run on FP32 matrix copies
+                         and FP32 vectors with FP32 accumulation; the true residual f - A x
+                         recomputed at every restart (iterative refinement), the Arnoldi
+                         orthogonalization, Givens/least-squares, the pressure Schur block
+                         and the solution update stay FP64 */
 } scvs_solve_opts;
 
 /* Fill `o` with the defaults (rtol 1e-10, m 60, 20000 iterations, degrees 10/20,
- * ratio 30, batch 0, graphs on). */
+ * ratio 30, batch 0, graphs on, FP64). */
 void scvs_solve_opts_default(scvs_solve_opts* o);
 
 typedef struct {

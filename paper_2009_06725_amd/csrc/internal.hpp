@@ -128,6 +128,8 @@ struct scvs_mesh_s {
   scvs::DBuf<int32_t> nf_list;
   // assembled values
   scvs::DBuf<double> Ks, M, G, Gt, Kd, Md, Mp;
+  scvs::DBuf<float> Ks32, M32, G32, Gt32, Kd32, Md32;  // made on the first mixed-precision solve
+  bool fp32_ready = false;
   // boundary conditions
   std::vector<int32_t> bc_tags, bc_kinds, traction_tags;
   scvs::DBuf<int32_t> dmask, dirnodes;
@@ -191,6 +193,12 @@ struct VArg {
   int64_t st = 0;
   __host__ __device__ double2* at(int k) const { return p + (int64_t)k * st; }
 };
+// Same, for complex single-precision vectors (mixed-precision solves).
+struct VArg32 {
+  float2* p = nullptr;
+  int64_t st = 0;
+  __host__ __device__ float2* at(int k) const { return p + (int64_t)k * st; }
+};
 // The active systems of one launch.
 struct Batch {
   int nact = 0;
@@ -208,10 +216,17 @@ void spmv_full(scvs_mesh m, const Batch& b, VArg x, VArg y, int mode, bool maskc
 struct PrecondArgs {
   int kv = 10, kp = 10;
   double ratio = 30.0;
+  int mixed = 0;  // 1: velocity block in FP32 (vt32, output z32); pressure block stays FP64
+  VArg32 vt32;    // FP32 velocity temps: 4 * d*n2 per slot
+  VArg32 z32;     // FP32 preconditioned vector (velocity part, plus a copy of the pressure part)
   VArg vt;  // velocity temps: 4 * d*n2 per slot (b, three rotating iterates)
   VArg pt;  // pressure temps: 4*nv per slot (r, d0, d1, x)
 };
 void precond_apply(scvs_mesh m, const Batch& b, const PrecondArgs& pa, VArg v, VArg z, hipStream_t s);
+// y = A x with FP32 matrix copies, FP32 input and FP32 accumulation; FP64 output.
+void spmv_apply32(scvs_mesh m, const Batch& b, VArg32 x, VArg y, hipStream_t s);
+// FP32 copies of the matrix values for mixed-precision solves (made once per assembly).
+void make_fp32_copies(scvs_mesh m, hipStream_t s);
 // Gershgorin bound of diag^-1 (mu Ks + |w| rho M) on the free rows, per slot.
 void velocity_bounds(scvs_mesh m, const Batch& b, double* lv_out, hipStream_t s);
 

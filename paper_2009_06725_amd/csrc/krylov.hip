@@ -306,6 +306,23 @@ __global__ void __launch_bounds__(RBS) k_combine(KArgs a, VArg t) {
   }
 }
 
+// Mixed precision: x += z with the velocity part from the FP32 vector and the
+// pressure part from the FP64 Schur-block result.
+__global__ void k_axpy32(KArgs a, VArg x, VArg32 z, VArg zp, int64_t DN) {
+  const int slot = a.act[blockIdx.y];
+  double2* xs = x.at(slot);
+  const float2* zs = z.at(slot);
+  const double2* zps = zp.at(slot);
+  for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < a.ndof; n += (int64_t)gridDim.x * blockDim.x) {
+    if (n < DN) {
+      const float2 zv = zs[n];
+      xs[n] = make_double2(xs[n].x + (double)zv.x, xs[n].y + (double)zv.y);
+    } else {
+      xs[n] = cadd(xs[n], zps[n]);
+    }
+  }
+}
+
 __global__ void k_axpy(KArgs a, VArg x, VArg z) {
   const int slot = a.act[blockIdx.y];
   double2* xs = x.at(slot);
@@ -412,6 +429,7 @@ struct Pool {
   int slots = 0, m = 0, nch = 0;
   int64_t ld = 0, DN = 0, nv = 0;
   DBuf<double2> V, W, vt, pt, part, trac;
+  DBuf<float2> vt32, z32;
   DBuf<SlotState> st;
   DBuf<double> omega, lv, info;
   DBuf<int> act, act_all;
@@ -421,9 +439,9 @@ struct Pool {
   VArg T() const { return VArg{W.p + 3 * ld, 4 * ld}; }
 };
 
-size_t slot_bytes(int64_t ld, int m, int64_t DN, int64_t nv, int nch) {
-  return sizeof(double2) * ((size_t)(m + 1 + 4) * ld + 4 * DN + 4 * nv + (size_t)nch * PSTRIDE) +
-         sizeof(SlotState) + 64;
+size_t slot_bytes(int64_t ld, int m, int64_t DN, int64_t nv, int nch, bool mixed) {
+  return sizeof(double2) * ((size_t)(m + 1 + 4) * ld + (mixed ? 0 : 4 * DN) + 4 * nv + (size_t)nch * PSTRIDE) +
+         (mixed ? sizeof(float2) * (4 * DN + ld) : 0) + sizeof(SlotState) + 64;
 }
 
 int choose_nch(int nact, int64_t ndof) {
@@ -465,7 +483,10 @@ void run_cycle(scvs_mesh m, Pool& P, const Batch& b, const PrecondArgs& pa, int6
     VArg vj{Vv.p + (int64_t)j * P.ld, Vv.st};
     VArg vn{Vv.p + (int64_t)(j + 1) * P.ld, Vv.st};
     precond_apply(m, bj, pa, vj, P.Z(), s);
-    spmv_full(m, b, P.Z(), vn, SPMV_APPLY, false, VArg{}, nullptr, s);
+    if (pa.mixed)
+      spmv_apply32(m, b, pa.z32, vn, s);
+    else
+      spmv_full(m, b, P.Z(), vn, SPMV_APPLY, false, VArg{}, nullptr, s);
     {
       ProfScope ps(prof, s, "k_dots1", vec * (j + 2));  // V_0..V_j and w once
       k_dots<1><<<gr, RBS, 0, s>>>(a, j);
@@ -494,8 +515,11 @@ void run_cycle(scvs_mesh m, Pool& P, const Batch& b, const PrecondArgs& pa, int6
   }
   precond_apply(m, b, pa, P.T(), P.Z(), s);
   {
-    ProfScope ps(prof, s, "k_axpy", vec * 3);
-    k_axpy<<<dim3(256, nact), 256, 0, s>>>(a, P.X(), P.Z());
+    ProfScope ps(prof, s, "k_axpy", vec * (pa.mixed ? 2.5 : 3.0));
+    if (pa.mixed)
+      k_axpy32<<<dim3(256, nact), 256, 0, s>>>(a, P.X(), pa.z32, P.Z(), P.DN);
+    else
+      k_axpy<<<dim3(256, nact), 256, 0, s>>>(a, P.X(), P.Z());
   }
   spmv_full(m, b, P.X(), Vv, SPMV_RESID, true, P.F(), nullptr, s);
   {
@@ -555,7 +579,9 @@ int solve_systems(scvs_mesh m, int64_t nsys, const double* omega, const double* 
   size_t fr = 0, tot = 0;
   SCVS_HIP(hipMemGetInfo(&fr, &tot));
   const int nch_max = choose_nch(1, ndof);
-  const size_t per = slot_bytes(P.ld, mk, DN, m->nv, nch_max);
+  const bool mixed = o->precision == 1;
+  if (mixed) make_fp32_copies(m, s);
+  const size_t per = slot_bytes(P.ld, mk, DN, m->nv, nch_max, mixed);
   int64_t fit = (int64_t)((double)fr * 0.9 / (double)per);
   SCVS_REQUIRE(fit >= 1, SCVS_E_NOMEM, "not enough device memory for one system's Krylov workspace");
   int B = (int)std::min<int64_t>(nsys, fit);
@@ -563,7 +589,12 @@ int solve_systems(scvs_mesh m, int64_t nsys, const double* omega, const double* 
   P.slots = B;
   P.V.alloc((size_t)B * (mk + 1) * P.ld);
   P.W.alloc((size_t)B * 4 * P.ld);
-  P.vt.alloc((size_t)B * 4 * DN);
+  if (mixed) {
+    P.vt32.alloc((size_t)B * 4 * DN);
+    P.z32.alloc((size_t)B * P.ld);
+  } else {
+    P.vt.alloc((size_t)B * 4 * DN);
+  }
   P.pt.alloc((size_t)B * 4 * m->nv);
   P.part.alloc((size_t)B * nch_max * PSTRIDE);
   P.st.alloc(B);
@@ -578,6 +609,9 @@ int solve_systems(scvs_mesh m, int64_t nsys, const double* omega, const double* 
   pa.kp = o->cheb_pres;
   pa.ratio = o->cheb_ratio;
   pa.vt = VArg{P.vt.p, 4 * DN};
+  pa.mixed = mixed ? 1 : 0;
+  pa.vt32 = VArg32{P.vt32.p, 4 * DN};
+  pa.z32 = VArg32{P.z32.p, P.ld};
   pa.pt = VArg{P.pt.p, 4 * m->nv};
   std::vector<int> all(B);
   for (int k = 0; k < B; ++k) all[k] = k;

@@ -40,6 +40,7 @@ struct MeshArgs {
   const int64_t *rowptr, *rowptr21;
   const int32_t *col, *nvc, *dmask;
   const double *Ks, *M, *G, *Gt, *Kd, *Md, *Mp, *lpdinv;
+  const float *Ks32, *M32, *G32, *Gt32, *Kd32, *Md32;
   const int64_t* lp_ptr;
   const int32_t* lp_col;
   const double* lp_val;
@@ -66,6 +67,12 @@ MeshArgs mesh_args(scvs_mesh m) {
   a.Kd = m->Kd;
   a.Md = m->Md;
   a.Mp = m->Mp;
+  a.Ks32 = m->Ks32;
+  a.M32 = m->M32;
+  a.G32 = m->G32;
+  a.Gt32 = m->Gt32;
+  a.Kd32 = m->Kd32;
+  a.Md32 = m->Md32;
   a.lpdinv = m->lpdinv;
   a.lp_ptr = m->lp_ptr;
   a.lp_col = m->lp_col;
@@ -74,6 +81,40 @@ MeshArgs mesh_args(scvs_mesh m) {
   a.rho = m->rho;
   a.lpmax = m->lp_lmax;
   return a;
+}
+
+// Matrix values and complex vector element type per working precision.
+template <class R>
+struct Prec;
+template <>
+struct Prec<double> {
+  using C = double2;
+  using V = VArg;
+  __device__ static const double* Ks(const MeshArgs& a) { return a.Ks; }
+  __device__ static const double* M(const MeshArgs& a) { return a.M; }
+  __device__ static const double* G(const MeshArgs& a) { return a.G; }
+  __device__ static const double* Gt(const MeshArgs& a) { return a.Gt; }
+  __device__ static const double* Kd(const MeshArgs& a) { return a.Kd; }
+  __device__ static const double* Md(const MeshArgs& a) { return a.Md; }
+};
+template <>
+struct Prec<float> {
+  using C = float2;
+  using V = VArg32;
+  __device__ static const float* Ks(const MeshArgs& a) { return a.Ks32; }
+  __device__ static const float* M(const MeshArgs& a) { return a.M32; }
+  __device__ static const float* G(const MeshArgs& a) { return a.G32; }
+  __device__ static const float* Gt(const MeshArgs& a) { return a.Gt32; }
+  __device__ static const float* Kd(const MeshArgs& a) { return a.Kd32; }
+  __device__ static const float* Md(const MeshArgs& a) { return a.Md32; }
+};
+
+template <class C>
+__device__ __forceinline__ C czero() {
+  C z;
+  z.x = 0;
+  z.y = 0;
+  return z;
 }
 
 struct Lane {
@@ -100,9 +141,9 @@ __device__ __forceinline__ double in_scale(const Batch& b, int slot) {
 }
 
 // Sum over the D lanes of one system (lanes p = s*D + c are adjacent).
-template <int D>
-__device__ __forceinline__ double2 sum_components(double2 v) {
-  double2 r = v;
+template <int D, class C>
+__device__ __forceinline__ C sum_components(C v) {
+  C r = v;
 #pragma unroll
   for (int k = 1; k < D; ++k) {
     r.x += __shfl_down(v.x, k, 64);
@@ -116,25 +157,31 @@ __device__ __forceinline__ double2 sum_components(double2 v) {
 // group calls this together: the group first loads W slots of (col, Ks, M)
 // lane-parallel (coalesced), then broadcasts them by shuffles and issues eight
 // independent gathers at a time. With MASK, Dirichlet columns are skipped.
-template <int D, bool MASK>
+template <int D, bool MASK, class R>
 __device__ __forceinline__ void row_acc(const MeshArgs& ma, int W, int li, int64_t j0, int64_t j1,
-                                        const double2* __restrict__ xs, int c, bool pairok, double ar, double ai,
-                                        bool wantK, bool wantGt, double2& au, double2& ap) {
+                                        const typename Prec<R>::C* __restrict__ xs, int c, bool pairok, R ar, R ai,
+                                        bool wantK, bool wantGt, typename Prec<R>::C& au,
+                                        typename Prec<R>::C& ap) {
+  using C = typename Prec<R>::C;
   constexpr int U = 8;
+  const R* __restrict__ Ks = Prec<R>::Ks(ma);
+  const R* __restrict__ Mv = Prec<R>::M(ma);
+  const R* __restrict__ Gt = Prec<R>::Gt(ma);
+  const R mu = (R)ma.mu;
   for (int64_t jb = j0; jb < j1; jb += W) {
     const int n = (int)min((int64_t)W, j1 - jb);
     int32_t mc = 0;
-    double mk = 0.0, mm = 0.0;
+    R mk = 0, mm = 0;
     if (li < n) {
       mc = ma.col[jb + li];
-      mk = ma.Ks[jb + li];
-      mm = ma.M[jb + li];
+      mk = Ks[jb + li];
+      mm = Mv[jb + li];
       if (MASK && ma.dmask[mc] != 0) mc = -1;
     }
     for (int t = 0; t < n; t += U) {
       int32_t B[U];
-      double k[U], m[U];
-      double2 xv[U];
+      R k[U], m[U];
+      C xv[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         B[u] = __shfl(mc, t + u < n ? t + u : 0, W);
@@ -143,16 +190,16 @@ __device__ __forceinline__ void row_acc(const MeshArgs& ma, int W, int li, int64
       }
 #pragma unroll
       for (int u = 0; u < U; ++u)
-        xv[u] = (pairok && t + u < n && B[u] >= 0) ? xs[(int64_t)B[u] * D + c] : make_double2(0.0, 0.0);
+        xv[u] = (pairok && t + u < n && B[u] >= 0) ? xs[(int64_t)B[u] * D + c] : czero<C>();
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         if (wantK) {
-          const double kr = ma.mu * k[u] + ar * m[u], ki = ai * m[u];
+          const R kr = mu * k[u] + ar * m[u], ki = ai * m[u];
           au.x += kr * xv[u].x - ki * xv[u].y;
           au.y += kr * xv[u].y + ki * xv[u].x;
         }
         if (wantGt && pairok && t + u < n) {
-          const double g = ma.Gt[(int64_t)c * ma.nnzv + jb + t + u];
+          const R g = Gt[(int64_t)c * ma.nnzv + jb + t + u];
           ap.x += g * xv[u].x;
           ap.y += g * xv[u].y;
         }
@@ -161,18 +208,19 @@ __device__ __forceinline__ void row_acc(const MeshArgs& ma, int W, int li, int64
   }
 }
 
-// acc += s * sum_{jj < nvc} G^c[row prefix] p[col] over the vertex-column prefix of a row.
-template <int D>
-__device__ __forceinline__ void g_acc(const MeshArgs& ma, int64_t A, int64_t j0, const double2* __restrict__ p,
-                                      int c, double s, double2& acc) {
+// acc += s * sum_{jj < nvc} G^c[row prefix] p[col] over the vertex-column prefix of a row
+// (G in precision R, pressure values of complex type P, accumulation in R).
+template <int D, class R, class P>
+__device__ __forceinline__ void g_acc(const MeshArgs& ma, int64_t A, int64_t j0, const P* __restrict__ p, int c,
+                                      R s, typename Prec<R>::C& acc) {
   const int nvr = ma.nvc[A];
-  const double* __restrict__ Gc = ma.G + (int64_t)c * ma.nnz21 + ma.rowptr21[A];
+  const R* __restrict__ Gc = Prec<R>::G(ma) + (int64_t)c * ma.nnz21 + ma.rowptr21[A];
   const int32_t* __restrict__ cl = ma.col + j0;
   int jj = 0;
   for (; jj + 4 <= nvr; jj += 4) {
     int32_t B[4];
-    double g[4];
-    double2 pv[4];
+    R g[4];
+    P pv[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) B[u] = cl[jj + u];
 #pragma unroll
@@ -182,21 +230,22 @@ __device__ __forceinline__ void g_acc(const MeshArgs& ma, int64_t A, int64_t j0,
     }
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      acc.x += s * g[u] * pv[u].x;
-      acc.y += s * g[u] * pv[u].y;
+      acc.x += s * g[u] * (R)pv[u].x;
+      acc.y += s * g[u] * (R)pv[u].y;
     }
   }
   for (; jj < nvr; ++jj) {
-    const double2 pv = p[cl[jj]];
-    acc.x += s * Gc[jj] * pv.x;
-    acc.y += s * Gc[jj] * pv.y;
+    const P pv = p[cl[jj]];
+    acc.x += s * Gc[jj] * (R)pv.x;
+    acc.y += s * Gc[jj] * (R)pv.y;
   }
 }
 
-template <int D, int MODE, bool MASK>
-__global__ void __launch_bounds__(256) k_full(MeshArgs ma, Batch b, LaneMap lm, VArg x, VArg y, VArg f,
-                                              const double* __restrict__ loads, int ntr,
+template <int D, int MODE, bool MASK, class R>
+__global__ void __launch_bounds__(256) k_full(MeshArgs ma, Batch b, LaneMap lm, typename Prec<R>::V x, VArg y,
+                                              VArg f, const double* __restrict__ loads, int ntr,
                                               const double2* __restrict__ trac) {
+  using C = typename Prec<R>::C;
   const Lane L = lane_of(lm, ma.n2);
   if (!L.rowok) return;  // uniform over the row group
   const int64_t A = L.row;
@@ -209,24 +258,24 @@ __global__ void __launch_bounds__(256) k_full(MeshArgs ma, Batch b, LaneMap lm, 
     const int si = ok ? p / D : 0, c = ok ? p % D : 0;
     const int slot = b.act[si];
     const double sc = in_scale(b, slot);
-    const double2* __restrict__ xs = x.at(slot);
-    const double wr = b.omega[slot] * ma.rho;
-    double2 au = make_double2(0.0, 0.0), ap = make_double2(0.0, 0.0);
-    if (dm == 0 || isv) row_acc<D, MASK>(ma, lm.W, L.li, j0, j1, xs, c, ok, 0.0, wr, dm == 0, isv, au, ap);
+    const C* __restrict__ xs = x.at(slot);
+    const R wr = (R)(b.omega[slot] * ma.rho);
+    C au = czero<C>(), ap = czero<C>();
+    if (dm == 0 || isv) row_acc<D, MASK, R>(ma, lm.W, L.li, j0, j1, xs, c, ok, (R)0, wr, dm == 0, isv, au, ap);
     if (ok) {
-      if (dm == 0) g_acc<D>(ma, A, j0, xs + D * ma.n2, c, 1.0, au);
+      if (dm == 0) g_acc<D, R, C>(ma, A, j0, xs + D * ma.n2, c, (R)1, au);
       double2 yu;
       if (dm != 0) {
-        yu = cscale(xs[A * D + c], sc);
+        yu = make_double2(sc * (double)xs[A * D + c].x, sc * (double)xs[A * D + c].y);
         if (MODE == SPMV_RESID) yu = csub(f.at(slot)[A * D + c], yu);
       } else {
-        au = cscale(au, sc);
+        const double2 a = make_double2(sc * (double)au.x, sc * (double)au.y);
         if (MODE == SPMV_APPLY) {
-          yu = au;
+          yu = a;
         } else if (MODE == SPMV_RESID) {
-          yu = csub(f.at(slot)[A * D + c], au);
+          yu = csub(f.at(slot)[A * D + c], a);
         } else {
-          yu = make_double2(-au.x, -au.y);
+          yu = make_double2(-a.x, -a.y);
           for (int t = 0; t < ntr; ++t) {
             const double2 P = trac[(int64_t)slot * ntr + t];
             const double ld = loads[((int64_t)t * ma.n2 + A) * D + c];
@@ -238,9 +287,9 @@ __global__ void __launch_bounds__(256) k_full(MeshArgs ma, Batch b, LaneMap lm, 
       y.at(slot)[A * D + c] = yu;
     }
     if (isv) {
-      const double2 ps = sum_components<D>(ap);
+      const C ps = sum_components<D, C>(ap);
       if (ok && c == 0) {
-        double2 yp = cscale(ps, sc);
+        double2 yp = make_double2(sc * (double)ps.x, sc * (double)ps.y);
         if (MODE == SPMV_RESID) yp = csub(f.at(slot)[D * ma.n2 + A], yp);
         if (MODE == SPMV_RHS) yp = make_double2(-yp.x, -yp.y);
         y.at(slot)[D * ma.n2 + A] = yp;
@@ -272,13 +321,17 @@ __device__ __forceinline__ void cheb_coef(double lmax, double ratio, int i, doub
 //   x_{k+1} = x_k + rho_k rho_{k-1} (x_k - x_{k-1}) + (2 rho_k / delta) diag^-1 (b - A_r x_k),
 // with b = insc*v_u - G zhat_p. Temps per slot: b, x_a, x_b, x_c (d*n2 each);
 // the last iterate is written into z. Dirichlet rows stay zero.
-__device__ __forceinline__ double2* vbuf(const VArg& vt, int slot, int64_t DN, int k) {
+template <class C, class V>
+__device__ __forceinline__ C* vbuf(const V& vt, int slot, int64_t DN, int k) {
   return vt.at(slot) + DN * (1 + (k % 3));
 }
 
-template <int D>
-__global__ void __launch_bounds__(256) k_vinit(MeshArgs ma, Batch b, LaneMap lm, VArg v, VArg z, VArg vt,
-                                               double ratio, int kv) {
+// In FP32 mode the output z is the FP32 vector z32 (velocity part written
+// here, pressure part copied from the FP64 Schur-block result zp).
+template <int D, class R>
+__global__ void __launch_bounds__(256) k_vinit(MeshArgs ma, Batch b, LaneMap lm, VArg v, VArg zp64,
+                                               typename Prec<R>::V z, typename Prec<R>::V vt, double ratio, int kv) {
+  using C = typename Prec<R>::C;
   const Lane L = lane_of(lm, ma.n2);
   for (int it = 0; it < lm.iters; ++it) {
     const int p = L.li + it * lm.UL;
@@ -286,28 +339,42 @@ __global__ void __launch_bounds__(256) k_vinit(MeshArgs ma, Batch b, LaneMap lm,
     const int si = p / D, c = p % D;
     const int slot = b.act[si];
     const int64_t A = L.row, DN = D * ma.n2;
-    double2* __restrict__ bb = vt.at(slot);
-    double2* __restrict__ x1 = (kv == 1) ? z.at(slot) : vbuf(vt, slot, DN, 1);
-    double2* __restrict__ zs = z.at(slot);
+    C* __restrict__ bb = vt.at(slot);
+    C* __restrict__ x1 = (kv == 1) ? z.at(slot) : vbuf<C>(vt, slot, DN, 1);
+    const double2* __restrict__ zp = zp64.at(slot) + DN;
     const int64_t k = A * D + c;
+    if (sizeof(R) == 4 && A < ma.nv && c == 0) {
+      const double2 q = zp[A];
+      C qq;
+      qq.x = (R)q.x;
+      qq.y = (R)q.y;
+      z.at(slot)[DN + A] = qq;
+    }
     if (ma.dmask[A] != 0) {
-      bb[k] = x1[k] = make_double2(0.0, 0.0);
+      bb[k] = x1[k] = czero<C>();
       continue;
     }
     const double sc = in_scale(b, slot);
-    double2 t = cscale(v.at(slot)[k], sc);
-    g_acc<D>(ma, A, ma.rowptr[A], zs + DN, c, -1.0, t);
+    const double2 vv = v.at(slot)[k];
+    C t;
+    t.x = (R)(sc * vv.x);
+    t.y = (R)(sc * vv.y);
+    g_acc<D, R, double2>(ma, A, ma.rowptr[A], zp, c, (R)-1, t);
     const double lmax = b.lv[slot];
-    const double theta = 0.5 * lmax * (1.0 + 1.0 / ratio);
-    const double dinv = 1.0 / (ma.mu * ma.Kd[A] + fabs(b.omega[slot]) * ma.rho * ma.Md[A]);
+    const R theta = (R)(0.5 * lmax * (1.0 + 1.0 / ratio));
+    const R dinv = (R)1 / ((R)ma.mu * Prec<R>::Kd(ma)[A] + (R)(fabs(b.omega[slot]) * ma.rho) * Prec<R>::Md(ma)[A]);
     bb[k] = t;
-    x1[k] = cscale(t, dinv / theta);
+    C xv;
+    xv.x = t.x * (dinv / theta);
+    xv.y = t.y * (dinv / theta);
+    x1[k] = xv;
   }
 }
 
-template <int D>
-__global__ void __launch_bounds__(256) k_vstep(MeshArgs ma, Batch b, LaneMap lm, VArg z, VArg vt, double ratio,
-                                               int step, int last) {
+template <int D, class R>
+__global__ void __launch_bounds__(256) k_vstep(MeshArgs ma, Batch b, LaneMap lm, typename Prec<R>::V z,
+                                               typename Prec<R>::V vt, double ratio, int step, int last) {
+  using C = typename Prec<R>::C;
   const Lane L = lane_of(lm, ma.n2);
   if (!L.rowok) return;  // uniform over the row group
   const int64_t A = L.row, DN = D * ma.n2;
@@ -318,27 +385,29 @@ __global__ void __launch_bounds__(256) k_vstep(MeshArgs ma, Batch b, LaneMap lm,
     const bool ok = L.pairok0 && p < lm.G;
     const int si = ok ? p / D : 0, c = ok ? p % D : 0;
     const int slot = b.act[si];
-    const double2* __restrict__ xk = vbuf(vt, slot, DN, step);
-    double2* __restrict__ xn = last ? z.at(slot) : vbuf(vt, slot, DN, step + 1);
+    const C* __restrict__ xk = vbuf<C>(vt, slot, DN, step);
+    C* __restrict__ xn = last ? z.at(slot) : vbuf<C>(vt, slot, DN, step + 1);
     const int64_t k = A * D + c;
     if (dir) {
-      if (ok) xn[k] = make_double2(0.0, 0.0);
+      if (ok) xn[k] = czero<C>();
       continue;
     }
-    const double wr = fabs(b.omega[slot]) * ma.rho;
-    double2 q = make_double2(0.0, 0.0), unused = make_double2(0.0, 0.0);
-    row_acc<D, false>(ma, lm.W, L.li, j0, j1, xk, c, ok, wr, 0.0, true, false, q, unused);
+    const R wr = (R)(fabs(b.omega[slot]) * ma.rho);
+    C q = czero<C>(), unused = czero<C>();
+    row_acc<D, false, R>(ma, lm.W, L.li, j0, j1, xk, c, ok, wr, (R)0, true, false, q, unused);
     if (!ok) continue;
-    const double2* __restrict__ bb = vt.at(slot);
-    const double2* __restrict__ xm = vbuf(vt, slot, DN, step - 1);
+    const C* __restrict__ bb = vt.at(slot);
+    const C* __restrict__ xm = vbuf<C>(vt, slot, DN, step - 1);
     double rp, rc, delta, theta;
     cheb_coef(b.lv[slot], ratio, step, rp, rc, delta, theta);
-    const double dinv = 1.0 / (ma.mu * ma.Kd[A] + wr * ma.Md[A]);
-    const double2 rk = csub(bb[k], q);
-    const double2 xv = xk[k];
-    const double2 xo = (step == 1) ? make_double2(0.0, 0.0) : xm[k];
-    const double ca = rc * rp, cb = 2.0 * rc / delta * dinv;
-    xn[k] = make_double2(xv.x + ca * (xv.x - xo.x) + cb * rk.x, xv.y + ca * (xv.y - xo.y) + cb * rk.y);
+    const R dinv = (R)1 / ((R)ma.mu * Prec<R>::Kd(ma)[A] + wr * Prec<R>::Md(ma)[A]);
+    const C bv = bb[k], xv = xk[k];
+    const C xo = (step == 1) ? czero<C>() : xm[k];
+    const R ca = (R)(rc * rp), cb = (R)(2.0 * rc / delta) * dinv;
+    C o;
+    o.x = xv.x + ca * (xv.x - xo.x) + cb * (bv.x - q.x);
+    o.y = xv.y + ca * (xv.y - xo.y) + cb * (bv.y - q.y);
+    xn[k] = o;
   }
 }
 
@@ -473,13 +542,26 @@ void full_launch(Profiler* prof, const MeshArgs& ma, const Batch& b, VArg x, VAr
   const char* nm = mode == SPMV_APPLY ? "k_full_apply" : (mode == SPMV_RESID ? "k_full_resid" : "k_full_rhs");
   ProfScope ps(prof, s, nm, full_bytes(ma, D, b.nact, mode));
   if (mode == SPMV_APPLY && mask)
-    k_full<D, SPMV_APPLY, true><<<nb, 256, 0, s>>>(ma, b, lm, x, y, f, loads, ntr, trac);
+    k_full<D, SPMV_APPLY, true, double><<<nb, 256, 0, s>>>(ma, b, lm, x, y, f, loads, ntr, trac);
   else if (mode == SPMV_APPLY)
-    k_full<D, SPMV_APPLY, false><<<nb, 256, 0, s>>>(ma, b, lm, x, y, f, loads, ntr, trac);
+    k_full<D, SPMV_APPLY, false, double><<<nb, 256, 0, s>>>(ma, b, lm, x, y, f, loads, ntr, trac);
   else if (mode == SPMV_RESID)
-    k_full<D, SPMV_RESID, true><<<nb, 256, 0, s>>>(ma, b, lm, x, y, f, loads, ntr, trac);
+    k_full<D, SPMV_RESID, true, double><<<nb, 256, 0, s>>>(ma, b, lm, x, y, f, loads, ntr, trac);
   else
-    k_full<D, SPMV_RHS, false><<<nb, 256, 0, s>>>(ma, b, lm, x, y, f, loads, ntr, trac);
+    k_full<D, SPMV_RHS, false, double><<<nb, 256, 0, s>>>(ma, b, lm, x, y, f, loads, ntr, trac);
+  launch_check(s);
+}
+
+template <int D>
+void full_launch32(Profiler* prof, const MeshArgs& ma, const Batch& b, VArg32 x, VArg y, hipStream_t s) {
+  const LaneMap lm = lane_map(b.nact, D);
+  const unsigned nb = row_blocks(ma.n2, lm);
+  // FP32 matrix values (col int32, values float), FP32 input, FP64 output
+  const double mat = (double)ma.nnz * 12.0 + (double)ma.nnz21 * (4.0 + 4.0 * D) + (double)ma.nnzv * 4.0 * D +
+                     (double)ma.n2 * 24.0;
+  const double ndof = (double)D * ma.n2 + ma.nv;
+  ProfScope ps(prof, s, "k_full_apply32", mat + b.nact * ndof * (8.0 + 16.0));
+  k_full<D, SPMV_APPLY, false, float><<<nb, 256, 0, s>>>(ma, b, lm, x, y, VArg{}, nullptr, 0, nullptr);
   launch_check(s);
 }
 
@@ -502,19 +584,33 @@ void precond_launch(Profiler* prof, const MeshArgs& ma, const Batch& b, const Pr
     ProfScope ps(prof, s, "k_pstep", pbytes + (i == pa.kp - 1 ? na * nv * 32.0 : 0.0));
     k_pstep<<<nbp, 256, 0, s>>>(ma, D, b, lp, v, z, pa.pt, pa.ratio, i, i == pa.kp - 1);
   }
+  const double es = pa.mixed ? 8.0 : 16.0, vs = pa.mixed ? 4.0 : 8.0;  // complex / real element bytes
   {
-    // vertex-column prefix (col + G), row arrays; per system v_u read, z_p read, b and x_1 written
-    ProfScope ps(prof, s, "k_vinit",
-                 (double)ma.nnz21 * (4.0 + 8.0 * D) + n2 * 40.0 + na * (3.0 * DN + nv) * 16.0);
-    k_vinit<D><<<nbu, 256, 0, s>>>(ma, b, lm, v, z, pa.vt, pa.ratio, pa.kv);
+    // vertex-column prefix (col + G), row arrays; per system v_u read (FP64), z_p read (FP64),
+    // b and x_1 written (and the FP32 copy of z_p in mixed mode)
+    ProfScope ps(prof, s, pa.mixed ? "k_vinit32" : "k_vinit",
+                 (double)ma.nnz21 * (4.0 + vs * D) + n2 * (24.0 + 2.0 * vs) +
+                     na * (DN * 16.0 + nv * 16.0 + 2.0 * DN * es + (pa.mixed ? nv * es : 0.0)));
+    if (pa.mixed)
+      k_vinit<D, float><<<nbu, 256, 0, s>>>(ma, b, lm, v, z, pa.z32, pa.vt32, pa.ratio, pa.kv);
+    else
+      k_vinit<D, double><<<nbu, 256, 0, s>>>(ma, b, lm, v, z, z, pa.vt, pa.ratio, pa.kv);
   }
   // S2 col/Ks/M, rowptr/dmask/Kd/Md; per system x_k (gathered, read once), b, x_{k-1} read, x_{k+1} written
-  const double vbytes = (double)ma.nnz * 20.0 + n2 * 28.0 + na * 4.0 * DN * 16.0;
+  const double vbytes = (double)ma.nnz * (4.0 + 2.0 * vs) + n2 * (12.0 + 2.0 * vs) + na * 4.0 * DN * es;
   for (int i = 1; i < pa.kv; ++i) {
-    ProfScope ps(prof, s, "k_vstep", vbytes);
-    k_vstep<D><<<nbu, 256, 0, s>>>(ma, b, lm, z, pa.vt, pa.ratio, i, i == pa.kv - 1);
+    ProfScope ps(prof, s, pa.mixed ? "k_vstep32" : "k_vstep", vbytes);
+    if (pa.mixed)
+      k_vstep<D, float><<<nbu, 256, 0, s>>>(ma, b, lm, pa.z32, pa.vt32, pa.ratio, i, i == pa.kv - 1);
+    else
+      k_vstep<D, double><<<nbu, 256, 0, s>>>(ma, b, lm, z, pa.vt, pa.ratio, i, i == pa.kv - 1);
   }
   launch_check(s);
+}
+
+__global__ void k_to_f32(const double* __restrict__ a, float* __restrict__ b, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    b[i] = (float)a[i];
 }
 
 }  // namespace
@@ -535,6 +631,32 @@ void precond_apply(scvs_mesh m, const Batch& b, const PrecondArgs& pa, VArg v, V
     precond_launch<2>(&m->ctx->prof, ma, b, pa, v, z, s);
   else
     precond_launch<3>(&m->ctx->prof, ma, b, pa, v, z, s);
+}
+
+void spmv_apply32(scvs_mesh m, const Batch& b, VArg32 x, VArg y, hipStream_t s) {
+  const MeshArgs ma = mesh_args(m);
+  if (m->dim == 2)
+    full_launch32<2>(&m->ctx->prof, ma, b, x, y, s);
+  else
+    full_launch32<3>(&m->ctx->prof, ma, b, x, y, s);
+}
+
+void make_fp32_copies(scvs_mesh m, hipStream_t s) {
+  if (m->fp32_ready) return;
+  const int D = m->dim;
+  auto conv = [&](const DBuf<double>& a, DBuf<float>& b, size_t n) {
+    b.alloc(n);
+    k_to_f32<<<1024, 256, 0, s>>>(a.p, b.p, (int64_t)n);
+    launch_check(s);
+  };
+  conv(m->Ks, m->Ks32, m->nnz);
+  conv(m->M, m->M32, m->nnz);
+  conv(m->G, m->G32, (size_t)D * m->nnz21);
+  conv(m->Gt, m->Gt32, (size_t)D * m->nnzv);
+  conv(m->Kd, m->Kd32, m->n2);
+  conv(m->Md, m->Md32, m->n2);
+  SCVS_HIP(hipStreamSynchronize(s));
+  m->fp32_ready = true;
 }
 
 void velocity_bounds(scvs_mesh m, const Batch& b, double* lv_out, hipStream_t s) {

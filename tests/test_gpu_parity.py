@@ -205,3 +205,21 @@ def test_validation_errors(ctx):
         m.solve(np.zeros(1), np.zeros((1, 1)))
     with pytest.raises(scvs.ScvsError):
         m.set_bc({1: 7})
+
+
+def test_solve_mixed_matches_lu(setup):
+    """FP32 operator and velocity polynomial inside FP64 refinement: modes
+    within 1e-8 (relative L2) of the LU solution."""
+    from paper_2009_06725_amd import scvs
+    c, asm, m = setup["case"], setup["asm"], setup["m"]
+    u_o, p_o, _, _ = solve_modes(asm, setup["loads"], setup["wall"], setup["dirn"], c["omega"], c["rho"],
+                                 c["mu"], c["traction"], setup["g"])
+    g = gpu_dirichlet(m, c, torch)
+    opts = scvs.default_opts(rtol=1e-12, precision=1)
+    u, p, rep = m.solve(c["omega"], c["traction"], g, opts=opts)
+    u, p = u.cpu().numpy(), p.cpu().numpy()
+    print("[gpu]", setup["name"], "mixed iterations", [r.iterations for r in rep], flush=True)
+    for s in range(len(c["omega"])):
+        assert rep[s].status == 0, (s, rep[s].status, rep[s].rel_residual)
+        eu, ep = rel_l2(asm, u[s], u_o[s], p[s], p_o[s])
+        assert eu <= 1e-8 and ep <= 1e-8, (s, eu, ep)
