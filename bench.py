@@ -47,6 +47,9 @@ def parse():
     ap.add_argument("--cheb-vel", type=int, default=10)
     ap.add_argument("--cheb-pres", type=int, default=20)
     ap.add_argument("--ntimes", type=int, default=64)
+    ap.add_argument("--precision", choices=["fp64", "mixed"], default="mixed")
+    ap.add_argument("--no-compare", action="store_true",
+                    help="skip the plain per-mode FP64 GMRES comparator step")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--verbose", action="store_true")
     return ap.parse_args()
@@ -128,7 +131,8 @@ def main():
     ut = torch.empty((args.ntimes, info.n2 * 3), dtype=torch.float64, device="cuda")
     pt = torch.empty((args.ntimes, info.nv), dtype=torch.float64, device="cuda")
     opts = scvs.default_opts(rtol=args.rtol, restart=args.restart, cheb_vel=args.cheb_vel,
-                             cheb_pres=args.cheb_pres, verbose=1 if args.verbose else 0)
+                             cheb_pres=args.cheb_pres, verbose=1 if args.verbose else 0,
+                             precision=1 if args.precision == "mixed" else 0)
     log(f"n2={info.n2} ndof={info.ndof} nnz_s2={info.nnz_s2} ingest+assembly {t_ingest:.2f}s")
 
     def step():
@@ -185,18 +189,39 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "c128",
+        "dtype": "c128" if args.precision == "fp64" else "c64 operator+velocity precond / c128 refinement",
         "data": "synthetic",
         "config": {"workload": f"pipe R=1 L=10, {mesh.nc} curved P2/P1 tets, {ns} modes (16 harmonics + mean)",
                    "ndof": int(info.ndof), "modes": ns, "rtol": args.rtol, "restart": args.restart,
                    "cheb_vel": args.cheb_vel, "cheb_pres": args.cheb_pres, "ntimes": args.ntimes},
         "dof_modes_per_s": info.ndof * ns * args.steps / dt,
         "roofline": roof(dominant),
-        "spmv_roofline": roof("k_full_apply"),
+        "spmv_roofline": roof("k_full_apply32" if "k_full_apply32" in stats else "k_full_apply"),
         "converged": conv,
         "iterations": iters,
         "kernels": kernels,
     }
+    if not args.no_compare:
+        # comparator: plain per-mode FP64 GMRES (one system at a time, same
+        # preconditioner, restart and tolerance, no graph batching)
+        plain = scvs.default_opts(rtol=args.rtol, restart=args.restart, cheb_vel=args.cheb_vel,
+                                  cheb_pres=args.cheb_pres, precision=0, max_batch=1,
+                                  verbose=1 if args.verbose else 0)
+        u2 = torch.empty_like(u)
+        p2 = torch.empty_like(p)
+        log("comparator: plain per-mode FP64 GMRES ...")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, _, rep2 = m.solve(case["omega"], case["traction"], g, u=u2, p=p2, opts=plain)
+        torch.cuda.synchronize()
+        dtp = time.perf_counter() - t0
+        du = torch.linalg.vector_norm(u - u2) / torch.linalg.vector_norm(u2)
+        dp = torch.linalg.vector_norm(p - p2) / torch.linalg.vector_norm(p2)
+        out["plain_fp64_per_mode"] = {"mode_solves_per_s": ns / dtp, "seconds": dtp,
+                                      "iterations": [r.iterations for r in rep2],
+                                      "converged": all(r.status == 0 for r in rep2)}
+        out["speedup_vs_plain_fp64"] = (ns / dtp and out["value"] / (ns / dtp))
+        out["rel_diff_vs_plain_fp64"] = {"u": float(du), "p": float(dp)}
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(h, int(info.ndof))

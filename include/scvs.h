@@ -197,6 +197,7 @@ typedef struct {
   int32_t iterations;   /* Arnoldi steps */
   int32_t restarts;     /* completed cycles */
   double rel_residual;  /* final ||f - A x|| / ||f|| */
+  int32_t warm;         /* 1 if the supplied x0 was kept, 0 if zero guess (none given or fallback) */
 } scvs_report;
 
 /* Solve nsys mode systems on one mesh (section 2.4, step 3).
@@ -220,6 +221,60 @@ int scvs_solve(scvs_mesh mesh, int64_t nsys, const double* omega, const double* 
 int scvs_synthesize(scvs_ctx ctx, int64_t nk, const double* omega, const void* modes,
                     int64_t nvals, int64_t nt, const double* times, void* out);
 
+/* ---- a9: learned warm start (no counterpart in the paper) ----
+ * A model built from the method's own solutions: POD of `nsnap` snapshot
+ * systems (device c128 [nsnap][ndof], each the solution for a unit-amplitude
+ * boundary datum at frequency omega[s]), truncated to `rank` <= nsnap <= 128
+ * modes, and an MLP with `layers` layers of width `width` (tanh hidden
+ * layers) from the features (w, sqrt w, w^2) of w = omega/max|omega| to the
+ * rank complex POD coefficients. With the Gram eigenpairs (sigma_i^2, W_i)
+ * of the snapshots, snapshot s equals sum_i sigma_i conj(W_si) phi_i; the
+ * network's targets are t_si = sigma_i conj(W_si) / sigma_0 (real parts, then
+ * imaginary parts), so the squared error weighs each coefficient by its
+ * share of the solution. Matrix products of the MLP run on BF16 matrix cores
+ * with FP32 accumulation and FP32 master weights. The model keeps its own
+ * copy of the basis.
+ *   scvs_ws_train    epochs of full-batch Adam (lr; beta 0.9/0.999, eps 1e-8);
+ *                    *loss = mean-squared error before the last epoch's update
+ *                    (epochs == 0: the current loss, no update)
+ *   scvs_ws_predict  x0[s] = amp[s] sigma_0 sum_i t_i(omega[s]) phi_i   (device c128 [n][ndof])
+ * Pass the predictions as x0 to scvs_solve; it falls back to the zero guess
+ * for any system whose initial residual is not below ||f||.
+ *   scvs_ws_refine   optional correction of guesses x0 (device c128 [n][ndof],
+ *                    updated in place): x0 += Phi d, d minimizing
+ *                    ||f - A(omega)(x0 + Phi d)|| over unconstrained rows, with
+ *                    f built from (traction, g) exactly as scvs_solve builds it.
+ *                    A(omega) Phi is affine in omega, so A(0) Phi and its slope
+ *                    (2*rank*ndof complex values) are formed on the first call
+ *                    after each assembly or boundary-condition change; each
+ *                    call then costs one residual, one projection and a host
+ *                    rank x rank solve per system. The result is the best
+ *                    residual in x0 + span(Phi), whatever the network said. */
+typedef struct scvs_ws_s* scvs_ws;
+int scvs_ws_create(scvs_mesh mesh, int64_t nsnap, const double* omega, const void* snaps, int rank,
+                   int width, int layers, uint64_t seed, scvs_ws* out);
+int scvs_ws_train(scvs_ws ws, int epochs, double lr, double* loss);
+int scvs_ws_predict(scvs_ws ws, int64_t n, const double* omega, const double* amp, void* x0);
+int scvs_ws_refine(scvs_ws ws, int64_t n, const double* omega, const double* traction, const void* g,
+                   void* x0);
+int scvs_ws_destroy(scvs_ws ws);
+/* Test/inspection hooks (host buffers unless stated):
+ *  SCVS_WS_SIGMA double[rank]; SCVS_WS_BASIS device c128[rank][ndof];
+ *  SCVS_WS_PARAMS float[nparam] (per layer W [out][in] row-major, then b);
+ *  SCVS_WS_TARGETS float[nsnap][2*rank]; SCVS_WS_NPARAM int64 */
+#define SCVS_WS_SIGMA 0
+#define SCVS_WS_BASIS 1
+#define SCVS_WS_PARAMS 2
+#define SCVS_WS_TARGETS 3
+#define SCVS_WS_NPARAM 4
+int scvs_ws_export(scvs_ws ws, int which, void* out);
+int scvs_ws_set_params(scvs_ws ws, const float* params);
+/* Loss and gradients of the MLP on given inputs x[n][3] and targets t[n][2*rank] (host). */
+int scvs_ws_loss_grad(scvs_ws ws, int64_t n, const float* x, const float* t, double* loss, float* grads);
+/* Host eigen-decomposition used by the POD (complex Hermitian, cyclic Jacobi):
+ * a c128[n][n] -> w double[n] descending, v c128[n][n] (columns). Needs no GPU. */
+int scvs_herm_eig(int n, const double* a, double* w, double* v);
+
 /* ---- measurement ----
  * When profiling is on, solves run without graph replay and every kernel
  * launch is bracketed by HIP events recorded on the context stream (the
@@ -242,6 +297,9 @@ int scvs_profile_read(scvs_ctx ctx, int max, scvs_kernel_stat* out, int* n);
  * B[k][j] = b[k*16+j] (host double[64] each) and returns D = A B (host
  * double[256], row-major) as laid out by the library's lane mapping. */
 int scvs_probe_mfma(scvs_ctx ctx, const double* a, const double* b, double* d);
+/* Same for one BF16 16x16x16 instruction (operands rounded to bfloat16, FP32
+ * accumulate): a float[16][16], b float[16][16], d float[16][16]. */
+int scvs_probe_mfma_bf16(scvs_ctx ctx, const float* a, const float* b, float* d);
 
 #ifdef __cplusplus
 }

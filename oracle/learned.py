@@ -14,6 +14,9 @@ mapping frequency features to POD coefficients.
   inputs rounded to bfloat16 (round to nearest even) and accumulates in
   float32; this reference rounds the same operands to bfloat16 and evaluates
   in float64.
+* Backward: the same rounding applies to both operands of every product
+  (the output-gradient signal and the weights or activations); the bias
+  gradient is a plain column sum.
 * Loss: mean squared error over all outputs; Adam updates the float32 master
   weights (Kingma & Ba 2015, with bias correction).
 
@@ -62,10 +65,12 @@ def mse_loss_grad(params, x, t, bf16=True):
         hin, Wr, z = cache[l]
         if l < L - 1:
             g = g * (1.0 - np.tanh(z) ** 2)
-        gW = g.T @ hin
+        # every matrix product rounds both operands to bfloat16 on the device
+        gq = bf16_round(g.astype(np.float32)) if bf16 else g
+        gW = gq.T @ hin
         gb = g.sum(0)
         grads[l] = (gW, gb)
-        g = g @ Wr
+        g = gq @ Wr
     return loss, grads
 
 

@@ -180,6 +180,7 @@ int scvs_mesh_set_bc(scvs_mesh m, int n, const int32_t* tags, const int32_t* kin
     m->bc_tags.assign(tags, tags + n);
     m->bc_kinds.assign(kinds, kinds + n);
     scvs::mesh_boundary(m, m->ctx->stream);
+    m->generation++;
     if (m->assembled) scvs::mesh_precond_setup(m, m->ctx->stream);
   });
 }
@@ -195,6 +196,7 @@ int scvs_assemble(scvs_mesh m, double rho, double mu) {
     m->mu = mu;
     m->assembled = true;
     m->fp32_ready = false;
+    m->generation++;
     if (m->bc_set) scvs::mesh_precond_setup(m, m->ctx->stream);
   });
 }
@@ -317,6 +319,115 @@ int scvs_synthesize(scvs_ctx ctx, int64_t nk, const double* omega, const void* m
     for (int64_t n = 0; n < nt; ++n) SCVS_REQUIRE(std::isfinite(times[n]), SCVS_E_INVALID, "non-finite time");
     use_device(ctx);
     scvs::synthesize(ctx->stream, nk, omega, (const double2*)modes, nvals, nt, times, (double*)out);
+  });
+}
+
+int scvs_ws_create(scvs_mesh mesh, int64_t nsnap, const double* omega, const void* snaps, int rank, int width,
+                   int layers, uint64_t seed, scvs_ws* out) {
+  return guarded([&] {
+    SCVS_REQUIRE(mesh && omega && snaps && out, SCVS_E_INVALID, "null warm-start argument");
+    SCVS_REQUIRE(nsnap >= 1 && nsnap <= 128, SCVS_E_INVALID, "nsnap must be in 1..128");
+    SCVS_REQUIRE(rank >= 1 && rank <= nsnap && rank <= 64, SCVS_E_INVALID, "rank must be in 1..min(nsnap, 64)");
+    SCVS_REQUIRE(width >= 8 && width <= 1024 && layers >= 2 && layers <= 8, SCVS_E_INVALID, "bad MLP shape");
+    for (int64_t k = 0; k < nsnap; ++k) SCVS_REQUIRE(std::isfinite(omega[k]), SCVS_E_INVALID, "non-finite omega");
+    use_device(mesh->ctx);
+    auto w = std::make_unique<scvs_ws_s>();
+    w->mesh = mesh;
+    w->ndof = mesh->dim * mesh->n2 + mesh->nv;
+    scvs::ws_build(w.get(), nsnap, omega, (const double2*)snaps, rank, width, layers, seed);
+    *out = w.release();
+  });
+}
+
+int scvs_ws_train(scvs_ws ws, int epochs, double lr, double* loss) {
+  return guarded([&] {
+    SCVS_REQUIRE(ws && epochs >= 0 && lr > 0.0, SCVS_E_INVALID, "bad training arguments");
+    use_device(ws->mesh->ctx);
+    const double l = scvs::ws_train(ws, epochs, lr);
+    if (loss) *loss = l;
+  });
+}
+
+int scvs_ws_predict(scvs_ws ws, int64_t n, const double* omega, const double* amp, void* x0) {
+  return guarded([&] {
+    SCVS_REQUIRE(ws && n >= 1 && n <= 4096 && omega && amp && x0, SCVS_E_INVALID, "bad prediction arguments");
+    use_device(ws->mesh->ctx);
+    scvs::ws_predict(ws, n, omega, amp, (double2*)x0);
+  });
+}
+
+int scvs_ws_refine(scvs_ws ws, int64_t n, const double* omega, const double* traction, const void* g, void* x0) {
+  return guarded([&] {
+    SCVS_REQUIRE(ws && n >= 1 && n <= 4096 && omega && x0, SCVS_E_INVALID, "bad refine arguments");
+    scvs_mesh m = ws->mesh;
+    require_ready(m);
+    SCVS_REQUIRE(m->dim * m->n2 + m->nv == ws->ndof, SCVS_E_STATE, "mesh changed size since the model was built");
+    SCVS_REQUIRE(m->traction_tags.empty() || traction, SCVS_E_INVALID, "traction is null");
+    SCVS_REQUIRE(m->ndir == 0 || g, SCVS_E_INVALID, "g is null but the mesh has Dirichlet nodes");
+    for (int64_t k = 0; k < n; ++k) SCVS_REQUIRE(std::isfinite(omega[k]), SCVS_E_INVALID, "non-finite omega");
+    use_device(m->ctx);
+    scvs::ws_refine(ws, n, omega, traction, m->ndir ? g : nullptr, (double2*)x0);
+  });
+}
+
+int scvs_ws_destroy(scvs_ws ws) {
+  return guarded([&] { delete ws; });
+}
+
+int scvs_ws_export(scvs_ws ws, int which, void* out) {
+  return guarded([&] {
+    SCVS_REQUIRE(ws && out, SCVS_E_INVALID, "null argument");
+    use_device(ws->mesh->ctx);
+    hipStream_t s = ws->mesh->ctx->stream;
+    switch (which) {
+      case SCVS_WS_SIGMA: memcpy(out, ws->sigma.data(), sizeof(double) * ws->r); break;
+      case SCVS_WS_BASIS:
+        SCVS_HIP(hipMemcpyAsync(out, ws->basis.p, sizeof(double2) * ws->r * ws->ndof, hipMemcpyDeviceToDevice, s));
+        SCVS_HIP(hipStreamSynchronize(s));
+        break;
+      case SCVS_WS_PARAMS: scvs::download((float*)out, ws->net.p.p, ws->net.nparam, s); break;
+      case SCVS_WS_TARGETS: memcpy(out, ws->targets.data(), sizeof(float) * ws->targets.size()); break;
+      case SCVS_WS_NPARAM: *(int64_t*)out = ws->net.nparam; break;
+      default: fail(SCVS_E_INVALID, "unknown export selector");
+    }
+  });
+}
+
+int scvs_ws_set_params(scvs_ws ws, const float* params) {
+  return guarded([&] {
+    SCVS_REQUIRE(ws && params, SCVS_E_INVALID, "null argument");
+    use_device(ws->mesh->ctx);
+    hipStream_t s = ws->mesh->ctx->stream;
+    SCVS_HIP(hipMemcpyAsync(ws->net.p.p, params, sizeof(float) * ws->net.nparam, hipMemcpyHostToDevice, s));
+    SCVS_HIP(hipStreamSynchronize(s));
+  });
+}
+
+int scvs_ws_loss_grad(scvs_ws ws, int64_t n, const float* x, const float* t, double* loss, float* grads) {
+  return guarded([&] {
+    SCVS_REQUIRE(ws && n >= 1 && n <= 65536 && x && t && loss && grads, SCVS_E_INVALID, "bad arguments");
+    use_device(ws->mesh->ctx);
+    *loss = scvs::ws_loss_grad(ws, (int)n, x, t, grads);
+  });
+}
+
+int scvs_herm_eig(int n, const double* a, double* w, double* v) {
+  return guarded([&] {
+    SCVS_REQUIRE(n >= 1 && n <= 4096 && a && w && v, SCVS_E_INVALID, "bad eigen-decomposition arguments");
+    std::vector<std::complex<double>> A((size_t)n * n), V;
+    memcpy(A.data(), a, sizeof(double) * 2 * n * n);
+    std::vector<double> ww;
+    scvs::herm_eig(n, A, ww, V);
+    memcpy(w, ww.data(), sizeof(double) * n);
+    memcpy(v, V.data(), sizeof(double) * 2 * n * n);
+  });
+}
+
+int scvs_probe_mfma_bf16(scvs_ctx ctx, const float* a, const float* b, float* d) {
+  return guarded([&] {
+    SCVS_REQUIRE(ctx && a && b && d, SCVS_E_INVALID, "null argument");
+    use_device(ctx);
+    scvs::probe_mfma_bf16(a, b, d, ctx->stream);
   });
 }
 

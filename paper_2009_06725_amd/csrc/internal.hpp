@@ -4,6 +4,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
+#include <complex>
+#include <random>
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
@@ -43,6 +46,20 @@ struct DBuf {
   DBuf() = default;
   DBuf(const DBuf&) = delete;
   DBuf& operator=(const DBuf&) = delete;
+  DBuf(DBuf&& o) noexcept : p(o.p), n(o.n) {
+    o.p = nullptr;
+    o.n = 0;
+  }
+  DBuf& operator=(DBuf&& o) noexcept {
+    if (this != &o) {
+      release();
+      p = o.p;
+      n = o.n;
+      o.p = nullptr;
+      o.n = 0;
+    }
+    return *this;
+  }
   ~DBuf() { release(); }
   void release() {
     if (p) (void)hipFree(p);
@@ -130,6 +147,7 @@ struct scvs_mesh_s {
   scvs::DBuf<double> Ks, M, G, Gt, Kd, Md, Mp;
   scvs::DBuf<float> Ks32, M32, G32, Gt32, Kd32, Md32;  // made on the first mixed-precision solve
   bool fp32_ready = false;
+  uint64_t generation = 0;  // bumped whenever the operator changes (assembly, boundary conditions)
   // boundary conditions
   std::vector<int32_t> bc_tags, bc_kinds, traction_tags;
   scvs::DBuf<int32_t> dmask, dirnodes;
@@ -237,11 +255,115 @@ int solve_systems(scvs_mesh m, int64_t nsys, const double* omega, const double* 
 void rhs_systems(scvs_mesh m, int64_t nsys, const double* omega, const double* traction,
                  const void* g, void* f);
 
+// ---- learned.hip ----
+struct Mlp;
+void herm_eig(int n, std::vector<std::complex<double>>& A, std::vector<double>& w,
+              std::vector<std::complex<double>>& V);
+void ws_build(scvs_ws w, int64_t S, const double* omega, const double2* snaps, int r, int width, int layers,
+              uint64_t seed);
+double ws_train(scvs_ws w, int epochs, double lr);
+void ws_predict(scvs_ws w, int64_t n, const double* omega, const double* amp, double2* x0);
+void ws_refine(scvs_ws w, int64_t n, const double* omega, const double* traction, const void* g, double2* x0);
+double ws_loss_grad(scvs_ws w, int n, const float* x_host, const float* t_host, float* grads_host);
+void probe_mfma_bf16(const float* a, const float* b, float* d, hipStream_t s);
+
 // ---- synth.hip ----
 void synthesize(hipStream_t s, int64_t nk, const double* omega, const double2* modes,
                 int64_t nvals, int64_t nt, const double* times, double* out);
 
 }  // namespace scvs
+
+
+namespace scvs {
+// ---- MLP object (device) ----
+struct Mlp {
+  std::vector<int> sizes;  // layer widths, sizes[0] = inputs
+  int64_t nparam = 0;
+  std::vector<int64_t> woff, boff;  // offsets of W_l and b_l in the flat parameter vector
+  DBuf<float> p, g, m, v;           // parameters, gradients, Adam moments
+  int64_t step = 0;
+  void init(const std::vector<int>& sz, uint64_t seed, hipStream_t s) {
+    sizes = sz;
+    nparam = 0;
+    woff.clear();
+    boff.clear();
+    for (size_t l = 0; l + 1 < sizes.size(); ++l) {
+      woff.push_back(nparam);
+      nparam += (int64_t)sizes[l] * sizes[l + 1];
+      boff.push_back(nparam);
+      nparam += sizes[l + 1];
+    }
+    std::vector<float> h(nparam, 0.f);
+    std::mt19937_64 rng(seed);
+    std::normal_distribution<float> nd(0.f, 1.f);
+    for (size_t l = 0; l + 1 < sizes.size(); ++l) {
+      const float sc = 1.f / std::sqrt((float)sizes[l]);
+      for (int64_t k = 0; k < (int64_t)sizes[l] * sizes[l + 1]; ++k) h[woff[l] + k] = sc * nd(rng);
+    }
+    p.upload(h.data(), nparam, s);
+    g.alloc(nparam);
+    m.alloc(nparam);
+    v.alloc(nparam);
+    m.zero(s);
+    v.zero(s);
+    step = 0;
+  }
+  int layers() const { return (int)sizes.size() - 1; }
+};
+
+// Forward pass for n samples; acts holds per layer the input H_l ([n][sizes[l]])
+// and pre-activation Z_l ([n][sizes[l+1]]); returns the output pointer.
+struct MlpWork {
+  std::vector<DBuf<float>> H, Z, dH;
+  DBuf<float> dZ;
+  DBuf<double> part;
+  int n = 0;
+  void ensure(const Mlp& net, int nn) {
+    if (nn <= n && !H.empty()) return;
+    n = nn;
+    const int L = net.layers();
+    H.clear();
+    Z.clear();
+    dH.clear();
+    H.resize(L + 1);
+    Z.resize(L);
+    dH.resize(L + 1);
+    int mx = 0;
+    for (int l = 0; l <= L; ++l) {
+      H[l].alloc((size_t)n * net.sizes[l]);
+      dH[l].alloc((size_t)n * net.sizes[l]);
+      mx = std::max(mx, net.sizes[l]);
+    }
+    for (int l = 0; l < L; ++l) Z[l].alloc((size_t)n * net.sizes[l + 1]);
+    dZ.alloc((size_t)n * mx);
+    part.alloc(256);
+  }
+};
+
+}  // namespace scvs
+
+// ---- warm-start model ----
+struct scvs_ws_s {
+  scvs_mesh mesh = nullptr;
+  int S = 0, r = 0;
+  int64_t ndof = 0;
+  double wmax = 1.0;
+  double sigma0 = 0.0;            // largest singular value (scale of the targets)
+  scvs::DBuf<double2> basis;      // [r][ndof]
+  scvs::DBuf<double> sigma_d;     // [r]
+  std::vector<double> sigma;      // [r]
+  std::vector<double> omega;      // [S] snapshot frequencies
+  std::vector<float> targets;     // [S][2r] POD coefficients sigma_i conj(W_si) / sigma_0
+  scvs::Mlp net;
+  scvs::MlpWork work;
+  scvs::DBuf<float> X, T;         // training inputs/targets on the device
+  // reduced operator for the subspace correction: Q = [Q0; Q1] ([2r][ndof]) with
+  // A(w) phi_i = Q0_i + j w Q1_i on unconstrained rows, and its Gram matrix H (host)
+  uint64_t red_gen = ~0ull;
+  scvs::DBuf<double2> Q;
+  std::vector<std::complex<double>> H;
+};
+
 
 // ---- device helpers ----
 __device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }

@@ -380,7 +380,7 @@ __global__ void k_init_x(VArg x, const double2* __restrict__ x0, int64_t x0st, c
                          int64_t gst, const int32_t* __restrict__ dmask, const int32_t* __restrict__ dirnodes,
                          int64_t ndir, int64_t n2, int64_t ndof, const int* act, int first) {
   const int slot = act[blockIdx.y];
-  const int sys = first + blockIdx.y;
+  const int sys = first + slot;  // slot k of a batch holds system first + k
   double2* xs = x.at(slot);
   // Entries of Dirichlet (kind 2) nodes are written only by the second loop
   // when data is given, so the two loops never write the same element.
@@ -657,6 +657,34 @@ int solve_systems(scvs_mesh m, int64_t nsys, const double* omega, const double* 
     k_norm<1><<<g0, RBS, 0, s>>>(a0, VArg{}, o->rtol);
     launch_check(s);
     std::vector<double> info(4 * nb);
+    std::vector<int> warm(nb, x0 ? 1 : 0);
+    if (x0) {
+      // keep a supplied initial guess only where its residual is below ||f||
+      download(info.data(), P.info.p, 4 * nb, s);
+      std::vector<int> back;
+      for (int k = 0; k < nb; ++k)
+        if (!(info[4 * k] < 1.0)) {
+          back.push_back(k);
+          warm[k] = 0;
+        }
+      if (!back.empty()) {
+        SCVS_HIP(hipMemcpyAsync(P.act.p, back.data(), sizeof(int) * back.size(), hipMemcpyHostToDevice, s));
+        Batch bb = b;
+        bb.nact = (int)back.size();
+        bb.act = P.act;
+        KArgs ab = kargs(P, ndof, choose_nch(bb.nact, ndof));
+        const dim3 gb(256, (unsigned)bb.nact), gn((unsigned)ab.nch, (unsigned)bb.nact);
+        if (D == 2)
+          k_init_x<2><<<gb, 256, 0, s>>>(P.X(), nullptr, 0, gp, m->ndir * D, m->dmask, m->dirnodes, m->ndir,
+                                         m->n2, ndof, P.act, (int)first);
+        else
+          k_init_x<3><<<gb, 256, 0, s>>>(P.X(), nullptr, 0, gp, m->ndir * D, m->dmask, m->dirnodes, m->ndir,
+                                         m->n2, ndof, P.act, (int)first);
+        spmv_full(m, bb, P.X(), VArg{P.V.p, (int64_t)(mk + 1) * P.ld}, SPMV_RESID, true, P.F(), nullptr, s);
+        k_norm<1><<<gn, RBS, 0, s>>>(ab, VArg{}, o->rtol);
+        launch_check(s);
+      }
+    }
     std::vector<int> iters(nb, 0), cycles(nb, 0), done(nb, 0);
     std::map<int, std::pair<hipGraph_t, hipGraphExec_t>> graphs;
     std::vector<int> act_prev;
@@ -732,6 +760,7 @@ int solve_systems(scvs_mesh m, int64_t nsys, const double* omega, const double* 
         r.restarts = cycles[k];
         r.rel_residual = rel;
         r.status = (info[4 * k + 2] != 0.0 || !std::isfinite(rel)) ? 3 : (rel <= o->rtol ? 0 : 1);
+        r.warm = warm[k];
       }
     }
   }

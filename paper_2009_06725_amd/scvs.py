@@ -24,7 +24,10 @@ EXPORTED = [
     "scvs_mesh_destroy", "scvs_mesh_info", "scvs_mesh_set_midside", "scvs_mesh_set_bc", "scvs_assemble",
     "scvs_mesh_export", "scvs_spmv", "scvs_rhs", "scvs_solve_opts_default", "scvs_solve",
     "scvs_synthesize", "scvs_probe_mfma", "scvs_profile_enable", "scvs_profile_read",
+    "scvs_ws_create", "scvs_ws_train", "scvs_ws_predict", "scvs_ws_refine", "scvs_ws_destroy", "scvs_ws_export",
+    "scvs_ws_set_params", "scvs_ws_loss_grad", "scvs_herm_eig", "scvs_probe_mfma_bf16",
 ]
+WS_SIGMA, WS_BASIS, WS_PARAMS, WS_TARGETS, WS_NPARAM = range(5)
 
 
 class ScvsError(RuntimeError):
@@ -54,7 +57,7 @@ class KernelStat(C.Structure):
 
 class Report(C.Structure):
     _fields_ = [("status", C.c_int32), ("iterations", C.c_int32), ("restarts", C.c_int32),
-                ("rel_residual", C.c_double)]
+                ("rel_residual", C.c_double), ("warm", C.c_int32)]
 
 
 _lib = None
@@ -86,6 +89,16 @@ def lib() -> C.CDLL:
         L.scvs_synthesize.argtypes = [vp, i64, vp, vp, i64, i64, vp, vp]
         L.scvs_probe_mfma.argtypes = [vp, vp, vp, vp]
         L.scvs_profile_enable.argtypes = [vp, C.c_int]
+        L.scvs_ws_create.argtypes = [vp, i64, vp, vp, C.c_int, C.c_int, C.c_int, C.c_uint64, C.POINTER(vp)]
+        L.scvs_ws_train.argtypes = [vp, C.c_int, C.c_double, C.POINTER(C.c_double)]
+        L.scvs_ws_predict.argtypes = [vp, i64, vp, vp, vp]
+        L.scvs_ws_refine.argtypes = [vp, i64, vp, vp, vp, vp]
+        L.scvs_ws_destroy.argtypes = [vp]
+        L.scvs_ws_export.argtypes = [vp, C.c_int, vp]
+        L.scvs_ws_set_params.argtypes = [vp, vp]
+        L.scvs_ws_loss_grad.argtypes = [vp, i64, vp, vp, C.POINTER(C.c_double), vp]
+        L.scvs_herm_eig.argtypes = [C.c_int, vp, vp, vp]
+        L.scvs_probe_mfma_bf16.argtypes = [vp, vp, vp, vp]
         L.scvs_profile_read.argtypes = [vp, C.c_int, C.POINTER(KernelStat), C.POINTER(C.c_int)]
         for name in EXPORTED:
             if name not in ("scvs_last_error", "scvs_version", "scvs_solve_opts_default"):
@@ -274,6 +287,107 @@ def probe_mfma(ctx: Context, a: np.ndarray, b: np.ndarray) -> np.ndarray:
     b, pb = _host(b, np.float64)
     d = np.zeros(256)
     _check(lib().scvs_probe_mfma(ctx.h, pa, pb, d.ctypes.data_as(C.c_void_p)))
+    return d.reshape(16, 16)
+
+
+class WarmStart:
+    """POD + MLP warm start built from unit-amplitude mode solutions (device
+    complex128 [nsnap, ndof]) at frequencies omega."""
+
+    def __init__(self, mesh: Mesh, omega, snaps, rank=32, width=256, layers=4, seed=0):
+        self.mesh = mesh
+        om, po = _host(omega, np.float64)
+        h = C.c_void_p()
+        _check(lib().scvs_ws_create(mesh.h, om.size, po, _dev(snaps, "torch.complex128"), rank, width, layers,
+                                    seed, C.byref(h)))
+        self.h, self.rank, self.nsnap = h, rank, om.size
+
+    def train(self, epochs: int, lr: float = 1e-3) -> float:
+        loss = C.c_double()
+        _check(lib().scvs_ws_train(self.h, epochs, lr, C.byref(loss)))
+        return loss.value
+
+    def predict(self, omega, amp, out=None):
+        import torch
+        om, po = _host(omega, np.float64)
+        a, pa = _host(np.asarray(amp, np.complex128).view(np.float64), np.float64)
+        if out is None:
+            out = torch.empty((om.size, self.mesh.info.ndof), dtype=torch.complex128,
+                              device=torch.device("cuda", self.mesh.ctx.device))
+        _check(lib().scvs_ws_predict(self.h, om.size, po, pa, _dev(out, "torch.complex128")))
+        return out
+
+    def refine(self, omega, traction, g, x0):
+        """In-place minimal-residual correction of x0 over x0 + span(POD basis)."""
+        om, po = _host(omega, np.float64)
+        tr, ptr = _host(np.asarray(traction, np.complex128).reshape(om.size, -1).view(np.float64), np.float64)
+        _check(lib().scvs_ws_refine(self.h, om.size, po, ptr if tr.size else None,
+                                    None if g is None else _dev(g, "torch.complex128"), _dev(x0, "torch.complex128")))
+        return x0
+
+    def nparam(self) -> int:
+        n = C.c_int64()
+        _check(lib().scvs_ws_export(self.h, WS_NPARAM, C.byref(n)))
+        return n.value
+
+    def export(self, which: int):
+        if which == WS_SIGMA:
+            out = np.zeros(self.rank)
+        elif which == WS_PARAMS:
+            out = np.zeros(self.nparam(), np.float32)
+        elif which == WS_TARGETS:
+            out = np.zeros((self.nsnap, 2 * self.rank), np.float32)
+        elif which == WS_BASIS:
+            import torch
+            out = torch.empty((self.rank, self.mesh.info.ndof), dtype=torch.complex128,
+                              device=torch.device("cuda", self.mesh.ctx.device))
+            _check(lib().scvs_ws_export(self.h, which, _dev(out, "torch.complex128")))
+            return out
+        else:
+            raise ValueError(which)
+        _check(lib().scvs_ws_export(self.h, which, out.ctypes.data_as(C.c_void_p)))
+        return out
+
+    def set_params(self, params):
+        p, pp = _host(params, np.float32)
+        _check(lib().scvs_ws_set_params(self.h, pp))
+
+    def loss_grad(self, x, t):
+        x, px = _host(x, np.float32)
+        t, pt = _host(t, np.float32)
+        g = np.zeros(self.nparam(), np.float32)
+        loss = C.c_double()
+        _check(lib().scvs_ws_loss_grad(self.h, x.shape[0], px, pt, C.byref(loss), g.ctypes.data_as(C.c_void_p)))
+        return loss.value, g
+
+    def close(self):
+        if getattr(self, "h", None):
+            _check(lib().scvs_ws_destroy(self.h))
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def herm_eig(a: np.ndarray):
+    """Host Hermitian eigen-decomposition of the library (descending)."""
+    a = np.ascontiguousarray(a, np.complex128)
+    n = a.shape[0]
+    w = np.zeros(n)
+    v = np.zeros((n, n), np.complex128)
+    _check(lib().scvs_herm_eig(n, a.ctypes.data_as(C.c_void_p), w.ctypes.data_as(C.c_void_p),
+                               v.ctypes.data_as(C.c_void_p)))
+    return w, v
+
+
+def probe_mfma_bf16(ctx: Context, a: np.ndarray, b: np.ndarray) -> np.ndarray:
+    a, pa = _host(a, np.float32)
+    b, pb = _host(b, np.float32)
+    d = np.zeros(256, np.float32)
+    _check(lib().scvs_probe_mfma_bf16(ctx.h, pa, pb, d.ctypes.data_as(C.c_void_p)))
     return d.reshape(16, 16)
 
 

@@ -62,3 +62,17 @@ def test_oracle_not_imported_by_product():
         for f in files:
             if f.endswith((".py", ".hip", ".cpp", ".hpp")):
                 assert "oracle" not in open(os.path.join(dp, f)).read().replace("Oracle", ""), f
+
+
+def test_host_hermitian_eigensolver(lib):
+    """The POD's host eigen-decomposition (cyclic Jacobi) against numpy."""
+    import numpy as np
+    from paper_2009_06725_amd import scvs
+    rng = np.random.default_rng(4)
+    for n in (1, 2, 7, 40):
+        A = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+        A = A + A.conj().T
+        w, v = scvs.herm_eig(A)
+        assert np.allclose(w, np.linalg.eigvalsh(A)[::-1], atol=1e-12 * max(1.0, np.abs(w).max()))
+        assert np.abs(A @ v - v * w).max() < 1e-11 * max(1.0, np.abs(w).max())
+        assert np.abs(v.conj().T @ v - np.eye(n)).max() < 1e-12
