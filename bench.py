@@ -43,7 +43,7 @@ def parse():
     ap.add_argument("--tets", type=int, default=200000)
     ap.add_argument("--harmonics", type=int, default=16)
     ap.add_argument("--rtol", type=float, default=1e-10)
-    ap.add_argument("--restart", type=int, default=60)
+    ap.add_argument("--restart", type=int, default=200)
     ap.add_argument("--cheb-vel", type=int, default=10)
     ap.add_argument("--cheb-pres", type=int, default=20)
     ap.add_argument("--ntimes", type=int, default=64)

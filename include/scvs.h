@@ -172,13 +172,14 @@ int scvs_rhs(scvs_mesh mesh, int64_t nsys, const double* omega, const double* tr
  * G^T diag(M)^-1 G on the free velocity rows). */
 typedef struct {
   double rtol;        /* stop when ||f - A x||_2 <= rtol ||f||_2 (true residual) */
-  int32_t restart;    /* Krylov dimension m per cycle, 1..64 */
+  int32_t restart;    /* Krylov dimension m per cycle, 1..256 (shortened, not below 30, when
+                         memory would hold fewer than min(nsys, 8) systems' workspaces) */
   int32_t max_iters;  /* cap on Arnoldi steps per system */
   int32_t cheb_vel;   /* Chebyshev degree of the velocity block, >= 1 */
   int32_t cheb_pres;  /* Chebyshev degree of the pressure Laplacian, >= 1 */
   double cheb_ratio;  /* assumed lambda_max / lambda_min of the Jacobi-scaled blocks */
   int32_t max_batch;  /* systems solved together (0 = as many as fit) */
-  int32_t use_graph;  /* replay each restart cycle from a captured hipGraph */
+  int32_t use_graph;  /* replay the steps of each cycle, in chunks of 30, from captured hipGraphs */
   int32_t verbose;    /* print per-cycle residuals to stderr */
   int32_t precision;  /* 0: all FP64. 1: mixed -- inside each restart cycle the operator
                          product and the velocity-block polynomial run on FP32 matrix copies
@@ -188,7 +189,7 @@ typedef struct {
                          and the solution update stay FP64 */
 } scvs_solve_opts;
 
-/* Fill `o` with the defaults (rtol 1e-10, m 60, 20000 iterations, degrees 10/20,
+/* Fill `o` with the defaults (rtol 1e-10, m 200, 20000 iterations, degrees 10/20,
  * ratio 30, batch 0, graphs on, FP64). */
 void scvs_solve_opts_default(scvs_solve_opts* o);
 

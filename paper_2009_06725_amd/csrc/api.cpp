@@ -276,7 +276,7 @@ int scvs_rhs(scvs_mesh m, int64_t nsys, const double* omega, const double* tract
 void scvs_solve_opts_default(scvs_solve_opts* o) {
   if (!o) return;
   o->rtol = 1e-10;
-  o->restart = 60;
+  o->restart = 200;
   o->max_iters = 20000;
   o->cheb_vel = 10;
   o->cheb_pres = 20;

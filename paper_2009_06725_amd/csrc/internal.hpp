@@ -102,8 +102,12 @@ struct Profiler {
   size_t used = 0;
   std::vector<Pending> pending;
   std::vector<std::pair<std::string, Stat>> stats;
+  std::vector<std::pair<std::string, double>> corrections;  // bytes charged for work skipped on the device
   hipEvent_t get();
-  void resolve();  // synchronizes, folds pending pairs into stats
+  void resolve();  // synchronizes, folds pending pairs and byte corrections into stats
+  void correct(const char* name, double bytes) {
+    if (on) corrections.push_back({name, bytes});
+  }
   ~Profiler();
 };
 // Brackets one launch with events when profiling is on.
@@ -126,7 +130,7 @@ struct scvs_ctx_s {
   scvs::Profiler prof;
 };
 
-constexpr int SCVS_MMAX = 64;  // largest Krylov dimension per cycle
+constexpr int SCVS_MMAX = 256;  // largest Krylov dimension per cycle
 
 struct scvs_mesh_s {
   scvs_ctx ctx = nullptr;

@@ -14,6 +14,7 @@
 // workgroups in a fixed order by the last workgroup to finish (no floating-
 // point atomics: results are bit-reproducible).
 #include <cmath>
+#include <functional>
 #include <map>
 
 #include "internal.hpp"
@@ -264,6 +265,144 @@ __global__ void __launch_bounds__(RBS) k_update(KArgs a, int j) {
   }
 }
 
+// First update fused with the second Gram-Schmidt pass: w' = w - sum_i (h1_i hs_i) V_i,
+// then h2_i = hs_i <V_i, w'> and ||w'||, with one read of the basis. Each tile of tn
+// elements of the chunk is staged in LDS (V_0..V_j and w; the next tile is already in
+// flight in registers). The tile width tn is the largest power of two with
+// (j+1) tn <= TILE, so a tile stays near 32 KB whatever j is. 256/tn lanes per element
+// form w', then lane (i, q) accumulates conj(V_i) w' over a quarter of the tile for
+// vectors i, i + 64, ... The last workgroup of a system reduces the chunk partials in a
+// fixed order and either keeps h2 for the second update or, when the first pass lost
+// less than 30% of the norm, finalizes the column with h1 alone.
+constexpr int TILE = 2048;                // staged complex values per tile
+constexpr int NDG = (MM + 1 + 63) / 64;   // vector groups of the dot phase
+constexpr int VS = TILE + MM + 1 + 64;    // tile with one pad per row (and room for the partials)
+__global__ void __launch_bounds__(RBS) k_upd_dots(KArgs a, int j) {
+  static_assert((RBS / 64) * (MM + 1) <= VS, "partials reuse the tile buffer");
+  __shared__ double2 vs[VS];
+  __shared__ double2 wsh[32];
+  __shared__ double2 coef[MM + 1];
+  __shared__ double nsh[RBS / 64];
+  const int slot = a.act[blockIdx.y];
+  SlotState& st = a.st[slot];
+  if (st.jstop >= 0) return;
+  const int t = threadIdx.x;
+  const int nvec = j + 1;
+  int tn = 32;
+  while (tn > 4 && nvec * tn > TILE) tn >>= 1;
+  const int lpe = RBS / tn, tp = tn + 1;
+  for (int i = t; i <= j; i += RBS) coef[i] = cscale(st.h1[i], st.hs[i]);
+  int64_t b0, b1;
+  chunk_range(a, b0, b1);
+  double2* __restrict__ w = vec(a, slot, j + 1);
+  const double2* __restrict__ V0 = vec(a, slot, 0);
+  const int eu = t / lpe, ru = t % lpe;  // update phase: element eu of the tile, part ru
+  const int di = t & 63, dq = t >> 6;    // dot phase: vectors di + 64 g; quarter dq of the tile
+  const int qlen = tn / 4;
+  double2 acc[NDG];
+#pragma unroll
+  for (int g = 0; g < NDG; ++g) acc[g] = make_double2(0.0, 0.0);
+  double nacc = 0.0;
+  constexpr int PF = TILE / RBS;
+  const int nld = nvec * tn;
+  double2 pre[PF], wpre = make_double2(0.0, 0.0);
+  auto fetch = [&](int64_t nb) {
+    const int len = (int)min((int64_t)tn, b1 - nb);
+#pragma unroll
+    for (int k = 0; k < PF; ++k) {
+      const int q = t + k * RBS, i = q / tn, e = q % tn;
+      pre[k] = (q < nld && e < len) ? V0[(int64_t)i * a.ld + nb + e] : make_double2(0.0, 0.0);
+    }
+    if (t < tn) wpre = t < len ? w[nb + t] : make_double2(0.0, 0.0);
+  };
+  if (b0 < b1) fetch(b0);
+  for (int64_t nb = b0; nb < b1; nb += tn) {
+    const int len = (int)min((int64_t)tn, b1 - nb);
+    __syncthreads();  // coef ready; previous tile consumed
+#pragma unroll
+    for (int k = 0; k < PF; ++k) {
+      const int q = t + k * RBS;
+      if (q < nld) vs[(q / tn) * tp + q % tn] = pre[k];
+    }
+    if (t < tn) wsh[t] = wpre;
+    __syncthreads();
+    if (nb + tn < b1) fetch(nb + tn);
+    double2 u = make_double2(0.0, 0.0);
+    for (int i = ru; i <= j; i += lpe) {
+      const double2 v = vs[i * tp + eu], c = coef[i];
+      u.x += c.x * v.x - c.y * v.y;
+      u.y += c.x * v.y + c.y * v.x;
+    }
+    for (int o = lpe / 2; o > 0; o >>= 1) {  // groups of lpe lanes are aligned
+      u.x += __shfl_xor(u.x, o, 64);
+      u.y += __shfl_xor(u.y, o, 64);
+    }
+    __syncthreads();  // every lane has read wsh's old value
+    if (ru == 0) {
+      const double2 wn = csub(wsh[eu], u);
+      wsh[eu] = wn;
+      if (eu < len) {
+        w[nb + eu] = wn;
+        nacc += wn.x * wn.x + wn.y * wn.y;
+      }
+    }
+    __syncthreads();
+    for (int e = dq * qlen; e < (dq + 1) * qlen; ++e) {
+      const double2 wv = wsh[e];
+#pragma unroll
+      for (int g = 0; g < NDG; ++g)
+        if (di + 64 * g <= j) {
+          const double2 v = vs[(di + 64 * g) * tp + e];
+          acc[g].x += v.x * wv.x + v.y * wv.y;
+          acc[g].y += v.x * wv.y - v.y * wv.x;
+        }
+    }
+  }
+  // block partials (in the tile buffer): h2 sums over the quarters, ||w'||^2 over the waves
+  double2* red = vs;  // [RBS/64][MM+1]
+  const double nw = wave_sum(nacc);
+  __syncthreads();
+#pragma unroll
+  for (int g = 0; g < NDG; ++g)
+    if (di + 64 * g <= j) red[dq * (MM + 1) + di + 64 * g] = acc[g];
+  if ((t & 63) == 0) nsh[t >> 6] = nw;
+  __syncthreads();
+  double2* part = a.part + ((int64_t)slot * a.nch + blockIdx.x) * PSTRIDE;
+  for (int i = t; i <= j; i += RBS) {
+    double2 sum = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int q = 0; q < RBS / 64; ++q) sum = cadd(sum, red[q * (MM + 1) + i]);
+    part[i] = sum;
+  }
+  if (t == 0) {
+    double sn = 0.0;
+#pragma unroll
+    for (int q = 0; q < RBS / 64; ++q) sn += nsh[q];
+    part[MM + 1] = make_double2(sn, 0.0);
+  }
+  if (!last_block(&st.ticket[2], a.nch)) return;
+  __shared__ double nrm_sh;
+  if (t == 0) {
+    double sn = 0.0;
+    for (int c = 0; c < a.nch; ++c) sn += a.part[((int64_t)slot * a.nch + c) * PSTRIDE + MM + 1].x;
+    nrm_sh = sqrt(sn);
+  }
+  __syncthreads();
+  const double nrm = nrm_sh;
+  const bool skip = nrm >= 0.7 * st.nrm0 || j + 1 > a.m;
+  if (!skip) {
+    for (int i = t; i <= j; i += RBS) {
+      double2 sum = make_double2(0.0, 0.0);
+      for (int c = 0; c < a.nch; ++c) sum = cadd(sum, a.part[((int64_t)slot * a.nch + c) * PSTRIDE + i]);
+      st.h2[i] = cscale(sum, st.hs[i]);
+    }
+  }
+  if (t == 0) {
+    st.skip2 = skip ? 1 : 0;
+    if (skip) finalize_column(st, j, nrm, false);
+  }
+}
+
 // Back substitution R y = gamma over the steps of this cycle; y_i *= hs_i.
 __global__ void k_trisolve(KArgs a, int nact) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
@@ -432,7 +571,7 @@ struct Pool {
   DBuf<float2> vt32, z32;
   DBuf<SlotState> st;
   DBuf<double> omega, lv, info;
-  DBuf<int> act, act_all;
+  DBuf<int> act, act_all, act_run, stops;
   VArg Z() const { return VArg{W.p, 4 * ld}; }
   VArg X() const { return VArg{W.p + ld, 4 * ld}; }
   VArg F() const { return VArg{W.p + 2 * ld, 4 * ld}; }
@@ -465,18 +604,20 @@ KArgs kargs(Pool& P, int64_t ndof, int nch) {
   return a;
 }
 
-// One restart cycle for the active slots, then the new true residual.
-void run_cycle(scvs_mesh m, Pool& P, const Batch& b, const PrecondArgs& pa, int64_t ndof, double rtol,
-               hipStream_t s) {
-  const int nact = b.nact;
+// Steps j0..j1-1 of a restart cycle for the systems of `br` that are still running
+// (a system that stops inside the chunk makes its later Arnoldi launches return at once).
+void cycle_steps(scvs_mesh m, Pool& P, const Batch& br, const PrecondArgs& pa, int64_t ndof, int j0, int j1,
+                 hipStream_t s) {
+  const int nact = br.nact;
   const int nch = choose_nch(nact, ndof);
   KArgs a = kargs(P, ndof, nch);
+  a.act = br.act;
   const dim3 gr((unsigned)nch, (unsigned)nact);
   const VArg Vv{P.V.p, (int64_t)(P.m + 1) * P.ld};
   Profiler* prof = &m->ctx->prof;
-  const double vec = (double)ndof * 16.0 * nact;  // one vector of every active system
-  for (int j = 0; j < P.m; ++j) {
-    Batch bj = b;
+  const double vec = (double)ndof * 16.0 * nact;  // one vector of every running system
+  for (int j = j0; j < j1; ++j) {
+    Batch bj = br;
     bj.insc = reinterpret_cast<const double*>(P.st.p) + offsetof(SlotState, hs) / sizeof(double) + j;
     bj.insc_st = sizeof(SlotState) / sizeof(double);
     bj.insc_idx = 0;
@@ -484,20 +625,16 @@ void run_cycle(scvs_mesh m, Pool& P, const Batch& b, const PrecondArgs& pa, int6
     VArg vn{Vv.p + (int64_t)(j + 1) * P.ld, Vv.st};
     precond_apply(m, bj, pa, vj, P.Z(), s);
     if (pa.mixed)
-      spmv_apply32(m, b, pa.z32, vn, s);
+      spmv_apply32(m, br, pa.z32, vn, s);
     else
-      spmv_full(m, b, P.Z(), vn, SPMV_APPLY, false, VArg{}, nullptr, s);
+      spmv_full(m, br, P.Z(), vn, SPMV_APPLY, false, VArg{}, nullptr, s);
     {
       ProfScope ps(prof, s, "k_dots1", vec * (j + 2));  // V_0..V_j and w once
       k_dots<1><<<gr, RBS, 0, s>>>(a, j);
     }
     {
-      ProfScope ps(prof, s, "k_update1", vec * (j + 3));  // V_0..V_j and w read, w written
-      k_update<1><<<gr, RBS, 0, s>>>(a, j);
-    }
-    {
-      ProfScope ps(prof, s, "k_dots2", vec * (j + 2));
-      k_dots<2><<<gr, RBS, 0, s>>>(a, j);
+      ProfScope ps(prof, s, "k_upd_dots", vec * (j + 3));  // V_0..V_j and w read, w written
+      k_upd_dots<<<gr, RBS, 0, s>>>(a, j);
     }
     {
       ProfScope ps(prof, s, "k_update2", vec * (j + 3));
@@ -505,6 +642,25 @@ void run_cycle(scvs_mesh m, Pool& P, const Batch& b, const PrecondArgs& pa, int6
     }
     launch_check(s);
   }
+}
+
+__global__ void k_stops(const SlotState* __restrict__ st, const int* __restrict__ act, int n, int* __restrict__ out) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) out[k] = st[act[k]].jstop;
+}
+
+// End of a restart cycle for the systems of `b` (all that started it): least squares,
+// x += P^-1 V y, and the new true residual.
+void cycle_end(scvs_mesh m, Pool& P, const Batch& b, const PrecondArgs& pa, int64_t ndof, double rtol,
+               hipStream_t s) {
+  const int nact = b.nact;
+  const int nch = choose_nch(nact, ndof);
+  KArgs a = kargs(P, ndof, nch);
+  a.act = b.act;
+  const dim3 gr((unsigned)nch, (unsigned)nact);
+  const VArg Vv{P.V.p, (int64_t)(P.m + 1) * P.ld};
+  Profiler* prof = &m->ctx->prof;
+  const double vec = (double)ndof * 16.0 * nact;
   {
     ProfScope ps(prof, s, "k_trisolve", 0.0);
     k_trisolve<<<(nact + 63) / 64, 64, 0, s>>>(a, nact);
@@ -569,18 +725,23 @@ int solve_systems(scvs_mesh m, int64_t nsys, const double* omega, const double* 
   const int64_t ndof = D * m->n2 + m->nv;
   const int64_t DN = D * m->n2;
   const int ntr = (int)m->traction_tags.size();
-  const int mk = o->restart;
   Pool P;
-  P.m = mk;
   P.ld = (ndof + 63) / 64 * 64;
   P.DN = DN;
   P.nv = m->nv;
-  // batch size from free memory (keep 10% spare)
+  // batch size from free memory (keep 10% spare); a long restart that would leave
+  // room for fewer than min(nsys, 8) systems is shortened (not below 30) first
   size_t fr = 0, tot = 0;
   SCVS_HIP(hipMemGetInfo(&fr, &tot));
   const int nch_max = choose_nch(1, ndof);
   const bool mixed = o->precision == 1;
   if (mixed) make_fp32_copies(m, s);
+  int mk = o->restart;
+  const int64_t want = std::min<int64_t>(nsys, 8);
+  while (mk > 30 && (int64_t)((double)fr * 0.9 / (double)slot_bytes(P.ld, mk, DN, m->nv, nch_max, mixed)) < want)
+    mk = std::max(30, mk * 3 / 4);
+  if (o->verbose && mk != o->restart) fprintf(stderr, "[scvs] restart shortened to %d to fit memory\n", mk);
+  P.m = mk;
   const size_t per = slot_bytes(P.ld, mk, DN, m->nv, nch_max, mixed);
   int64_t fit = (int64_t)((double)fr * 0.9 / (double)per);
   SCVS_REQUIRE(fit >= 1, SCVS_E_NOMEM, "not enough device memory for one system's Krylov workspace");
@@ -603,6 +764,8 @@ int solve_systems(scvs_mesh m, int64_t nsys, const double* omega, const double* 
   P.info.alloc(4 * B);
   P.act.alloc(B);
   P.act_all.alloc(B);
+  P.act_run.alloc(B);
+  P.stops.alloc(B);
   P.trac.alloc((size_t)B * std::max(ntr, 1));
   PrecondArgs pa;
   pa.kv = o->cheb_vel;
@@ -687,6 +850,7 @@ int solve_systems(scvs_mesh m, int64_t nsys, const double* omega, const double* 
     }
     std::vector<int> iters(nb, 0), cycles(nb, 0), done(nb, 0);
     std::map<int, std::pair<hipGraph_t, hipGraphExec_t>> graphs;
+    const int chunk = std::min(mk, 30);
     std::vector<int> act_prev;
     for (;;) {
       download(info.data(), P.info.p, 4 * nb, s);
@@ -716,15 +880,22 @@ int solve_systems(scvs_mesh m, int64_t nsys, const double* omega, const double* 
       bc.nact = (int)act.size();
       bc.act = P.act;
       const int na = bc.nact;
-      if (o->use_graph && !m->ctx->prof.on) {
-        auto it = graphs.find(na);
+      // the cycle runs in chunks of steps; between chunks the host drops the systems that
+      // stopped, and the cycle ends as soon as none is running
+      const bool use_graph = o->use_graph && !m->ctx->prof.on;
+      auto launch = [&](int key, const std::function<void(hipStream_t)>& body) {
+        if (!use_graph) {
+          body(s);
+          return;
+        }
+        auto it = graphs.find(key);
         if (it == graphs.end()) {
           hipGraph_t gph;
           hipGraphExec_t ex;
           hipStream_t cs = m->ctx->capture;
           SCVS_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
           try {
-            run_cycle(m, P, bc, pa, ndof, o->rtol, cs);
+            body(cs);
           } catch (...) {
             hipGraph_t bad = nullptr;
             (void)hipStreamEndCapture(cs, &bad);
@@ -734,13 +905,50 @@ int solve_systems(scvs_mesh m, int64_t nsys, const double* omega, const double* 
           }
           SCVS_HIP(hipStreamEndCapture(cs, &gph));
           SCVS_HIP(hipGraphInstantiate(&ex, gph, nullptr, nullptr, 0));
-          it = graphs.emplace(na, std::make_pair(gph, ex)).first;
+          it = graphs.emplace(key, std::make_pair(gph, ex)).first;
         }
         SCVS_HIP(hipGraphLaunch(it->second.second, s));
         SCVS_HIP(hipGetLastError());
-      } else {
-        run_cycle(m, P, bc, pa, ndof, o->rtol, s);
+      };
+      std::vector<int> run = act;
+      std::vector<int> stops(na), jend(nb, mk);
+      for (int j0 = 0; j0 < mk; j0 += chunk) {
+        const int j1 = std::min(mk, j0 + chunk);
+        const bool all = run.size() == act.size();
+        Batch br = bc;
+        br.nact = (int)run.size();
+        br.act = all ? P.act.p : P.act_run.p;
+        const int key = ((all ? 0 : 1) * 4096 + br.nact) * 1024 + j0 / chunk;
+        launch(key, [&](hipStream_t st) { cycle_steps(m, P, br, pa, ndof, j0, j1, st); });
+        const bool prof_on = m->ctx->prof.on;
+        if (j1 == mk && !prof_on) break;
+        k_stops<<<(br.nact + 63) / 64, 64, 0, s>>>(P.st, br.act, br.nact, P.stops);
+        launch_check(s);
+        download(stops.data(), P.stops.p, br.nact, s);
+        std::vector<int> next;
+        for (int k = 0; k < br.nact; ++k) {
+          const int J = stops[k];
+          if (J < 0) {
+            next.push_back(run[k]);
+            continue;
+          }
+          jend[run[k]] = J;
+          // Arnoldi launches of steps J.. returned at once: take back their bytes
+          for (int jj = std::max(J, j0); jj < j1; ++jj) {
+            const double v = (double)ndof * 16.0;
+            m->ctx->prof.correct("k_dots1", -v * (jj + 2));
+            m->ctx->prof.correct("k_upd_dots", -v * (jj + 3));
+            m->ctx->prof.correct("k_update2", -v * (jj + 3));
+          }
+        }
+        if (next.empty() || j1 == mk) break;
+        if (next.size() != run.size()) {
+          SCVS_HIP(hipMemcpyAsync(P.act_run.p, next.data(), sizeof(int) * next.size(), hipMemcpyHostToDevice, s));
+          run.swap(next);
+        }
       }
+      for (int k : act) m->ctx->prof.correct("k_combine", -(double)ndof * 16.0 * (mk - jend[k]));
+      launch(-1 - na, [&](hipStream_t st) { cycle_end(m, P, bc, pa, ndof, o->rtol, st); });
       for (int k : act) cycles[k]++;
     }
     for (auto& kv : graphs) {

@@ -152,14 +152,17 @@ __device__ __forceinline__ C sum_components(C v) {
   return r;
 }
 
-// Walk slots [j0, j1) of an S2 row: au += (mu Ks + (ar + j ai) M) x[col][c] (when
-// wantK) and ap += Gt^c x[col][c] (when wantGt). Every lane of the W-lane row
+// Walk slots [j0, j1) of an S2 row: au += (mu Ks + (ar + j ai) M) x[col] (when
+// wantK) and ap += Gt^c x[col] (when wantGt), where the lane's value of node col
+// sits at xs[col * xst + xoff] (system-major: xst = D, xoff = c; interleaved
+// temporaries: xst = pairs per node, xoff = pair). Every lane of the W-lane row
 // group calls this together: the group first loads W slots of (col, Ks, M)
 // lane-parallel (coalesced), then broadcasts them by shuffles and issues eight
 // independent gathers at a time. With MASK, Dirichlet columns are skipped.
 template <int D, bool MASK, class R>
 __device__ __forceinline__ void row_acc(const MeshArgs& ma, int W, int li, int64_t j0, int64_t j1,
-                                        const typename Prec<R>::C* __restrict__ xs, int c, bool pairok, R ar, R ai,
+                                        const typename Prec<R>::C* __restrict__ xs, int64_t xst, int xoff, int c,
+                                        bool pairok, R ar, R ai,
                                         bool wantK, bool wantGt, typename Prec<R>::C& au,
                                         typename Prec<R>::C& ap) {
   using C = typename Prec<R>::C;
@@ -190,7 +193,7 @@ __device__ __forceinline__ void row_acc(const MeshArgs& ma, int W, int li, int64
       }
 #pragma unroll
       for (int u = 0; u < U; ++u)
-        xv[u] = (pairok && t + u < n && B[u] >= 0) ? xs[(int64_t)B[u] * D + c] : czero<C>();
+        xv[u] = (pairok && t + u < n && B[u] >= 0) ? xs[(int64_t)B[u] * xst + xoff] : czero<C>();
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         if (wantK) {
@@ -261,7 +264,8 @@ __global__ void __launch_bounds__(256) k_full(MeshArgs ma, Batch b, LaneMap lm, 
     const C* __restrict__ xs = x.at(slot);
     const R wr = (R)(b.omega[slot] * ma.rho);
     C au = czero<C>(), ap = czero<C>();
-    if (dm == 0 || isv) row_acc<D, MASK, R>(ma, lm.W, L.li, j0, j1, xs, c, ok, (R)0, wr, dm == 0, isv, au, ap);
+    if (dm == 0 || isv)
+      row_acc<D, MASK, R>(ma, lm.W, L.li, j0, j1, xs, D, c, c, ok, (R)0, wr, dm == 0, isv, au, ap);
     if (ok) {
       if (dm == 0) g_acc<D, R, C>(ma, A, j0, xs + D * ma.n2, c, (R)1, au);
       double2 yu;
@@ -319,18 +323,28 @@ __device__ __forceinline__ void cheb_coef(double lmax, double ratio, int i, doub
 // (same for every component), in three-term form
 //   x_1 = diag^-1 b / theta,
 //   x_{k+1} = x_k + rho_k rho_{k-1} (x_k - x_{k-1}) + (2 rho_k / delta) diag^-1 (b - A_r x_k),
-// with b = insc*v_u - G zhat_p. Temps per slot: b, x_a, x_b, x_c (d*n2 each);
-// the last iterate is written into z. Dirichlet rows stay zero.
-template <class C, class V>
-__device__ __forceinline__ C* vbuf(const V& vt, int slot, int64_t DN, int k) {
-  return vt.at(slot) + DN * (1 + (k % 3));
-}
+// with b = insc*v_u - G zhat_p. The last iterate is written into z (system-major);
+// Dirichlet rows stay zero.
+//
+// The temporaries b, x_a, x_b, x_c live only inside one application, so they use
+// the layout that suits the gathers: pair p = si*D + c of the batch's active list
+// (si-th active system, component c) of node A sits at A*G + p (G = pairs), and the
+// values that one column contributes to all systems and components are adjacent.
+template <class C>
+struct ITemps {
+  C* base;
+  int64_t n2;
+  int G;
+  __device__ C* arr(int k) const { return base + (int64_t)k * n2 * G; }  // 0: b, 1..3: iterates
+  __device__ C* iter(int k) const { return arr(1 + k % 3); }
+};
 
 // In FP32 mode the output z is the FP32 vector z32 (velocity part written
 // here, pressure part copied from the FP64 Schur-block result zp).
 template <int D, class R>
 __global__ void __launch_bounds__(256) k_vinit(MeshArgs ma, Batch b, LaneMap lm, VArg v, VArg zp64,
-                                               typename Prec<R>::V z, typename Prec<R>::V vt, double ratio, int kv) {
+                                               typename Prec<R>::V z, ITemps<typename Prec<R>::C> vt,
+                                               double ratio, int kv) {
   using C = typename Prec<R>::C;
   const Lane L = lane_of(lm, ma.n2);
   for (int it = 0; it < lm.iters; ++it) {
@@ -339,10 +353,10 @@ __global__ void __launch_bounds__(256) k_vinit(MeshArgs ma, Batch b, LaneMap lm,
     const int si = p / D, c = p % D;
     const int slot = b.act[si];
     const int64_t A = L.row, DN = D * ma.n2;
-    C* __restrict__ bb = vt.at(slot);
-    C* __restrict__ x1 = (kv == 1) ? z.at(slot) : vbuf<C>(vt, slot, DN, 1);
+    const int64_t k = A * D + c, ki = A * lm.G + p;
+    C* __restrict__ bb = vt.arr(0);
+    C* __restrict__ x1 = (kv == 1) ? z.at(slot) + k : vt.iter(1) + ki;
     const double2* __restrict__ zp = zp64.at(slot) + DN;
-    const int64_t k = A * D + c;
     if (sizeof(R) == 4 && A < ma.nv && c == 0) {
       const double2 q = zp[A];
       C qq;
@@ -351,7 +365,7 @@ __global__ void __launch_bounds__(256) k_vinit(MeshArgs ma, Batch b, LaneMap lm,
       z.at(slot)[DN + A] = qq;
     }
     if (ma.dmask[A] != 0) {
-      bb[k] = x1[k] = czero<C>();
+      bb[ki] = *x1 = czero<C>();
       continue;
     }
     const double sc = in_scale(b, slot);
@@ -363,71 +377,69 @@ __global__ void __launch_bounds__(256) k_vinit(MeshArgs ma, Batch b, LaneMap lm,
     const double lmax = b.lv[slot];
     const R theta = (R)(0.5 * lmax * (1.0 + 1.0 / ratio));
     const R dinv = (R)1 / ((R)ma.mu * Prec<R>::Kd(ma)[A] + (R)(fabs(b.omega[slot]) * ma.rho) * Prec<R>::Md(ma)[A]);
-    bb[k] = t;
+    bb[ki] = t;
     C xv;
     xv.x = t.x * (dinv / theta);
     xv.y = t.y * (dinv / theta);
-    x1[k] = xv;
+    *x1 = xv;
   }
 }
 
 template <int D, class R>
 __global__ void __launch_bounds__(256) k_vstep(MeshArgs ma, Batch b, LaneMap lm, typename Prec<R>::V z,
-                                               typename Prec<R>::V vt, double ratio, int step, int last) {
+                                               ITemps<typename Prec<R>::C> vt, double ratio, int step, int last) {
   using C = typename Prec<R>::C;
   const Lane L = lane_of(lm, ma.n2);
   if (!L.rowok) return;  // uniform over the row group
-  const int64_t A = L.row, DN = D * ma.n2;
+  const int64_t A = L.row;
   const bool dir = ma.dmask[A] != 0;
   const int64_t j0 = ma.rowptr[A], j1 = ma.rowptr[A + 1];
+  const C* __restrict__ xk = vt.iter(step);
   for (int it = 0; it < lm.iters; ++it) {
     const int p = L.li + it * lm.UL;
     const bool ok = L.pairok0 && p < lm.G;
     const int si = ok ? p / D : 0, c = ok ? p % D : 0;
     const int slot = b.act[si];
-    const C* __restrict__ xk = vbuf<C>(vt, slot, DN, step);
-    C* __restrict__ xn = last ? z.at(slot) : vbuf<C>(vt, slot, DN, step + 1);
-    const int64_t k = A * D + c;
+    const int64_t ki = A * lm.G + p;
+    C* __restrict__ xn = last ? z.at(slot) + A * D + c : vt.iter(step + 1) + ki;
     if (dir) {
-      if (ok) xn[k] = czero<C>();
+      if (ok) *xn = czero<C>();
       continue;
     }
     const R wr = (R)(fabs(b.omega[slot]) * ma.rho);
     C q = czero<C>(), unused = czero<C>();
-    row_acc<D, false, R>(ma, lm.W, L.li, j0, j1, xk, c, ok, wr, (R)0, true, false, q, unused);
+    row_acc<D, false, R>(ma, lm.W, L.li, j0, j1, xk, lm.G, p, c, ok, wr, (R)0, true, false, q, unused);
     if (!ok) continue;
-    const C* __restrict__ bb = vt.at(slot);
-    const C* __restrict__ xm = vbuf<C>(vt, slot, DN, step - 1);
     double rp, rc, delta, theta;
     cheb_coef(b.lv[slot], ratio, step, rp, rc, delta, theta);
     const R dinv = (R)1 / ((R)ma.mu * Prec<R>::Kd(ma)[A] + wr * Prec<R>::Md(ma)[A]);
-    const C bv = bb[k], xv = xk[k];
-    const C xo = (step == 1) ? czero<C>() : xm[k];
+    const C bv = vt.arr(0)[ki], xv = xk[ki];
+    const C xo = (step == 1) ? czero<C>() : vt.iter(step - 1)[ki];
     const R ca = (R)(rc * rp), cb = (R)(2.0 * rc / delta) * dinv;
     C o;
     o.x = xv.x + ca * (xv.x - xo.x) + cb * (bv.x - q.x);
     o.y = xv.y + ca * (xv.y - xo.y) + cb * (bv.y - q.y);
-    xn[k] = o;
+    *xn = o;
   }
 }
 
 // Pressure block, first step (elementwise over vertices): r = insc*v_p,
 // d0 = diag(L)^-1 r / theta, x = d0; with one step the Schur block is final:
-// zhat_p = -(mu Mp^-1 v_p + j w rho x). Temps per slot: r, d0, d1, x (nv each).
-__global__ void k_pinit(MeshArgs ma, int D, Batch b, VArg v, VArg z, VArg pt, double ratio, int kp) {
+// zhat_p = -(mu Mp^-1 v_p + j w rho x). Temps r, d0, d1, x are interleaved like the
+// velocity ones: system si of the active list at vertex A sits at A*G + si.
+__global__ void k_pinit(MeshArgs ma, int D, Batch b, VArg v, VArg z, ITemps<double2> pt, double ratio, int kp) {
   const int64_t vv = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (vv >= ma.nv) return;
-  const int slot = b.act[blockIdx.y];
-  const int64_t DN = D * ma.n2, nv = ma.nv;
+  const int si = blockIdx.y;
+  const int slot = b.act[si];
+  const int64_t DN = D * ma.n2, ki = vv * pt.G + si;
   const double sc = in_scale(b, slot);
   const double2 vp = cscale(v.at(slot)[DN + vv], sc);
-  double2* rp = pt.at(slot);
-  double2 *d0 = rp + nv, *xp = rp + 3 * nv;
   const double theta = 0.5 * ma.lpmax * (1.0 + 1.0 / ratio);
   const double2 dd = cscale(vp, ma.lpdinv[vv] / theta);
-  rp[vv] = vp;
-  d0[vv] = dd;
-  xp[vv] = dd;
+  pt.arr(0)[ki] = vp;
+  pt.arr(1)[ki] = dd;
+  pt.arr(3)[ki] = dd;
   if (kp == 1) {
     const double wr = b.omega[slot] * ma.rho, im = ma.mu / ma.Mp[vv];
     z.at(slot)[DN + vv] = make_double2(-(im * vp.x - wr * dd.y), -(im * vp.y + wr * dd.x));
@@ -436,19 +448,20 @@ __global__ void k_pinit(MeshArgs ma, int D, Batch b, VArg v, VArg z, VArg pt, do
 
 // Pressure Laplacian Chebyshev step on the assembled L (one lane per system):
 // r -= L d_old; d_new = a d_old + b diag(L)^-1 r; x += d_new; on the last step
-// zhat_p = -(mu Mp^-1 v_p + j w rho x).
-__global__ void __launch_bounds__(256) k_pstep(MeshArgs ma, int D, Batch b, LaneMap lm, VArg v, VArg z, VArg pt,
-                                               double ratio, int step, int last) {
+// zhat_p = -(mu Mp^-1 v_p + j w rho x). A column's values of all systems are adjacent.
+__global__ void __launch_bounds__(256) k_pstep(MeshArgs ma, int D, Batch b, LaneMap lm, VArg v, VArg z,
+                                               ITemps<double2> pt, double ratio, int step, int last) {
   const Lane L = lane_of(lm, ma.nv);
+  const int G = pt.G;
   for (int it = 0; it < lm.iters; ++it) {
     const int p = L.li + it * lm.UL;
     if (!(L.rowok && L.pairok0 && p < lm.G)) continue;
     const int slot = b.act[p];
-    const int64_t A = L.row, nv = ma.nv;
-    double2* rp = pt.at(slot);
-    const double2* __restrict__ dold = rp + ((step & 1) ? nv : 2 * nv);
-    double2* dnew = rp + ((step & 1) ? 2 * nv : nv);
-    double2* xp = rp + 3 * nv;
+    const int64_t A = L.row, ki = A * G + p;
+    double2* rp = pt.arr(0);
+    const double2* __restrict__ dold = pt.arr((step & 1) ? 1 : 2);
+    double2* dnew = pt.arr((step & 1) ? 2 : 1);
+    double2* xp = pt.arr(3);
     double2 q = make_double2(0.0, 0.0);
     const int64_t k0 = ma.lp_ptr[A], k1 = ma.lp_ptr[A + 1];
     int64_t k = k0;
@@ -461,7 +474,7 @@ __global__ void __launch_bounds__(256) k_pstep(MeshArgs ma, int D, Batch b, Lane
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
         l[t] = ma.lp_val[k + t];
-        dv[t] = dold[u[t]];
+        dv[t] = dold[(int64_t)u[t] * G + p];
       }
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
@@ -471,20 +484,20 @@ __global__ void __launch_bounds__(256) k_pstep(MeshArgs ma, int D, Batch b, Lane
     }
     for (; k < k1; ++k) {
       const double l = ma.lp_val[k];
-      const double2 dv = dold[ma.lp_col[k]];
+      const double2 dv = dold[(int64_t)ma.lp_col[k] * G + p];
       q.x += l * dv.x;
       q.y += l * dv.y;
     }
     double rpv, rc, delta, theta;
     cheb_coef(ma.lpmax, ratio, step, rpv, rc, delta, theta);
-    const double2 rn = csub(rp[A], q);
+    const double2 rn = csub(rp[ki], q);
     const double ca = rc * rpv, cb = 2.0 * rc / delta * ma.lpdinv[A];
-    const double2 dk = dold[A];
+    const double2 dk = dold[ki];
     const double2 dn = make_double2(ca * dk.x + cb * rn.x, ca * dk.y + cb * rn.y);
-    const double2 xn = cadd(xp[A], dn);
-    rp[A] = rn;
-    dnew[A] = dn;
-    xp[A] = xn;
+    const double2 xn = cadd(xp[ki], dn);
+    rp[ki] = rn;
+    dnew[ki] = dn;
+    xp[ki] = xn;
     if (last) {
       const int64_t DN = D * ma.n2;
       const double sc = in_scale(b, slot);
@@ -572,19 +585,24 @@ void precond_launch(Profiler* prof, const MeshArgs& ma, const Batch& b, const Pr
   const unsigned nbu = row_blocks(ma.n2, lm), nbp = row_blocks(ma.nv, lp);
   const double n2 = (double)ma.n2, nv = (double)ma.nv, DN = (double)D * ma.n2, na = b.nact;
   dim3 gp((unsigned)((ma.nv + 255) / 256), (unsigned)b.nact);
+  // interleaved pressure temporaries inside the slot pool's block (4 * nv per slot, contiguous)
+  const ITemps<double2> ptl{pa.pt.p, ma.nv, b.nact};
   {
     // per system: v_p read, r/d0/x written (and z_p when one step); lpdinv, Mp read
     ProfScope ps(prof, s, "k_pinit", nv * 16.0 + na * nv * 16.0 * 4.0);
-    k_pinit<<<gp, 256, 0, s>>>(ma, D, b, v, z, pa.pt, pa.ratio, pa.kp);
+    k_pinit<<<gp, 256, 0, s>>>(ma, D, b, v, z, ptl, pa.ratio, pa.kp);
   }
   // L values and columns, row pointers, diag, Mp; per system d_old gathered,
   // r read+written, d_new written, x read+written
   const double pbytes = (double)ma.nnzl * 12.0 + nv * 24.0 + na * nv * 16.0 * 6.0;
   for (int i = 1; i < pa.kp; ++i) {
     ProfScope ps(prof, s, "k_pstep", pbytes + (i == pa.kp - 1 ? na * nv * 32.0 : 0.0));
-    k_pstep<<<nbp, 256, 0, s>>>(ma, D, b, lp, v, z, pa.pt, pa.ratio, i, i == pa.kp - 1);
+    k_pstep<<<nbp, 256, 0, s>>>(ma, D, b, lp, v, z, ptl, pa.ratio, i, i == pa.kp - 1);
   }
   const double es = pa.mixed ? 8.0 : 16.0, vs = pa.mixed ? 4.0 : 8.0;  // complex / real element bytes
+  // interleaved temporaries inside the slot pool's temp block (4 * D*n2 per slot, contiguous)
+  const ITemps<double2> it64{pa.vt.p, ma.n2, lm.G};
+  const ITemps<float2> it32{pa.vt32.p, ma.n2, lm.G};
   {
     // vertex-column prefix (col + G), row arrays; per system v_u read (FP64), z_p read (FP64),
     // b and x_1 written (and the FP32 copy of z_p in mixed mode)
@@ -592,18 +610,18 @@ void precond_launch(Profiler* prof, const MeshArgs& ma, const Batch& b, const Pr
                  (double)ma.nnz21 * (4.0 + vs * D) + n2 * (24.0 + 2.0 * vs) +
                      na * (DN * 16.0 + nv * 16.0 + 2.0 * DN * es + (pa.mixed ? nv * es : 0.0)));
     if (pa.mixed)
-      k_vinit<D, float><<<nbu, 256, 0, s>>>(ma, b, lm, v, z, pa.z32, pa.vt32, pa.ratio, pa.kv);
+      k_vinit<D, float><<<nbu, 256, 0, s>>>(ma, b, lm, v, z, pa.z32, it32, pa.ratio, pa.kv);
     else
-      k_vinit<D, double><<<nbu, 256, 0, s>>>(ma, b, lm, v, z, z, pa.vt, pa.ratio, pa.kv);
+      k_vinit<D, double><<<nbu, 256, 0, s>>>(ma, b, lm, v, z, z, it64, pa.ratio, pa.kv);
   }
   // S2 col/Ks/M, rowptr/dmask/Kd/Md; per system x_k (gathered, read once), b, x_{k-1} read, x_{k+1} written
   const double vbytes = (double)ma.nnz * (4.0 + 2.0 * vs) + n2 * (12.0 + 2.0 * vs) + na * 4.0 * DN * es;
   for (int i = 1; i < pa.kv; ++i) {
     ProfScope ps(prof, s, pa.mixed ? "k_vstep32" : "k_vstep", vbytes);
     if (pa.mixed)
-      k_vstep<D, float><<<nbu, 256, 0, s>>>(ma, b, lm, pa.z32, pa.vt32, pa.ratio, i, i == pa.kv - 1);
+      k_vstep<D, float><<<nbu, 256, 0, s>>>(ma, b, lm, pa.z32, it32, pa.ratio, i, i == pa.kv - 1);
     else
-      k_vstep<D, double><<<nbu, 256, 0, s>>>(ma, b, lm, z, pa.vt, pa.ratio, i, i == pa.kv - 1);
+      k_vstep<D, double><<<nbu, 256, 0, s>>>(ma, b, lm, z, it64, pa.ratio, i, i == pa.kv - 1);
   }
   launch_check(s);
 }

@@ -15,8 +15,8 @@ hipEvent_t Profiler::get() {
 }
 
 void Profiler::resolve() {
-  if (pending.empty()) return;
-  SCVS_HIP(hipEventSynchronize(pending.back().b));
+  if (pending.empty() && corrections.empty()) return;
+  if (!pending.empty()) SCVS_HIP(hipEventSynchronize(pending.back().b));
   for (auto& pd : pending) {
     float ms = 0.0f;
     SCVS_HIP(hipEventElapsedTime(&ms, pd.a, pd.b));
@@ -29,6 +29,10 @@ void Profiler::resolve() {
     it->second.ms += ms;
     it->second.bytes += pd.bytes;
   }
+  for (auto& c : corrections)
+    for (auto& kv : stats)
+      if (kv.first == c.first) kv.second.bytes += c.second;
+  corrections.clear();
   pending.clear();
   used = 0;
 }
