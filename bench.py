@@ -45,7 +45,7 @@ def parse():
     ap.add_argument("--rtol", type=float, default=1e-10)
     ap.add_argument("--restart", type=int, default=200)
     ap.add_argument("--cheb-vel", type=int, default=10)
-    ap.add_argument("--cheb-pres", type=int, default=20)
+    ap.add_argument("--cheb-pres", type=int, default=50)
     ap.add_argument("--ntimes", type=int, default=64)
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="mixed")
     ap.add_argument("--no-compare", action="store_true",

@@ -189,7 +189,7 @@ typedef struct {
                          and the solution update stay FP64 */
 } scvs_solve_opts;
 
-/* Fill `o` with the defaults (rtol 1e-10, m 200, 20000 iterations, degrees 10/20,
+/* Fill `o` with the defaults (rtol 1e-10, m 200, 20000 iterations, degrees 10/50,
  * ratio 30, batch 0, graphs on, FP64). */
 void scvs_solve_opts_default(scvs_solve_opts* o);
 

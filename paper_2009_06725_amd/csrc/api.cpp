@@ -279,7 +279,7 @@ void scvs_solve_opts_default(scvs_solve_opts* o) {
   o->restart = 200;
   o->max_iters = 20000;
   o->cheb_vel = 10;
-  o->cheb_pres = 20;
+  o->cheb_pres = 50;
   o->cheb_ratio = 30.0;
   o->max_batch = 0;
   o->use_graph = 1;

@@ -244,7 +244,13 @@ struct PrecondArgs {
   VArg vt;  // velocity temps: 4 * d*n2 per slot (b, three rotating iterates)
   VArg pt;  // pressure temps: 4*nv per slot (r, d0, d1, x)
 };
-void precond_apply(scvs_mesh m, const Batch& b, const PrecondArgs& pa, VArg v, VArg z, hipStream_t s);
+// With zil (a buffer of nact*ndof values, FP32 in mixed mode) the result is written
+// interleaved for spmv_apply_il instead of into z (z still receives the FP64 pressure
+// part in the Schur step).
+void precond_apply(scvs_mesh m, const Batch& b, const PrecondArgs& pa, VArg v, VArg z, hipStream_t s,
+                   void* zil = nullptr);
+// y = A x with x in the interleaved layout written by precond_apply(..., zil).
+void spmv_apply_il(scvs_mesh m, const Batch& b, const void* xil, bool fp32, VArg y, hipStream_t s);
 // y = A x with FP32 matrix copies, FP32 input and FP32 accumulation; FP64 output.
 void spmv_apply32(scvs_mesh m, const Batch& b, VArg32 x, VArg y, hipStream_t s);
 // FP32 copies of the matrix values for mixed-precision solves (made once per assembly).

@@ -572,6 +572,7 @@ struct Pool {
   DBuf<SlotState> st;
   DBuf<double> omega, lv, info;
   DBuf<int> act, act_all, act_run, stops;
+  DBuf<double2> zil;  // interleaved preconditioner output inside a cycle (FP32 pairs in mixed mode)
   VArg Z() const { return VArg{W.p, 4 * ld}; }
   VArg X() const { return VArg{W.p + ld, 4 * ld}; }
   VArg F() const { return VArg{W.p + 2 * ld, 4 * ld}; }
@@ -579,8 +580,11 @@ struct Pool {
 };
 
 size_t slot_bytes(int64_t ld, int m, int64_t DN, int64_t nv, int nch, bool mixed) {
+  // basis, Z/X/F/T, velocity temps (FP64 path), pressure temps, partial sums; FP32 temps,
+  // z32 (mixed path); interleaved operator input (FP32 pairs in mixed mode)
   return sizeof(double2) * ((size_t)(m + 1 + 4) * ld + (mixed ? 0 : 4 * DN) + 4 * nv + (size_t)nch * PSTRIDE) +
-         (mixed ? sizeof(float2) * (4 * DN + ld) : 0) + sizeof(SlotState) + 64;
+         (mixed ? sizeof(float2) * (4 * DN + ld) : 0) + (mixed ? sizeof(float2) : sizeof(double2)) * ld +
+         sizeof(SlotState) + 64;
 }
 
 int choose_nch(int nact, int64_t ndof) {
@@ -623,11 +627,8 @@ void cycle_steps(scvs_mesh m, Pool& P, const Batch& br, const PrecondArgs& pa, i
     bj.insc_idx = 0;
     VArg vj{Vv.p + (int64_t)j * P.ld, Vv.st};
     VArg vn{Vv.p + (int64_t)(j + 1) * P.ld, Vv.st};
-    precond_apply(m, bj, pa, vj, P.Z(), s);
-    if (pa.mixed)
-      spmv_apply32(m, br, pa.z32, vn, s);
-    else
-      spmv_full(m, br, P.Z(), vn, SPMV_APPLY, false, VArg{}, nullptr, s);
+    precond_apply(m, bj, pa, vj, P.Z(), s, P.zil.p);
+    spmv_apply_il(m, br, P.zil.p, pa.mixed != 0, vn, s);
     {
       ProfScope ps(prof, s, "k_dots1", vec * (j + 2));  // V_0..V_j and w once
       k_dots<1><<<gr, RBS, 0, s>>>(a, j);
@@ -766,6 +767,7 @@ int solve_systems(scvs_mesh m, int64_t nsys, const double* omega, const double* 
   P.act_all.alloc(B);
   P.act_run.alloc(B);
   P.stops.alloc(B);
+  P.zil.alloc(mixed ? ((size_t)B * P.ld + 1) / 2 : (size_t)B * P.ld);
   P.trac.alloc((size_t)B * std::max(ntr, 1));
   PrecondArgs pa;
   pa.kv = o->cheb_vel;

@@ -212,10 +212,11 @@ __device__ __forceinline__ void row_acc(const MeshArgs& ma, int W, int li, int64
 }
 
 // acc += s * sum_{jj < nvc} G^c[row prefix] p[col] over the vertex-column prefix of a row
-// (G in precision R, pressure values of complex type P, accumulation in R).
+// (G in precision R, pressure values of complex type P at p[col * pst + poff],
+// accumulation in R).
 template <int D, class R, class P>
-__device__ __forceinline__ void g_acc(const MeshArgs& ma, int64_t A, int64_t j0, const P* __restrict__ p, int c,
-                                      R s, typename Prec<R>::C& acc) {
+__device__ __forceinline__ void g_acc(const MeshArgs& ma, int64_t A, int64_t j0, const P* __restrict__ p,
+                                      int64_t pst, int poff, int c, R s, typename Prec<R>::C& acc) {
   const int nvr = ma.nvc[A];
   const R* __restrict__ Gc = Prec<R>::G(ma) + (int64_t)c * ma.nnz21 + ma.rowptr21[A];
   const int32_t* __restrict__ cl = ma.col + j0;
@@ -229,7 +230,7 @@ __device__ __forceinline__ void g_acc(const MeshArgs& ma, int64_t A, int64_t j0,
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       g[u] = Gc[jj + u];
-      pv[u] = p[B[u]];
+      pv[u] = p[(int64_t)B[u] * pst + poff];
     }
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
@@ -238,16 +239,20 @@ __device__ __forceinline__ void g_acc(const MeshArgs& ma, int64_t A, int64_t j0,
     }
   }
   for (; jj < nvr; ++jj) {
-    const P pv = p[cl[jj]];
+    const P pv = p[(int64_t)cl[jj] * pst + poff];
     acc.x += s * Gc[jj] * (R)pv.x;
     acc.y += s * Gc[jj] * (R)pv.y;
   }
 }
 
-template <int D, int MODE, bool MASK, class R>
+// With IL the input is the interleaved vector xil written by the preconditioner inside a
+// cycle: velocity pair p of node A at xil[A*G + p], pressure of system si at vertex v at
+// xil[n2*G + v*nact + si] (G = nact*D pairs); x is then unused.
+template <int D, int MODE, bool MASK, class R, bool IL = false>
 __global__ void __launch_bounds__(256) k_full(MeshArgs ma, Batch b, LaneMap lm, typename Prec<R>::V x, VArg y,
                                               VArg f, const double* __restrict__ loads, int ntr,
-                                              const double2* __restrict__ trac) {
+                                              const double2* __restrict__ trac,
+                                              const typename Prec<R>::C* __restrict__ xil = nullptr) {
   using C = typename Prec<R>::C;
   const Lane L = lane_of(lm, ma.n2);
   if (!L.rowok) return;  // uniform over the row group
@@ -261,16 +266,24 @@ __global__ void __launch_bounds__(256) k_full(MeshArgs ma, Batch b, LaneMap lm, 
     const int si = ok ? p / D : 0, c = ok ? p % D : 0;
     const int slot = b.act[si];
     const double sc = in_scale(b, slot);
-    const C* __restrict__ xs = x.at(slot);
+    const C* __restrict__ xs = IL ? xil : x.at(slot);
+    const int64_t xst = IL ? lm.G : D;
+    const int xo = IL ? p : c;
     const R wr = (R)(b.omega[slot] * ma.rho);
     C au = czero<C>(), ap = czero<C>();
     if (dm == 0 || isv)
-      row_acc<D, MASK, R>(ma, lm.W, L.li, j0, j1, xs, D, c, c, ok, (R)0, wr, dm == 0, isv, au, ap);
+      row_acc<D, MASK, R>(ma, lm.W, L.li, j0, j1, xs, xst, xo, c, ok, (R)0, wr, dm == 0, isv, au, ap);
     if (ok) {
-      if (dm == 0) g_acc<D, R, C>(ma, A, j0, xs + D * ma.n2, c, (R)1, au);
+      if (dm == 0) {
+        if (IL)
+          g_acc<D, R, C>(ma, A, j0, xil + ma.n2 * lm.G, b.nact, si, c, (R)1, au);
+        else
+          g_acc<D, R, C>(ma, A, j0, xs + D * ma.n2, 1, 0, c, (R)1, au);
+      }
       double2 yu;
       if (dm != 0) {
-        yu = make_double2(sc * (double)xs[A * D + c].x, sc * (double)xs[A * D + c].y);
+        const C xv = xs[A * xst + xo];
+        yu = make_double2(sc * (double)xv.x, sc * (double)xv.y);
         if (MODE == SPMV_RESID) yu = csub(f.at(slot)[A * D + c], yu);
       } else {
         const double2 a = make_double2(sc * (double)au.x, sc * (double)au.y);
@@ -341,10 +354,12 @@ struct ITemps {
 
 // In FP32 mode the output z is the FP32 vector z32 (velocity part written
 // here, pressure part copied from the FP64 Schur-block result zp).
+// With zil the result goes to the interleaved vector read by the next operator product
+// (layout of k_full's IL input); the pressure part is copied there too.
 template <int D, class R>
 __global__ void __launch_bounds__(256) k_vinit(MeshArgs ma, Batch b, LaneMap lm, VArg v, VArg zp64,
                                                typename Prec<R>::V z, ITemps<typename Prec<R>::C> vt,
-                                               double ratio, int kv) {
+                                               double ratio, int kv, typename Prec<R>::C* __restrict__ zil) {
   using C = typename Prec<R>::C;
   const Lane L = lane_of(lm, ma.n2);
   for (int it = 0; it < lm.iters; ++it) {
@@ -355,14 +370,17 @@ __global__ void __launch_bounds__(256) k_vinit(MeshArgs ma, Batch b, LaneMap lm,
     const int64_t A = L.row, DN = D * ma.n2;
     const int64_t k = A * D + c, ki = A * lm.G + p;
     C* __restrict__ bb = vt.arr(0);
-    C* __restrict__ x1 = (kv == 1) ? z.at(slot) + k : vt.iter(1) + ki;
+    C* __restrict__ x1 = (kv == 1) ? (zil ? zil + ki : z.at(slot) + k) : vt.iter(1) + ki;
     const double2* __restrict__ zp = zp64.at(slot) + DN;
-    if (sizeof(R) == 4 && A < ma.nv && c == 0) {
+    if ((zil || sizeof(R) == 4) && A < ma.nv && c == 0) {
       const double2 q = zp[A];
       C qq;
       qq.x = (R)q.x;
       qq.y = (R)q.y;
-      z.at(slot)[DN + A] = qq;
+      if (zil)
+        zil[ma.n2 * lm.G + A * b.nact + si] = qq;
+      else
+        z.at(slot)[DN + A] = qq;
     }
     if (ma.dmask[A] != 0) {
       bb[ki] = *x1 = czero<C>();
@@ -373,7 +391,7 @@ __global__ void __launch_bounds__(256) k_vinit(MeshArgs ma, Batch b, LaneMap lm,
     C t;
     t.x = (R)(sc * vv.x);
     t.y = (R)(sc * vv.y);
-    g_acc<D, R, double2>(ma, A, ma.rowptr[A], zp, c, (R)-1, t);
+    g_acc<D, R, double2>(ma, A, ma.rowptr[A], zp, 1, 0, c, (R)-1, t);
     const double lmax = b.lv[slot];
     const R theta = (R)(0.5 * lmax * (1.0 + 1.0 / ratio));
     const R dinv = (R)1 / ((R)ma.mu * Prec<R>::Kd(ma)[A] + (R)(fabs(b.omega[slot]) * ma.rho) * Prec<R>::Md(ma)[A]);
@@ -387,7 +405,8 @@ __global__ void __launch_bounds__(256) k_vinit(MeshArgs ma, Batch b, LaneMap lm,
 
 template <int D, class R>
 __global__ void __launch_bounds__(256) k_vstep(MeshArgs ma, Batch b, LaneMap lm, typename Prec<R>::V z,
-                                               ITemps<typename Prec<R>::C> vt, double ratio, int step, int last) {
+                                               ITemps<typename Prec<R>::C> vt, double ratio, int step, int last,
+                                               typename Prec<R>::C* __restrict__ zil) {
   using C = typename Prec<R>::C;
   const Lane L = lane_of(lm, ma.n2);
   if (!L.rowok) return;  // uniform over the row group
@@ -401,7 +420,7 @@ __global__ void __launch_bounds__(256) k_vstep(MeshArgs ma, Batch b, LaneMap lm,
     const int si = ok ? p / D : 0, c = ok ? p % D : 0;
     const int slot = b.act[si];
     const int64_t ki = A * lm.G + p;
-    C* __restrict__ xn = last ? z.at(slot) + A * D + c : vt.iter(step + 1) + ki;
+    C* __restrict__ xn = last ? (zil ? zil + ki : z.at(slot) + A * D + c) : vt.iter(step + 1) + ki;
     if (dir) {
       if (ok) *xn = czero<C>();
       continue;
@@ -578,9 +597,25 @@ void full_launch32(Profiler* prof, const MeshArgs& ma, const Batch& b, VArg32 x,
   launch_check(s);
 }
 
+// y = A x for the interleaved preconditioner output (FP64 or FP32 values by R).
+template <int D, class R>
+void full_launch_il(Profiler* prof, const MeshArgs& ma, const Batch& b, const typename Prec<R>::C* xil, VArg y,
+                    hipStream_t s) {
+  const LaneMap lm = lane_map(b.nact, D);
+  const unsigned nb = row_blocks(ma.n2, lm);
+  const double vb = sizeof(R);  // bytes per real matrix value
+  const double mat = (double)ma.nnz * (4.0 + 2.0 * vb) + (double)ma.nnz21 * (4.0 + vb * D) +
+                     (double)ma.nnzv * vb * D + (double)ma.n2 * 24.0;
+  const double ndof = (double)D * ma.n2 + ma.nv;
+  ProfScope ps(prof, s, sizeof(R) == 4 ? "k_full_apply32" : "k_full_apply", mat + b.nact * ndof * (2.0 * vb + 16.0));
+  k_full<D, SPMV_APPLY, false, R, true><<<nb, 256, 0, s>>>(ma, b, lm, typename Prec<R>::V{}, y, VArg{}, nullptr, 0,
+                                                           nullptr, xil);
+  launch_check(s);
+}
+
 template <int D>
 void precond_launch(Profiler* prof, const MeshArgs& ma, const Batch& b, const PrecondArgs& pa, VArg v, VArg z,
-                    hipStream_t s) {
+                    void* zil, hipStream_t s) {
   const LaneMap lm = lane_map(b.nact, D), lp = lane_map(b.nact, 1);
   const unsigned nbu = row_blocks(ma.n2, lm), nbp = row_blocks(ma.nv, lp);
   const double n2 = (double)ma.n2, nv = (double)ma.nv, DN = (double)D * ma.n2, na = b.nact;
@@ -610,18 +645,18 @@ void precond_launch(Profiler* prof, const MeshArgs& ma, const Batch& b, const Pr
                  (double)ma.nnz21 * (4.0 + vs * D) + n2 * (24.0 + 2.0 * vs) +
                      na * (DN * 16.0 + nv * 16.0 + 2.0 * DN * es + (pa.mixed ? nv * es : 0.0)));
     if (pa.mixed)
-      k_vinit<D, float><<<nbu, 256, 0, s>>>(ma, b, lm, v, z, pa.z32, it32, pa.ratio, pa.kv);
+      k_vinit<D, float><<<nbu, 256, 0, s>>>(ma, b, lm, v, z, pa.z32, it32, pa.ratio, pa.kv, (float2*)zil);
     else
-      k_vinit<D, double><<<nbu, 256, 0, s>>>(ma, b, lm, v, z, z, it64, pa.ratio, pa.kv);
+      k_vinit<D, double><<<nbu, 256, 0, s>>>(ma, b, lm, v, z, z, it64, pa.ratio, pa.kv, (double2*)zil);
   }
   // S2 col/Ks/M, rowptr/dmask/Kd/Md; per system x_k (gathered, read once), b, x_{k-1} read, x_{k+1} written
   const double vbytes = (double)ma.nnz * (4.0 + 2.0 * vs) + n2 * (12.0 + 2.0 * vs) + na * 4.0 * DN * es;
   for (int i = 1; i < pa.kv; ++i) {
     ProfScope ps(prof, s, pa.mixed ? "k_vstep32" : "k_vstep", vbytes);
     if (pa.mixed)
-      k_vstep<D, float><<<nbu, 256, 0, s>>>(ma, b, lm, pa.z32, it32, pa.ratio, i, i == pa.kv - 1);
+      k_vstep<D, float><<<nbu, 256, 0, s>>>(ma, b, lm, pa.z32, it32, pa.ratio, i, i == pa.kv - 1, (float2*)zil);
     else
-      k_vstep<D, double><<<nbu, 256, 0, s>>>(ma, b, lm, z, it64, pa.ratio, i, i == pa.kv - 1);
+      k_vstep<D, double><<<nbu, 256, 0, s>>>(ma, b, lm, z, it64, pa.ratio, i, i == pa.kv - 1, (double2*)zil);
   }
   launch_check(s);
 }
@@ -643,12 +678,27 @@ void spmv_full(scvs_mesh m, const Batch& b, VArg x, VArg y, int mode, bool maskc
     full_launch<3>(&m->ctx->prof, ma, b, x, y, mode, maskcol, f, m->loads, ntr, trac, s);
 }
 
-void precond_apply(scvs_mesh m, const Batch& b, const PrecondArgs& pa, VArg v, VArg z, hipStream_t s) {
+void precond_apply(scvs_mesh m, const Batch& b, const PrecondArgs& pa, VArg v, VArg z, hipStream_t s, void* zil) {
   const MeshArgs ma = mesh_args(m);
   if (m->dim == 2)
-    precond_launch<2>(&m->ctx->prof, ma, b, pa, v, z, s);
+    precond_launch<2>(&m->ctx->prof, ma, b, pa, v, z, zil, s);
   else
-    precond_launch<3>(&m->ctx->prof, ma, b, pa, v, z, s);
+    precond_launch<3>(&m->ctx->prof, ma, b, pa, v, z, zil, s);
+}
+
+void spmv_apply_il(scvs_mesh m, const Batch& b, const void* xil, bool fp32, VArg y, hipStream_t s) {
+  const MeshArgs ma = mesh_args(m);
+  if (m->dim == 2) {
+    if (fp32)
+      full_launch_il<2, float>(&m->ctx->prof, ma, b, (const float2*)xil, y, s);
+    else
+      full_launch_il<2, double>(&m->ctx->prof, ma, b, (const double2*)xil, y, s);
+  } else {
+    if (fp32)
+      full_launch_il<3, float>(&m->ctx->prof, ma, b, (const float2*)xil, y, s);
+    else
+      full_launch_il<3, double>(&m->ctx->prof, ma, b, (const double2*)xil, y, s);
+  }
 }
 
 void spmv_apply32(scvs_mesh m, const Batch& b, VArg32 x, VArg y, hipStream_t s) {
