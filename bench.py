@@ -48,6 +48,8 @@ def parse():
     ap.add_argument("--cheb-pres", type=int, default=50)
     ap.add_argument("--ntimes", type=int, default=64)
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="mixed")
+    ap.add_argument("--orth", type=int, choices=[0, 1], default=1,
+                    help="0: two-pass classical Gram-Schmidt, 1: lagged second pass (DCGS2)")
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the plain per-mode FP64 GMRES comparator step")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -132,7 +134,7 @@ def main():
     pt = torch.empty((args.ntimes, info.nv), dtype=torch.float64, device="cuda")
     opts = scvs.default_opts(rtol=args.rtol, restart=args.restart, cheb_vel=args.cheb_vel,
                              cheb_pres=args.cheb_pres, verbose=1 if args.verbose else 0,
-                             precision=1 if args.precision == "mixed" else 0)
+                             precision=1 if args.precision == "mixed" else 0, orth=args.orth)
     log(f"n2={info.n2} ndof={info.ndof} nnz_s2={info.nnz_s2} ingest+assembly {t_ingest:.2f}s")
 
     def step():
@@ -193,7 +195,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"pipe R=1 L=10, {mesh.nc} curved P2/P1 tets, {ns} modes (16 harmonics + mean)",
                    "ndof": int(info.ndof), "modes": ns, "rtol": args.rtol, "restart": args.restart,
-                   "cheb_vel": args.cheb_vel, "cheb_pres": args.cheb_pres, "ntimes": args.ntimes},
+                   "cheb_vel": args.cheb_vel, "cheb_pres": args.cheb_pres, "orth": args.orth,
+                   "ntimes": args.ntimes},
         "dof_modes_per_s": info.ndof * ns * args.steps / dt,
         "roofline": roof(dominant),
         "spmv_roofline": roof("k_full_apply32" if "k_full_apply32" in stats else "k_full_apply"),
@@ -203,9 +206,9 @@ def main():
     }
     if not args.no_compare:
         # comparator: plain per-mode FP64 GMRES (one system at a time, same
-        # preconditioner, restart and tolerance, no graph batching)
+        # preconditioner, restart and tolerance, two-pass Gram-Schmidt)
         plain = scvs.default_opts(rtol=args.rtol, restart=args.restart, cheb_vel=args.cheb_vel,
-                                  cheb_pres=args.cheb_pres, precision=0, max_batch=1,
+                                  cheb_pres=args.cheb_pres, precision=0, max_batch=1, orth=0,
                                   verbose=1 if args.verbose else 0)
         u2 = torch.empty_like(u)
         p2 = torch.empty_like(p)

@@ -187,10 +187,15 @@ typedef struct {
                          recomputed at every restart (iterative refinement), the Arnoldi
                          orthogonalization, Givens/least-squares, the pressure Schur block
                          and the solution update stay FP64 */
+  int32_t orth;       /* 0: classical Gram-Schmidt, second pass when the first loses more than
+                         30% of the norm (three passes over the basis per step). 1: the second
+                         pass of each vector lagged into the next step's single reduction
+                         (DCGS2, Swirydowicz et al. 2020; two passes per step, one extra
+                         closing reduction per cycle) */
 } scvs_solve_opts;
 
 /* Fill `o` with the defaults (rtol 1e-10, m 200, 20000 iterations, degrees 10/50,
- * ratio 30, batch 0, graphs on, FP64). */
+ * ratio 30, batch 0, graphs on, FP64, lagged orthogonalization). */
 void scvs_solve_opts_default(scvs_solve_opts* o);
 
 typedef struct {

@@ -23,7 +23,7 @@ namespace scvs {
 namespace {
 
 constexpr int MM = SCVS_MMAX;
-constexpr int PSTRIDE = MM + 2;  // partial sums per (slot, chunk)
+constexpr int PSTRIDE = 2 * MM + 4;  // partial sums per (slot, chunk)
 constexpr int RBS = 256;         // reduction block size
 constexpr int JB = 8;            // basis vectors per accumulation group
 
@@ -35,6 +35,9 @@ struct SlotState {
   double2 y[MM];
   double2 h1[MM + 1], h2[MM + 1];
   double hs[MM + 1];  // scale of stored basis vector i (V_i is kept unnormalized)
+  double2 Hu[(MM + 1) * MM];  // unrotated Hessenberg matrix (lagged orthogonalization)
+  double2 gq;                 // lagged: <q_j, W>
+  double sig, rho;            // lagged: norm of the reorthogonalized u_j; norm of the last first-pass vector
   double nrm0, fnorm, tolabs, beta;
   int jstop, skip2, nonfinite, lastJ;
   unsigned int ticket[8];
@@ -160,22 +163,19 @@ __global__ void __launch_bounds__(RBS) k_dots(KArgs a, int j) {
   }
 }
 
-// Column j of the Hessenberg matrix is final: apply the earlier rotations,
-// form the new one, update the residual estimate and decide whether the
-// system stops within this cycle.
-__device__ void finalize_column(SlotState& st, int j, double nrm, bool second) {
+// Column j of the Hessenberg matrix (entries 0..j in col, subdiagonal nrm) is final:
+// apply the earlier rotations, form the new one, update the residual estimate and
+// decide whether the system stops within this cycle. Returns false when the column
+// is not finite (the system then stops with the columns before j).
+__device__ bool givens_column(SlotState& st, int j, double nrm) {
   double2* col = st.H + (MM + 1) * j;
   double hn2 = nrm * nrm;
-  for (int i = 0; i <= j; ++i) {
-    col[i] = second ? cadd(st.h1[i], st.h2[i]) : st.h1[i];
-    hn2 += col[i].x * col[i].x + col[i].y * col[i].y;
-  }
+  for (int i = 0; i <= j; ++i) hn2 += col[i].x * col[i].x + col[i].y * col[i].y;
   col[j + 1] = make_double2(nrm, 0.0);
   if (!(isfinite(hn2))) {
     st.nonfinite = 1;
     st.jstop = j;
-    st.hs[j + 1] = 0.0;
-    return;
+    return false;
   }
   for (int i = 0; i < j; ++i) {
     const double2 a = col[i], b = col[i + 1];
@@ -214,6 +214,17 @@ __device__ void finalize_column(SlotState& st, int j, double nrm, bool second) {
   const double res = hypot(st.gam[j + 1].x, st.gam[j + 1].y);
   const bool breakdown = nrm <= 1e-13 * sqrt(hn2);
   if (res <= st.tolabs || breakdown) st.jstop = j + 1;
+  return true;
+}
+
+// Column j from the Gram-Schmidt coefficients (h1, plus h2 after a second pass).
+__device__ void finalize_column(SlotState& st, int j, double nrm, bool second) {
+  double2* col = st.H + (MM + 1) * j;
+  for (int i = 0; i <= j; ++i) col[i] = second ? cadd(st.h1[i], st.h2[i]) : st.h1[i];
+  if (!givens_column(st, j, nrm)) {
+    st.hs[j + 1] = 0.0;
+    return;
+  }
   st.hs[j + 1] = (st.jstop < 0 && nrm > 0.0) ? 1.0 / nrm : 0.0;
 }
 
@@ -400,6 +411,235 @@ __global__ void __launch_bounds__(RBS) k_upd_dots(KArgs a, int j) {
   if (t == 0) {
     st.skip2 = skip ? 1 : 0;
     if (skip) finalize_column(st, j, nrm, false);
+  }
+}
+
+// ---- Lagged classical Gram-Schmidt with reorthogonalization (DCGS2) ----
+// (Swirydowicz, Langou, Ananthan, Yang, Thomas, 2020.) Step j starts from
+// u = hs_j V_j, orthogonalized once against q_0..q_{j-1}, and W = A P^-1 u in V_{j+1}.
+// Pass 1 (k_lag_dots) forms S_i = <V_i, V_j> and A_i = <V_i, W>, i <= j, in one read.
+// Its last workgroup then
+//   * reorthogonalizes u on paper: s_i = <q_i, u>, sigma^2 = |u|^2 - |s|^2, so that
+//     u = Q s + sigma q_j, and completes column j-1 (its first-pass part plus rho s,
+//     subdiagonal rho sigma, rho being |u|'s first-pass norm) and its Givens rotation;
+//   * derives the projections of A P^-1 q_j = (W - [Q q_j] H s) / sigma without touching
+//     the vectors: with a_i = <q_i, W> and gamma = <q_j, W> = (<u, W> - s^H a) / sigma,
+//     column j's first-pass part is ([a; gamma] - H s) / sigma.
+// Pass 2 (k_lag_update) writes q_j = (u - Q s) / sigma over V_j and the next first-pass
+// vector (W - Q a - gamma q_j) / sigma over V_{j+1}, sharing one read of the basis, and
+// its norm rho_j. After the last step one more pass 1 (final) completes the last column.
+constexpr int VS2 = TILE + MM + 2 + 64;
+__global__ void __launch_bounds__(RBS) k_lag_dots(KArgs a, int j, int final) {
+  static_assert((RBS / 64) * 2 * (MM + 1) <= VS2, "partials reuse the tile buffer");
+  __shared__ double2 vs[VS2];
+  const int slot = a.act[blockIdx.y];
+  SlotState& st = a.st[slot];
+  if (st.jstop >= 0) return;
+  const int t = threadIdx.x;
+  const int nrow = final ? j + 1 : j + 2;  // V_0..V_j, and W = V_{j+1}
+  int tn = 32;
+  while (tn > 4 && nrow * tn > TILE) tn >>= 1;
+  const int tp = tn + 1;
+  int64_t b0, b1;
+  chunk_range(a, b0, b1);
+  const double2* __restrict__ V0 = vec(a, slot, 0);
+  const int di = t & 63, dq = t >> 6, qlen = tn / 4;
+  double2 accS[NDG], accA[NDG];
+#pragma unroll
+  for (int g = 0; g < NDG; ++g) accS[g] = accA[g] = make_double2(0.0, 0.0);
+  constexpr int PF = TILE / RBS;
+  const int nld = nrow * tn;
+  double2 pre[PF];
+  auto fetch = [&](int64_t nb) {
+    const int len = (int)min((int64_t)tn, b1 - nb);
+#pragma unroll
+    for (int k = 0; k < PF; ++k) {
+      const int q = t + k * RBS, i = q / tn, e = q % tn;
+      pre[k] = (q < nld && e < len) ? V0[(int64_t)i * a.ld + nb + e] : make_double2(0.0, 0.0);
+    }
+  };
+  if (b0 < b1) fetch(b0);
+  for (int64_t nb = b0; nb < b1; nb += tn) {
+    __syncthreads();  // previous tile consumed
+#pragma unroll
+    for (int k = 0; k < PF; ++k) {
+      const int q = t + k * RBS;
+      if (q < nld) vs[(q / tn) * tp + q % tn] = pre[k];
+    }
+    __syncthreads();
+    if (nb + tn < b1) fetch(nb + tn);
+    for (int e = dq * qlen; e < (dq + 1) * qlen; ++e) {
+      const double2 uv = vs[j * tp + e];
+      const double2 wv = final ? make_double2(0.0, 0.0) : vs[(j + 1) * tp + e];
+#pragma unroll
+      for (int g = 0; g < NDG; ++g)
+        if (di + 64 * g <= j) {
+          const double2 v = vs[(di + 64 * g) * tp + e];
+          accS[g].x += v.x * uv.x + v.y * uv.y;
+          accS[g].y += v.x * uv.y - v.y * uv.x;
+          accA[g].x += v.x * wv.x + v.y * wv.y;
+          accA[g].y += v.x * wv.y - v.y * wv.x;
+        }
+    }
+  }
+  double2* red = vs;  // [RBS/64][2(MM+1)]
+  const int R2 = 2 * (MM + 1);
+  __syncthreads();
+#pragma unroll
+  for (int g = 0; g < NDG; ++g)
+    if (di + 64 * g <= j) {
+      red[dq * R2 + 2 * (di + 64 * g)] = accS[g];
+      red[dq * R2 + 2 * (di + 64 * g) + 1] = accA[g];
+    }
+  __syncthreads();
+  double2* part = a.part + ((int64_t)slot * a.nch + blockIdx.x) * PSTRIDE;
+  for (int i = t; i < 2 * (j + 1); i += RBS) {
+    double2 sum = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int q = 0; q < RBS / 64; ++q) sum = cadd(sum, red[q * R2 + i]);
+    part[i] = sum;
+  }
+  if (!last_block(&st.ticket[0], a.nch)) return;
+  // ---- last workgroup: fixed-order sums over the chunks, then the scalar work ----
+  double2* S = vs;            // [MM+1]
+  double2* Av = vs + MM + 1;  // [MM+1]
+  __shared__ double sh_sig, sh_rho;
+  __shared__ int sh_go;
+  for (int i = t; i <= j; i += RBS) {
+    double2 s0 = make_double2(0.0, 0.0), s1 = make_double2(0.0, 0.0);
+    for (int c = 0; c < a.nch; ++c) {
+      const double2* pc = a.part + ((int64_t)slot * a.nch + c) * PSTRIDE;
+      s0 = cadd(s0, pc[2 * i]);
+      s1 = cadd(s1, pc[2 * i + 1]);
+    }
+    S[i] = s0;
+    Av[i] = s1;
+  }
+  __syncthreads();
+  const double hsj = st.hs[j];
+  // s_i = <q_i, u> (i < j) into h1, a_i = <q_i, W> into h2
+  for (int i = t; i < j; i += RBS) {
+    st.h1[i] = cscale(S[i], st.hs[i] * hsj);
+    if (!final) st.h2[i] = cscale(Av[i], st.hs[i]);
+  }
+  __syncthreads();
+  if (t == 0) {
+    double ss = 0.0;
+    for (int i = 0; i < j; ++i) ss += st.h1[i].x * st.h1[i].x + st.h1[i].y * st.h1[i].y;
+    const double nu = hsj * hsj * S[j].x;
+    const double sg2 = nu - ss;
+    const double sig = sg2 > 1e-28 * nu ? sqrt(sg2) : 0.0;
+    sh_sig = sig;
+    sh_rho = st.rho;
+    sh_go = 1;
+  }
+  __syncthreads();
+  const double sig = sh_sig, rho = sh_rho;
+  if (j > 0) {
+    // complete column j-1 and rotate it
+    double2* hu = st.Hu + (MM + 1) * (j - 1);
+    for (int i = t; i < j; i += RBS) hu[i] = cadd(hu[i], cscale(st.h1[i], rho));
+    __syncthreads();
+    if (t == 0) {
+      hu[j] = make_double2(rho * sig, 0.0);
+      double2* col = st.H + (MM + 1) * (j - 1);
+      for (int i = 0; i < j; ++i) col[i] = hu[i];
+      givens_column(st, j - 1, rho * sig);
+      if (st.jstop >= 0 || final || !(sig > 0.0)) {
+        if (st.jstop < 0) st.jstop = j;  // u in the span of Q: the space is invariant
+        sh_go = 0;
+      }
+    }
+    __syncthreads();
+  } else if (t == 0 && !(sig > 0.0)) {
+    st.jstop = 0;
+    sh_go = 0;
+  }
+  if (final) return;
+  __syncthreads();
+  if (!sh_go) return;
+  // gamma = (<u, W> - s^H a) / sigma, then column j's first-pass part ([a; gamma] - H s) / sigma
+  __shared__ double2 sh_g;
+  if (t == 0) {
+    double2 g = cscale(Av[j], hsj);
+    for (int i = 0; i < j; ++i) {
+      const double2 si = st.h1[i], ai = st.h2[i];
+      g.x -= si.x * ai.x + si.y * ai.y;
+      g.y -= si.x * ai.y - si.y * ai.x;
+    }
+    g = cscale(g, 1.0 / sig);
+    sh_g = g;
+    st.gq = g;
+    st.sig = sig;
+  }
+  __syncthreads();
+  double2* huj = st.Hu + (MM + 1) * j;
+  for (int r = t; r <= j; r += RBS) {
+    double2 c = r < j ? st.h2[r] : sh_g;
+    for (int i = (r > 0 ? r - 1 : 0); i < j; ++i) c = csub(c, cmul(st.Hu[(MM + 1) * i + r], st.h1[i]));
+    huj[r] = cscale(c, 1.0 / sig);
+  }
+}
+
+// Pass 2 of a lagged step: q_j over V_j, the next first-pass vector over V_{j+1}, and its norm.
+__global__ void __launch_bounds__(RBS) k_lag_update(KArgs a, int j) {
+  __shared__ double2 cq[MM + 1], cw[MM + 1];
+  __shared__ double2 sh[RBS / 64];
+  const int slot = a.act[blockIdx.y];
+  SlotState& st = a.st[slot];
+  if (st.jstop >= 0) return;
+  for (int i = threadIdx.x; i < j; i += RBS) {
+    cq[i] = cscale(st.h1[i], st.hs[i]);
+    cw[i] = cscale(st.h2[i], st.hs[i]);
+  }
+  __syncthreads();
+  const double hsj = st.hs[j], inv = 1.0 / st.sig;
+  const double2 gq = st.gq;
+  int64_t b0, b1;
+  chunk_range(a, b0, b1);
+  double2* __restrict__ u = vec(a, slot, j);
+  double2* __restrict__ w = vec(a, slot, j + 1);
+  const double2* __restrict__ V0 = vec(a, slot, 0);
+  double2 acc[1] = {make_double2(0.0, 0.0)};
+  for (int64_t n = b0 + threadIdx.x; n < b1; n += RBS) {
+    double2 sq = make_double2(0.0, 0.0), sw = make_double2(0.0, 0.0);
+    for (int i = 0; i < j; ++i) {
+      const double2 v = V0[(int64_t)i * a.ld + n];
+      sq = cadd(sq, cmul(cq[i], v));
+      sw = cadd(sw, cmul(cw[i], v));
+    }
+    const double2 uv = u[n], wv = w[n];
+    const double2 q = cscale(csub(cscale(uv, hsj), sq), inv);
+    const double2 wn = cscale(csub(csub(wv, sw), cmul(gq, q)), inv);
+    u[n] = q;
+    w[n] = wn;
+    acc[0].x += wn.x * wn.x + wn.y * wn.y;
+  }
+  const double2 r = block_sum<1>(acc, sh);
+  double2* part = a.part + ((int64_t)slot * a.nch + blockIdx.x) * PSTRIDE;
+  if (threadIdx.x == 0) part[MM + 1] = r;
+  if (!last_block(&st.ticket[1], a.nch)) return;
+  if (threadIdx.x == 0) {
+    double sn = 0.0;
+    for (int c = 0; c < a.nch; ++c) sn += a.part[((int64_t)slot * a.nch + c) * PSTRIDE + MM + 1].x;
+    const double rho = sqrt(sn);
+    st.hs[j] = 1.0;
+    double2* huj = st.Hu + (MM + 1) * j;
+    double hn2 = 0.0;
+    for (int i = 0; i <= j; ++i) hn2 += huj[i].x * huj[i].x + huj[i].y * huj[i].y;
+    if (!(rho > 1e-13 * sqrt(hn2)) || !isfinite(rho)) {
+      // the new direction vanished: column j is final with a zero subdiagonal
+      double2* col = st.H + (MM + 1) * j;
+      for (int i = 0; i <= j; ++i) col[i] = huj[i];
+      givens_column(st, j, 0.0);
+      if (st.jstop < 0) st.jstop = j + 1;
+      st.hs[j + 1] = 0.0;
+      st.rho = 0.0;
+    } else {
+      st.rho = rho;
+      st.hs[j + 1] = 1.0 / rho;
+      huj[j + 1] = make_double2(rho, 0.0);
+    }
   }
 }
 
@@ -611,7 +851,7 @@ KArgs kargs(Pool& P, int64_t ndof, int nch) {
 // Steps j0..j1-1 of a restart cycle for the systems of `br` that are still running
 // (a system that stops inside the chunk makes its later Arnoldi launches return at once).
 void cycle_steps(scvs_mesh m, Pool& P, const Batch& br, const PrecondArgs& pa, int64_t ndof, int j0, int j1,
-                 hipStream_t s) {
+                 bool lagged, hipStream_t s) {
   const int nact = br.nact;
   const int nch = choose_nch(nact, ndof);
   KArgs a = kargs(P, ndof, nch);
@@ -629,17 +869,28 @@ void cycle_steps(scvs_mesh m, Pool& P, const Batch& br, const PrecondArgs& pa, i
     VArg vn{Vv.p + (int64_t)(j + 1) * P.ld, Vv.st};
     precond_apply(m, bj, pa, vj, P.Z(), s, P.zil.p);
     spmv_apply_il(m, br, P.zil.p, pa.mixed != 0, vn, s);
-    {
-      ProfScope ps(prof, s, "k_dots1", vec * (j + 2));  // V_0..V_j and w once
-      k_dots<1><<<gr, RBS, 0, s>>>(a, j);
-    }
-    {
-      ProfScope ps(prof, s, "k_upd_dots", vec * (j + 3));  // V_0..V_j and w read, w written
-      k_upd_dots<<<gr, RBS, 0, s>>>(a, j);
-    }
-    {
-      ProfScope ps(prof, s, "k_update2", vec * (j + 3));
-      k_update<2><<<gr, RBS, 0, s>>>(a, j);
+    if (lagged) {
+      {
+        ProfScope ps(prof, s, "k_lag_dots", vec * (j + 2));  // V_0..V_j and W once
+        k_lag_dots<<<gr, RBS, 0, s>>>(a, j, 0);
+      }
+      {
+        ProfScope ps(prof, s, "k_lag_update", vec * (j + 4));  // V_0..V_j and W read, V_j and W written
+        k_lag_update<<<gr, RBS, 0, s>>>(a, j);
+      }
+    } else {
+      {
+        ProfScope ps(prof, s, "k_dots1", vec * (j + 2));  // V_0..V_j and w once
+        k_dots<1><<<gr, RBS, 0, s>>>(a, j);
+      }
+      {
+        ProfScope ps(prof, s, "k_upd_dots", vec * (j + 3));  // V_0..V_j and w read, w written
+        k_upd_dots<<<gr, RBS, 0, s>>>(a, j);
+      }
+      {
+        ProfScope ps(prof, s, "k_update2", vec * (j + 3));
+        k_update<2><<<gr, RBS, 0, s>>>(a, j);
+      }
     }
     launch_check(s);
   }
@@ -653,7 +904,7 @@ __global__ void k_stops(const SlotState* __restrict__ st, const int* __restrict_
 // End of a restart cycle for the systems of `b` (all that started it): least squares,
 // x += P^-1 V y, and the new true residual.
 void cycle_end(scvs_mesh m, Pool& P, const Batch& b, const PrecondArgs& pa, int64_t ndof, double rtol,
-               hipStream_t s) {
+               bool lagged, hipStream_t s) {
   const int nact = b.nact;
   const int nch = choose_nch(nact, ndof);
   KArgs a = kargs(P, ndof, nch);
@@ -662,6 +913,11 @@ void cycle_end(scvs_mesh m, Pool& P, const Batch& b, const PrecondArgs& pa, int6
   const VArg Vv{P.V.p, (int64_t)(P.m + 1) * P.ld};
   Profiler* prof = &m->ctx->prof;
   const double vec = (double)ndof * 16.0 * nact;
+  if (lagged) {
+    // the last column still needs the lagged correction of V_m
+    ProfScope ps(prof, s, "k_lag_dots", vec * (P.m + 1));
+    k_lag_dots<<<gr, RBS, 0, s>>>(a, P.m, 1);
+  }
   {
     ProfScope ps(prof, s, "k_trisolve", 0.0);
     k_trisolve<<<(nact + 63) / 64, 64, 0, s>>>(a, nact);
@@ -853,6 +1109,7 @@ int solve_systems(scvs_mesh m, int64_t nsys, const double* omega, const double* 
     std::vector<int> iters(nb, 0), cycles(nb, 0), done(nb, 0);
     std::map<int, std::pair<hipGraph_t, hipGraphExec_t>> graphs;
     const int chunk = std::min(mk, 30);
+    const bool lagged = o->orth == 1;
     std::vector<int> act_prev;
     for (;;) {
       download(info.data(), P.info.p, 4 * nb, s);
@@ -921,7 +1178,7 @@ int solve_systems(scvs_mesh m, int64_t nsys, const double* omega, const double* 
         br.nact = (int)run.size();
         br.act = all ? P.act.p : P.act_run.p;
         const int key = ((all ? 0 : 1) * 4096 + br.nact) * 1024 + j0 / chunk;
-        launch(key, [&](hipStream_t st) { cycle_steps(m, P, br, pa, ndof, j0, j1, st); });
+        launch(key, [&](hipStream_t st) { cycle_steps(m, P, br, pa, ndof, j0, j1, lagged, st); });
         const bool prof_on = m->ctx->prof.on;
         if (j1 == mk && !prof_on) break;
         k_stops<<<(br.nact + 63) / 64, 64, 0, s>>>(P.st, br.act, br.nact, P.stops);
@@ -935,12 +1192,18 @@ int solve_systems(scvs_mesh m, int64_t nsys, const double* omega, const double* 
             continue;
           }
           jend[run[k]] = J;
-          // Arnoldi launches of steps J.. returned at once: take back their bytes
+          // Arnoldi launches of steps J.. returned at once (lagged: pass 2 from J, pass 1 from
+          // J + 1, since pass 1 of step J found the stop): take back their bytes
           for (int jj = std::max(J, j0); jj < j1; ++jj) {
             const double v = (double)ndof * 16.0;
-            m->ctx->prof.correct("k_dots1", -v * (jj + 2));
-            m->ctx->prof.correct("k_upd_dots", -v * (jj + 3));
-            m->ctx->prof.correct("k_update2", -v * (jj + 3));
+            if (lagged) {
+              if (jj > J) m->ctx->prof.correct("k_lag_dots", -v * (jj + 2));
+              m->ctx->prof.correct("k_lag_update", -v * (jj + 4));
+            } else {
+              m->ctx->prof.correct("k_dots1", -v * (jj + 2));
+              m->ctx->prof.correct("k_upd_dots", -v * (jj + 3));
+              m->ctx->prof.correct("k_update2", -v * (jj + 3));
+            }
           }
         }
         if (next.empty() || j1 == mk) break;
@@ -949,8 +1212,11 @@ int solve_systems(scvs_mesh m, int64_t nsys, const double* omega, const double* 
           run.swap(next);
         }
       }
-      for (int k : act) m->ctx->prof.correct("k_combine", -(double)ndof * 16.0 * (mk - jend[k]));
-      launch(-1 - na, [&](hipStream_t st) { cycle_end(m, P, bc, pa, ndof, o->rtol, st); });
+      for (int k : act) {
+        m->ctx->prof.correct("k_combine", -(double)ndof * 16.0 * (mk - jend[k]));
+        if (lagged && jend[k] < mk) m->ctx->prof.correct("k_lag_dots", -(double)ndof * 16.0 * (mk + 1));
+      }
+      launch(-1 - na, [&](hipStream_t st) { cycle_end(m, P, bc, pa, ndof, o->rtol, lagged, st); });
       for (int k : act) cycles[k]++;
     }
     for (auto& kv : graphs) {

@@ -223,3 +223,21 @@ def test_solve_mixed_matches_lu(setup):
         assert rep[s].status == 0, (s, rep[s].status, rep[s].rel_residual)
         eu, ep = rel_l2(asm, u[s], u_o[s], p[s], p_o[s])
         assert eu <= 1e-8 and ep <= 1e-8, (s, eu, ep)
+
+
+def test_orthogonalization_variants_agree(setup):
+    """Lagged (DCGS2) and classical two-pass Gram-Schmidt give the same modes."""
+    from paper_2009_06725_amd import scvs
+    c, asm, m = setup["case"], setup["asm"], setup["m"]
+    g = gpu_dirichlet(m, c, torch)
+    res = []
+    for orth in (0, 1):
+        for restart in (25, 60):
+            opts = scvs.default_opts(rtol=1e-12, orth=orth, restart=restart)
+            u, p, rep = m.solve(c["omega"], c["traction"], g, opts=opts)
+            assert all(r.status == 0 for r in rep), (orth, restart)
+            res.append((u.cpu().numpy(), p.cpu().numpy()))
+    for u, p in res[1:]:
+        for s in range(len(c["omega"])):
+            eu, ep = rel_l2(asm, u[s], res[0][0][s], p[s], res[0][1][s])
+            assert eu <= 1e-9 and ep <= 1e-9
