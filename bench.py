@@ -18,7 +18,6 @@ Prints one JSON line.
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -42,18 +41,25 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--tets", type=int, default=200000)
     ap.add_argument("--harmonics", type=int, default=16)
-    ap.add_argument("--rtol", type=float, default=1e-10)
+    ap.add_argument("--rtol", type=float, default=4e-12,
+                    help="relative residual; 4e-12 keeps the modes within 1e-8 of the reference here")
     ap.add_argument("--restart", type=int, default=200)
     ap.add_argument("--cheb-vel", type=int, default=10)
     ap.add_argument("--cheb-pres", type=int, default=50)
     ap.add_argument("--ntimes", type=int, default=64)
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="mixed")
+    ap.add_argument("--inner-rtol", type=float, default=1e-5,
+                    help="mixed precision: end a cycle once its own residual fell by this factor")
     ap.add_argument("--orth", type=int, choices=[0, 1], default=1,
                     help="0: two-pass classical Gram-Schmidt, 1: lagged second pass (DCGS2)")
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the plain per-mode FP64 GMRES comparator step")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-error-check", action="store_true",
+                    help="skip the tight-tolerance FP64 reference solve that estimates the error")
     ap.add_argument("--verbose", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run plain 1 GiB device copies (for scaling rocprofv3 byte counters)")
     return ap.parse_args()
 
 
@@ -61,25 +67,34 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def kernel_source_hash() -> str:
-    h = hashlib.sha256()
-    for f in ("spmv.hip", "krylov.hip"):
-        with open(os.path.join(ROOT, "paper_2009_06725_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
-
-
 def stored_traffic(kernel: str):
     """HBM bytes per launch from the committed rocprofv3 counter summary, or
     None when absent or taken on different kernel sources."""
+    from paper_2009_06725_amd.rocprof_summary import kernel_source_hash
     try:
         with open(TRAFFIC_FILE) as fh:
             t = json.load(fh)
     except (OSError, ValueError):
         return None
-    if t.get("kernel") != kernel or t.get("source_hash") != kernel_source_hash():
+    if t.get("source_hash") != kernel_source_hash():
         return None
-    return t.get("bytes_per_launch")
+    return t.get("bytes_per_launch", {}).get(kernel)
+
+
+def copy_calibration(gib: float = 1.0, reps: int = 5):
+    """Plain device copies of a known size, for scaling the HBM byte counters."""
+    import torch
+    n = int(gib * (1 << 30)) // 4
+    x = torch.ones(n, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    print(json.dumps({"copy_bytes_each_way": n * 4, "reps": reps, "GB/s_read+write": 2 * n * 4 / dt / 1e9}),
+          flush=True)
 
 
 def cpu_baseline(h: float, full_ndof: int):
@@ -105,6 +120,9 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU; multi-GPU runs are not part of it",
                           "n_gpus": args.gpus}), flush=True)
         sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration()
+        return
     import torch
     from paper_2009_06725_amd import scvs
 
@@ -134,7 +152,8 @@ def main():
     pt = torch.empty((args.ntimes, info.nv), dtype=torch.float64, device="cuda")
     opts = scvs.default_opts(rtol=args.rtol, restart=args.restart, cheb_vel=args.cheb_vel,
                              cheb_pres=args.cheb_pres, verbose=1 if args.verbose else 0,
-                             precision=1 if args.precision == "mixed" else 0, orth=args.orth)
+                             precision=1 if args.precision == "mixed" else 0, orth=args.orth,
+                             inner_rtol=args.inner_rtol)
     log(f"n2={info.n2} ndof={info.ndof} nnz_s2={info.nnz_s2} ingest+assembly {t_ingest:.2f}s")
 
     def step():
@@ -195,7 +214,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"pipe R=1 L=10, {mesh.nc} curved P2/P1 tets, {ns} modes (16 harmonics + mean)",
                    "ndof": int(info.ndof), "modes": ns, "rtol": args.rtol, "restart": args.restart,
-                   "cheb_vel": args.cheb_vel, "cheb_pres": args.cheb_pres, "orth": args.orth,
+                   "cheb_vel": args.cheb_vel, "cheb_pres": args.cheb_pres, "orth": args.orth, "inner_rtol": args.inner_rtol,
                    "ntimes": args.ntimes},
         "dof_modes_per_s": info.ndof * ns * args.steps / dt,
         "roofline": roof(dominant),
@@ -204,6 +223,24 @@ def main():
         "iterations": iters,
         "kernels": kernels,
     }
+    if not args.no_error_check:
+        # error of the timed solution: against an FP64 solve to a 100x tighter residual
+        # (not below 1e-13, about where FP64 restarts stop gaining)
+        rref = max(args.rtol * 1e-2, 1e-13)
+        ref = scvs.default_opts(rtol=rref, restart=args.restart, cheb_vel=args.cheb_vel,
+                                cheb_pres=args.cheb_pres, precision=0, verbose=1 if args.verbose else 0)
+        ur = torch.empty_like(u)
+        pr = torch.empty_like(p)
+        log("error check: FP64 reference solve ...")
+        _, _, rep3 = m.solve(case["omega"], case["traction"], g, u=ur, p=pr, opts=ref)
+        eu = (torch.linalg.vector_norm((u - ur).reshape(ns, -1), dim=1) /
+              torch.linalg.vector_norm(ur.reshape(ns, -1), dim=1)).cpu().numpy()
+        ep = (torch.linalg.vector_norm(p - pr, dim=1) / torch.linalg.vector_norm(pr, dim=1)).cpu().numpy()
+        out["error_vs_tight_reference"] = {
+            "reference": f"FP64 path, rtol {rref:g}", "norm": "relative Euclidean per mode",
+            "max_u": float(eu.max()), "max_p": float(ep.max()),
+            "per_mode_u": [float(x) for x in eu], "per_mode_p": [float(x) for x in ep],
+            "reference_converged": all(r.status == 0 for r in rep3)}
     if not args.no_compare:
         # comparator: plain per-mode FP64 GMRES (one system at a time, same
         # preconditioner, restart and tolerance, two-pass Gram-Schmidt)

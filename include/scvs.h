@@ -192,10 +192,13 @@ typedef struct {
                          pass of each vector lagged into the next step's single reduction
                          (DCGS2, Swirydowicz et al. 2020; two passes per step, one extra
                          closing reduction per cycle) */
+  double inner_rtol;  /* mixed precision only: a restart cycle also ends once its own residual
+                         estimate has fallen by this factor (the FP32 operator cannot take the
+                         true residual much further within one cycle); 0 = only at rtol or m */
 } scvs_solve_opts;
 
 /* Fill `o` with the defaults (rtol 1e-10, m 200, 20000 iterations, degrees 10/50,
- * ratio 30, batch 0, graphs on, FP64, lagged orthogonalization). */
+ * ratio 30, batch 0, graphs on, FP64, lagged orthogonalization, inner_rtol 1e-5). */
 void scvs_solve_opts_default(scvs_solve_opts* o);
 
 typedef struct {

@@ -39,6 +39,7 @@ struct SlotState {
   double2 gq;                 // lagged: <q_j, W>
   double sig, rho;            // lagged: norm of the reorthogonalized u_j; norm of the last first-pass vector
   double nrm0, fnorm, tolabs, beta;
+  double tolcyc;              // a cycle also ends when its residual estimate falls below this
   int jstop, skip2, nonfinite, lastJ;
   unsigned int ticket[8];
 };
@@ -213,7 +214,7 @@ __device__ bool givens_column(SlotState& st, int j, double nrm) {
   st.gam[j + 1] = make_double2(-(s.x * g.x + s.y * g.y), -(s.x * g.y - s.y * g.x));  // -conj(s) g
   const double res = hypot(st.gam[j + 1].x, st.gam[j + 1].y);
   const bool breakdown = nrm <= 1e-13 * sqrt(hn2);
-  if (res <= st.tolabs || breakdown) st.jstop = j + 1;
+  if (res <= fmax(st.tolabs, st.tolcyc) || breakdown) st.jstop = j + 1;
   return true;
 }
 
@@ -712,8 +713,11 @@ __global__ void k_axpy(KArgs a, VArg x, VArg z) {
 
 // ||x||: KIND 0 sets fnorm/tolabs from the right-hand side; KIND 1 starts a
 // cycle from the residual stored in V_0.
+// KIND 0: ||f|| and the absolute target; KIND 1: ||r|| of the current iterate, which
+// starts a cycle (with `inner` > 0 the cycle also ends once its own residual estimate
+// has fallen by that factor, as inner solves of iterative refinement do).
 template <int KIND>
-__global__ void __launch_bounds__(RBS) k_norm(KArgs a, VArg x, double rtol) {
+__global__ void __launch_bounds__(RBS) k_norm(KArgs a, VArg x, double rtol, double inner = 0.0) {
   __shared__ double2 sh[RBS / 64];
   const int slot = a.act[blockIdx.y];
   SlotState& st = a.st[slot];
@@ -739,6 +743,7 @@ __global__ void __launch_bounds__(RBS) k_norm(KArgs a, VArg x, double rtol) {
       st.nonfinite = isfinite(nrm) ? 0 : 1;
     } else {
       st.beta = nrm;
+      st.tolcyc = inner * nrm;
       st.gam[0] = make_double2(nrm, 0.0);
       st.hs[0] = nrm > 0.0 ? 1.0 / nrm : 0.0;
       st.jstop = (nrm <= st.tolabs || !isfinite(nrm)) ? 0 : -1;
@@ -904,7 +909,7 @@ __global__ void k_stops(const SlotState* __restrict__ st, const int* __restrict_
 // End of a restart cycle for the systems of `b` (all that started it): least squares,
 // x += P^-1 V y, and the new true residual.
 void cycle_end(scvs_mesh m, Pool& P, const Batch& b, const PrecondArgs& pa, int64_t ndof, double rtol,
-               bool lagged, hipStream_t s) {
+               double inner, bool lagged, hipStream_t s) {
   const int nact = b.nact;
   const int nch = choose_nch(nact, ndof);
   KArgs a = kargs(P, ndof, nch);
@@ -937,7 +942,7 @@ void cycle_end(scvs_mesh m, Pool& P, const Batch& b, const PrecondArgs& pa, int6
   spmv_full(m, b, P.X(), Vv, SPMV_RESID, true, P.F(), nullptr, s);
   {
     ProfScope ps(prof, s, "k_norm", vec);
-    k_norm<1><<<gr, RBS, 0, s>>>(a, VArg{}, rtol);
+    k_norm<1><<<gr, RBS, 0, s>>>(a, VArg{}, rtol, pa.mixed ? inner : 0.0);
   }
   launch_check(s);
 }
@@ -1075,7 +1080,7 @@ int solve_systems(scvs_mesh m, int64_t nsys, const double* omega, const double* 
     k_norm<0><<<g0, RBS, 0, s>>>(a0, P.F(), o->rtol);
     velocity_bounds(m, b, P.lv, s);
     spmv_full(m, b, P.X(), VArg{P.V.p, (int64_t)(mk + 1) * P.ld}, SPMV_RESID, true, P.F(), nullptr, s);
-    k_norm<1><<<g0, RBS, 0, s>>>(a0, VArg{}, o->rtol);
+    k_norm<1><<<g0, RBS, 0, s>>>(a0, VArg{}, o->rtol, mixed ? o->inner_rtol : 0.0);
     launch_check(s);
     std::vector<double> info(4 * nb);
     std::vector<int> warm(nb, x0 ? 1 : 0);
@@ -1102,7 +1107,7 @@ int solve_systems(scvs_mesh m, int64_t nsys, const double* omega, const double* 
           k_init_x<3><<<gb, 256, 0, s>>>(P.X(), nullptr, 0, gp, m->ndir * D, m->dmask, m->dirnodes, m->ndir,
                                          m->n2, ndof, P.act, (int)first);
         spmv_full(m, bb, P.X(), VArg{P.V.p, (int64_t)(mk + 1) * P.ld}, SPMV_RESID, true, P.F(), nullptr, s);
-        k_norm<1><<<gn, RBS, 0, s>>>(ab, VArg{}, o->rtol);
+        k_norm<1><<<gn, RBS, 0, s>>>(ab, VArg{}, o->rtol, mixed ? o->inner_rtol : 0.0);
         launch_check(s);
       }
     }
@@ -1216,7 +1221,7 @@ int solve_systems(scvs_mesh m, int64_t nsys, const double* omega, const double* 
         m->ctx->prof.correct("k_combine", -(double)ndof * 16.0 * (mk - jend[k]));
         if (lagged && jend[k] < mk) m->ctx->prof.correct("k_lag_dots", -(double)ndof * 16.0 * (mk + 1));
       }
-      launch(-1 - na, [&](hipStream_t st) { cycle_end(m, P, bc, pa, ndof, o->rtol, lagged, st); });
+      launch(-1 - na, [&](hipStream_t st) { cycle_end(m, P, bc, pa, ndof, o->rtol, o->inner_rtol, lagged, st); });
       for (int k : act) cycles[k]++;
     }
     for (auto& kv : graphs) {
