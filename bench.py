@@ -47,7 +47,9 @@ def parse():
     ap.add_argument("--cheb-vel", type=int, default=10)
     ap.add_argument("--cheb-pres", type=int, default=50)
     ap.add_argument("--ntimes", type=int, default=64)
-    ap.add_argument("--precision", choices=["fp64", "mixed"], default="mixed")
+    ap.add_argument("--precision", choices=["fp64", "mixed", "mixed32"], default="mixed",
+                    help="mixed: FP32 operator and velocity block in FP64 refinement; mixed32: also an FP32 "
+                         "Krylov basis (FP64 arithmetic)")
     ap.add_argument("--inner-rtol", type=float, default=1e-5,
                     help="mixed precision: end a cycle once its own residual fell by this factor")
     ap.add_argument("--orth", type=int, choices=[0, 1], default=1,
@@ -152,7 +154,7 @@ def main():
     pt = torch.empty((args.ntimes, info.nv), dtype=torch.float64, device="cuda")
     opts = scvs.default_opts(rtol=args.rtol, restart=args.restart, cheb_vel=args.cheb_vel,
                              cheb_pres=args.cheb_pres, verbose=1 if args.verbose else 0,
-                             precision=1 if args.precision == "mixed" else 0, orth=args.orth,
+                             precision={"fp64": 0, "mixed": 1, "mixed32": 2}[args.precision], orth=args.orth,
                              inner_rtol=args.inner_rtol)
     log(f"n2={info.n2} ndof={info.ndof} nnz_s2={info.nnz_s2} ingest+assembly {t_ingest:.2f}s")
 
@@ -210,7 +212,9 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "c128" if args.precision == "fp64" else "c64 operator+velocity precond / c128 refinement",
+        "dtype": {"fp64": "c128", "mixed": "c64 operator+velocity precond / c128 refinement",
+                  "mixed32": "c64 operator+velocity precond+Krylov basis storage / c128 arithmetic+refinement"
+                  }[args.precision],
         "data": "synthetic",
         "config": {"workload": f"pipe R=1 L=10, {mesh.nc} curved P2/P1 tets, {ns} modes (16 harmonics + mean)",
                    "ndof": int(info.ndof), "modes": ns, "rtol": args.rtol, "restart": args.restart,

@@ -303,7 +303,8 @@ int scvs_solve(scvs_mesh m, int64_t nsys, const double* omega, const double* tra
       scvs_solve_opts_default(&o);
     SCVS_REQUIRE(o.rtol > 0.0 && o.restart >= 1 && o.restart <= SCVS_MMAX && o.max_iters >= 1 &&
                      o.cheb_vel >= 1 && o.cheb_pres >= 1 && o.cheb_ratio > 1.0 && o.max_batch >= 0 &&
-                     (o.precision == 0 || o.precision == 1) && (o.orth == 0 || o.orth == 1) &&
+                     (o.precision >= 0 && o.precision <= 2) && (o.orth == 0 || o.orth == 1) &&
+                     (o.precision != 2 || o.orth == 1) &&
                      o.inner_rtol >= 0.0 && o.inner_rtol < 1.0,
                  SCVS_E_INVALID, "bad solve options");
     for (int64_t k = 0; k < nsys; ++k) SCVS_REQUIRE(std::isfinite(omega[k]), SCVS_E_INVALID, "non-finite omega");

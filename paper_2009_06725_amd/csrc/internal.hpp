@@ -210,17 +210,24 @@ void mesh_set_midside(scvs_mesh m, int64_t n, const int32_t* ev, const double* x
 
 // ---- spmv.hip ----
 // A per-slot vector argument: the vector of slot k starts at p + k * st.
-struct VArg {
-  double2* p = nullptr;
+template <class T>
+struct SV {
+  T* p = nullptr;
   int64_t st = 0;
-  __host__ __device__ double2* at(int k) const { return p + (int64_t)k * st; }
+  __host__ __device__ T* at(int k) const { return p + (int64_t)k * st; }
 };
-// Same, for complex single-precision vectors (mixed-precision solves).
-struct VArg32 {
-  float2* p = nullptr;
-  int64_t st = 0;
-  __host__ __device__ float2* at(int k) const { return p + (int64_t)k * st; }
-};
+using VArg = SV<double2>;   // complex double vectors
+using VArg32 = SV<float2>;  // complex single vectors (mixed-precision solves)
+
+// Conversions between the complex element types.
+template <class T>
+__host__ __device__ inline T cvt2(double2 v);
+template <>
+__host__ __device__ inline double2 cvt2<double2>(double2 v) { return v; }
+template <>
+__host__ __device__ inline float2 cvt2<float2>(double2 v) { return make_float2((float)v.x, (float)v.y); }
+__host__ __device__ inline double2 to_d2(double2 v) { return v; }
+__host__ __device__ inline double2 to_d2(float2 v) { return make_double2((double)v.x, (double)v.y); }
 // The active systems of one launch.
 struct Batch {
   int nact = 0;
@@ -249,8 +256,15 @@ struct PrecondArgs {
 // part in the Schur step).
 void precond_apply(scvs_mesh m, const Batch& b, const PrecondArgs& pa, VArg v, VArg z, hipStream_t s,
                    void* zil = nullptr);
-// y = A x with x in the interleaved layout written by precond_apply(..., zil).
+// Same, reading an FP32 input vector (FP32 Krylov basis).
+void precond_apply(scvs_mesh m, const Batch& b, const PrecondArgs& pa, VArg32 v, VArg z, hipStream_t s,
+                   void* zil = nullptr);
+// y = A x with x in the interleaved layout written by precond_apply(..., zil), into an
+// FP64 or an FP32 output.
 void spmv_apply_il(scvs_mesh m, const Batch& b, const void* xil, bool fp32, VArg y, hipStream_t s);
+void spmv_apply_il(scvs_mesh m, const Batch& b, const void* xil, bool fp32, VArg32 y, hipStream_t s);
+// y = f - A x (masked columns, as SPMV_RESID) with an FP32 output.
+void spmv_resid32(scvs_mesh m, const Batch& b, VArg x, VArg32 y, VArg f, hipStream_t s);
 // y = A x with FP32 matrix copies, FP32 input and FP32 accumulation; FP64 output.
 void spmv_apply32(scvs_mesh m, const Batch& b, VArg32 x, VArg y, hipStream_t s);
 // FP32 copies of the matrix values for mixed-precision solves (made once per assembly).

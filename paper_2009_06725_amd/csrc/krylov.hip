@@ -52,11 +52,24 @@ struct KArgs {
   int64_t ndof, ld;
   int m;
   double2* V;  // slot k, vector i at V + (k*(m+1) + i)*ld
+  float2* V32;  // the same storage as FP32 pairs when the basis is kept in FP32
   double* info;  // per slot: rel, lastJ, nonfinite, beta
 };
 
 __device__ __forceinline__ double2* vec(const KArgs& a, int slot, int i) {
   return a.V + ((int64_t)slot * (a.m + 1) + i) * a.ld;
+}
+
+// Basis vector i of a slot in the storage precision VT (double2 or float2).
+template <class VT>
+__device__ __forceinline__ VT* vecT(const KArgs& a, int slot, int i);
+template <>
+__device__ __forceinline__ double2* vecT<double2>(const KArgs& a, int slot, int i) {
+  return vec(a, slot, i);
+}
+template <>
+__device__ __forceinline__ float2* vecT<float2>(const KArgs& a, int slot, int i) {
+  return a.V32 + ((int64_t)slot * (a.m + 1) + i) * a.ld;
 }
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -430,33 +443,38 @@ __global__ void __launch_bounds__(RBS) k_upd_dots(KArgs a, int j) {
 // vector (W - Q a - gamma q_j) / sigma over V_{j+1}, sharing one read of the basis, and
 // its norm rho_j. After the last step one more pass 1 (final) completes the last column.
 constexpr int VS2 = TILE + MM + 2 + 64;
+template <class VT>
 __global__ void __launch_bounds__(RBS) k_lag_dots(KArgs a, int j, int final) {
   static_assert((RBS / 64) * 2 * (MM + 1) <= VS2, "partials reuse the tile buffer");
-  __shared__ double2 vs[VS2];
+  // the tile holds basis values in their storage type: FP32 pairs fit twice as many
+  constexpr int TL = TILE * (int)(sizeof(double2) / sizeof(VT));
+  static_assert((TL + MM + 2 + 64) * sizeof(VT) <= VS2 * sizeof(double2), "tile fits");
+  __shared__ double2 vsd[VS2];
+  VT* vs = reinterpret_cast<VT*>(vsd);
   const int slot = a.act[blockIdx.y];
   SlotState& st = a.st[slot];
   if (st.jstop >= 0) return;
   const int t = threadIdx.x;
   const int nrow = final ? j + 1 : j + 2;  // V_0..V_j, and W = V_{j+1}
   int tn = 32;
-  while (tn > 4 && nrow * tn > TILE) tn >>= 1;
+  while (tn > 4 && nrow * tn > TL) tn >>= 1;
   const int tp = tn + 1;
   int64_t b0, b1;
   chunk_range(a, b0, b1);
-  const double2* __restrict__ V0 = vec(a, slot, 0);
+  const VT* __restrict__ V0 = vecT<VT>(a, slot, 0);
   const int di = t & 63, dq = t >> 6, qlen = tn / 4;
   double2 accS[NDG], accA[NDG];
 #pragma unroll
   for (int g = 0; g < NDG; ++g) accS[g] = accA[g] = make_double2(0.0, 0.0);
-  constexpr int PF = TILE / RBS;
+  constexpr int PF = TL / RBS;
   const int nld = nrow * tn;
-  double2 pre[PF];
+  VT pre[PF];
   auto fetch = [&](int64_t nb) {
     const int len = (int)min((int64_t)tn, b1 - nb);
 #pragma unroll
     for (int k = 0; k < PF; ++k) {
       const int q = t + k * RBS, i = q / tn, e = q % tn;
-      pre[k] = (q < nld && e < len) ? V0[(int64_t)i * a.ld + nb + e] : make_double2(0.0, 0.0);
+      pre[k] = (q < nld && e < len) ? V0[(int64_t)i * a.ld + nb + e] : cvt2<VT>(make_double2(0.0, 0.0));
     }
   };
   if (b0 < b1) fetch(b0);
@@ -470,12 +488,12 @@ __global__ void __launch_bounds__(RBS) k_lag_dots(KArgs a, int j, int final) {
     __syncthreads();
     if (nb + tn < b1) fetch(nb + tn);
     for (int e = dq * qlen; e < (dq + 1) * qlen; ++e) {
-      const double2 uv = vs[j * tp + e];
-      const double2 wv = final ? make_double2(0.0, 0.0) : vs[(j + 1) * tp + e];
+      const double2 uv = to_d2(vs[j * tp + e]);
+      const double2 wv = final ? make_double2(0.0, 0.0) : to_d2(vs[(j + 1) * tp + e]);
 #pragma unroll
       for (int g = 0; g < NDG; ++g)
         if (di + 64 * g <= j) {
-          const double2 v = vs[(di + 64 * g) * tp + e];
+          const double2 v = to_d2(vs[(di + 64 * g) * tp + e]);
           accS[g].x += v.x * uv.x + v.y * uv.y;
           accS[g].y += v.x * uv.y - v.y * uv.x;
           accA[g].x += v.x * wv.x + v.y * wv.y;
@@ -483,7 +501,7 @@ __global__ void __launch_bounds__(RBS) k_lag_dots(KArgs a, int j, int final) {
         }
     }
   }
-  double2* red = vs;  // [RBS/64][2(MM+1)]
+  double2* red = vsd;  // [RBS/64][2(MM+1)]
   const int R2 = 2 * (MM + 1);
   __syncthreads();
 #pragma unroll
@@ -502,8 +520,8 @@ __global__ void __launch_bounds__(RBS) k_lag_dots(KArgs a, int j, int final) {
   }
   if (!last_block(&st.ticket[0], a.nch)) return;
   // ---- last workgroup: fixed-order sums over the chunks, then the scalar work ----
-  double2* S = vs;            // [MM+1]
-  double2* Av = vs + MM + 1;  // [MM+1]
+  double2* S = vsd;            // [MM+1]
+  double2* Av = vsd + MM + 1;  // [MM+1]
   __shared__ double sh_sig, sh_rho;
   __shared__ int sh_go;
   for (int i = t; i <= j; i += RBS) {
@@ -583,6 +601,7 @@ __global__ void __launch_bounds__(RBS) k_lag_dots(KArgs a, int j, int final) {
 }
 
 // Pass 2 of a lagged step: q_j over V_j, the next first-pass vector over V_{j+1}, and its norm.
+template <class VT>
 __global__ void __launch_bounds__(RBS) k_lag_update(KArgs a, int j) {
   __shared__ double2 cq[MM + 1], cw[MM + 1];
   __shared__ double2 sh[RBS / 64];
@@ -598,22 +617,23 @@ __global__ void __launch_bounds__(RBS) k_lag_update(KArgs a, int j) {
   const double2 gq = st.gq;
   int64_t b0, b1;
   chunk_range(a, b0, b1);
-  double2* __restrict__ u = vec(a, slot, j);
-  double2* __restrict__ w = vec(a, slot, j + 1);
-  const double2* __restrict__ V0 = vec(a, slot, 0);
+  VT* __restrict__ u = vecT<VT>(a, slot, j);
+  VT* __restrict__ w = vecT<VT>(a, slot, j + 1);
+  const VT* __restrict__ V0 = vecT<VT>(a, slot, 0);
   double2 acc[1] = {make_double2(0.0, 0.0)};
   for (int64_t n = b0 + threadIdx.x; n < b1; n += RBS) {
     double2 sq = make_double2(0.0, 0.0), sw = make_double2(0.0, 0.0);
+#pragma unroll 8
     for (int i = 0; i < j; ++i) {
-      const double2 v = V0[(int64_t)i * a.ld + n];
+      const double2 v = to_d2(V0[(int64_t)i * a.ld + n]);
       sq = cadd(sq, cmul(cq[i], v));
       sw = cadd(sw, cmul(cw[i], v));
     }
-    const double2 uv = u[n], wv = w[n];
+    const double2 uv = to_d2(u[n]), wv = to_d2(w[n]);
     const double2 q = cscale(csub(cscale(uv, hsj), sq), inv);
     const double2 wn = cscale(csub(csub(wv, sw), cmul(gq, q)), inv);
-    u[n] = q;
-    w[n] = wn;
+    u[n] = cvt2<VT>(q);
+    w[n] = cvt2<VT>(wn);
     acc[0].x += wn.x * wn.x + wn.y * wn.y;
   }
   const double2 r = block_sum<1>(acc, sh);
@@ -664,6 +684,7 @@ __global__ void k_trisolve(KArgs a, int nact) {
 }
 
 // t = sum_{i<J} y_i V_i
+template <class VT>
 __global__ void __launch_bounds__(RBS) k_combine(KArgs a, VArg t) {
   __shared__ double2 y[MM];
   const int slot = a.act[blockIdx.y];
@@ -673,12 +694,12 @@ __global__ void __launch_bounds__(RBS) k_combine(KArgs a, VArg t) {
   __syncthreads();
   int64_t b0, b1;
   chunk_range(a, b0, b1);
-  const double2* __restrict__ V0 = vec(a, slot, 0);
+  const VT* __restrict__ V0 = vecT<VT>(a, slot, 0);
   double2* __restrict__ ts = t.at(slot);
   for (int64_t n = b0 + threadIdx.x; n < b1; n += RBS) {
     double2 s = make_double2(0.0, 0.0);
     for (int i = 0; i < J; ++i) {
-      const double2 v = V0[(int64_t)i * a.ld + n];
+      const double2 v = to_d2(V0[(int64_t)i * a.ld + n]);
       s.x += y[i].x * v.x - y[i].y * v.y;
       s.y += y[i].x * v.y + y[i].y * v.x;
     }
@@ -716,17 +737,18 @@ __global__ void k_axpy(KArgs a, VArg x, VArg z) {
 // KIND 0: ||f|| and the absolute target; KIND 1: ||r|| of the current iterate, which
 // starts a cycle (with `inner` > 0 the cycle also ends once its own residual estimate
 // has fallen by that factor, as inner solves of iterative refinement do).
-template <int KIND>
+template <int KIND, class VT = double2>
 __global__ void __launch_bounds__(RBS) k_norm(KArgs a, VArg x, double rtol, double inner = 0.0) {
   __shared__ double2 sh[RBS / 64];
   const int slot = a.act[blockIdx.y];
   SlotState& st = a.st[slot];
   int64_t b0, b1;
   chunk_range(a, b0, b1);
-  const double2* __restrict__ xs = KIND == 0 ? x.at(slot) : vec(a, slot, 0);
+  const double2* __restrict__ xs = x.at(slot);
+  const VT* __restrict__ v0 = vecT<VT>(a, slot, 0);
   double2 acc[1] = {make_double2(0.0, 0.0)};
   for (int64_t n = b0 + threadIdx.x; n < b1; n += RBS) {
-    const double2 v = xs[n];
+    const double2 v = KIND == 0 ? xs[n] : to_d2(v0[n]);
     acc[0].x += v.x * v.x + v.y * v.y;
   }
   const double2 r = block_sum<1>(acc, sh);
@@ -811,6 +833,7 @@ __global__ void k_copy_out(const VArg x, const int* act, int first, int nact, in
 // Device workspace for a batch of `slots` systems.
 struct Pool {
   int slots = 0, m = 0, nch = 0;
+  bool v32 = false;  // Krylov basis stored as FP32 pairs (arithmetic stays FP64)
   int64_t ld = 0, DN = 0, nv = 0;
   DBuf<double2> V, W, vt, pt, part, trac;
   DBuf<float2> vt32, z32;
@@ -824,10 +847,11 @@ struct Pool {
   VArg T() const { return VArg{W.p + 3 * ld, 4 * ld}; }
 };
 
-size_t slot_bytes(int64_t ld, int m, int64_t DN, int64_t nv, int nch, bool mixed) {
+size_t slot_bytes(int64_t ld, int m, int64_t DN, int64_t nv, int nch, bool mixed, bool v32) {
   // basis, Z/X/F/T, velocity temps (FP64 path), pressure temps, partial sums; FP32 temps,
   // z32 (mixed path); interleaved operator input (FP32 pairs in mixed mode)
-  return sizeof(double2) * ((size_t)(m + 1 + 4) * ld + (mixed ? 0 : 4 * DN) + 4 * nv + (size_t)nch * PSTRIDE) +
+  return (v32 ? sizeof(float2) : sizeof(double2)) * (size_t)(m + 1) * ld +
+         sizeof(double2) * ((size_t)4 * ld + (mixed ? 0 : 4 * DN) + 4 * nv + (size_t)nch * PSTRIDE) +
          (mixed ? sizeof(float2) * (4 * DN + ld) : 0) + (mixed ? sizeof(float2) : sizeof(double2)) * ld +
          sizeof(SlotState) + 64;
 }
@@ -849,6 +873,7 @@ KArgs kargs(Pool& P, int64_t ndof, int nch) {
   a.ld = P.ld;
   a.m = P.m;
   a.V = P.V;
+  a.V32 = reinterpret_cast<float2*>(P.V.p);
   a.info = P.info;
   return a;
 }
@@ -862,26 +887,37 @@ void cycle_steps(scvs_mesh m, Pool& P, const Batch& br, const PrecondArgs& pa, i
   KArgs a = kargs(P, ndof, nch);
   a.act = br.act;
   const dim3 gr((unsigned)nch, (unsigned)nact);
-  const VArg Vv{P.V.p, (int64_t)(P.m + 1) * P.ld};
+  const int64_t vst = (int64_t)(P.m + 1) * P.ld;
   Profiler* prof = &m->ctx->prof;
-  const double vec = (double)ndof * 16.0 * nact;  // one vector of every running system
+  // one basis vector of every running system
+  const double vec = (double)ndof * (P.v32 ? 8.0 : 16.0) * nact;
   for (int j = j0; j < j1; ++j) {
     Batch bj = br;
     bj.insc = reinterpret_cast<const double*>(P.st.p) + offsetof(SlotState, hs) / sizeof(double) + j;
     bj.insc_st = sizeof(SlotState) / sizeof(double);
     bj.insc_idx = 0;
-    VArg vj{Vv.p + (int64_t)j * P.ld, Vv.st};
-    VArg vn{Vv.p + (int64_t)(j + 1) * P.ld, Vv.st};
-    precond_apply(m, bj, pa, vj, P.Z(), s, P.zil.p);
-    spmv_apply_il(m, br, P.zil.p, pa.mixed != 0, vn, s);
+    if (P.v32) {
+      float2* V32 = reinterpret_cast<float2*>(P.V.p);
+      precond_apply(m, bj, pa, VArg32{V32 + (int64_t)j * P.ld, vst}, P.Z(), s, P.zil.p);
+      spmv_apply_il(m, br, P.zil.p, pa.mixed != 0, VArg32{V32 + (int64_t)(j + 1) * P.ld, vst}, s);
+    } else {
+      precond_apply(m, bj, pa, VArg{P.V.p + (int64_t)j * P.ld, vst}, P.Z(), s, P.zil.p);
+      spmv_apply_il(m, br, P.zil.p, pa.mixed != 0, VArg{P.V.p + (int64_t)(j + 1) * P.ld, vst}, s);
+    }
     if (lagged) {
       {
         ProfScope ps(prof, s, "k_lag_dots", vec * (j + 2));  // V_0..V_j and W once
-        k_lag_dots<<<gr, RBS, 0, s>>>(a, j, 0);
+        if (P.v32)
+          k_lag_dots<float2><<<gr, RBS, 0, s>>>(a, j, 0);
+        else
+          k_lag_dots<double2><<<gr, RBS, 0, s>>>(a, j, 0);
       }
       {
         ProfScope ps(prof, s, "k_lag_update", vec * (j + 4));  // V_0..V_j and W read, V_j and W written
-        k_lag_update<<<gr, RBS, 0, s>>>(a, j);
+        if (P.v32)
+          k_lag_update<float2><<<gr, RBS, 0, s>>>(a, j);
+        else
+          k_lag_update<double2><<<gr, RBS, 0, s>>>(a, j);
       }
     } else {
       {
@@ -915,21 +951,28 @@ void cycle_end(scvs_mesh m, Pool& P, const Batch& b, const PrecondArgs& pa, int6
   KArgs a = kargs(P, ndof, nch);
   a.act = b.act;
   const dim3 gr((unsigned)nch, (unsigned)nact);
-  const VArg Vv{P.V.p, (int64_t)(P.m + 1) * P.ld};
+  const int64_t vst = (int64_t)(P.m + 1) * P.ld;
   Profiler* prof = &m->ctx->prof;
   const double vec = (double)ndof * 16.0 * nact;
+  const double vecb = (double)ndof * (P.v32 ? 8.0 : 16.0) * nact;  // one basis vector of each
   if (lagged) {
     // the last column still needs the lagged correction of V_m
-    ProfScope ps(prof, s, "k_lag_dots", vec * (P.m + 1));
-    k_lag_dots<<<gr, RBS, 0, s>>>(a, P.m, 1);
+    ProfScope ps(prof, s, "k_lag_dots", vecb * (P.m + 1));
+    if (P.v32)
+      k_lag_dots<float2><<<gr, RBS, 0, s>>>(a, P.m, 1);
+    else
+      k_lag_dots<double2><<<gr, RBS, 0, s>>>(a, P.m, 1);
   }
   {
     ProfScope ps(prof, s, "k_trisolve", 0.0);
     k_trisolve<<<(nact + 63) / 64, 64, 0, s>>>(a, nact);
   }
   {
-    ProfScope ps(prof, s, "k_combine", vec * (P.m + 1));
-    k_combine<<<gr, RBS, 0, s>>>(a, P.T());
+    ProfScope ps(prof, s, "k_combine", vecb * P.m + vec);
+    if (P.v32)
+      k_combine<float2><<<gr, RBS, 0, s>>>(a, P.T());
+    else
+      k_combine<double2><<<gr, RBS, 0, s>>>(a, P.T());
   }
   precond_apply(m, b, pa, P.T(), P.Z(), s);
   {
@@ -939,10 +982,16 @@ void cycle_end(scvs_mesh m, Pool& P, const Batch& b, const PrecondArgs& pa, int6
     else
       k_axpy<<<dim3(256, nact), 256, 0, s>>>(a, P.X(), P.Z());
   }
-  spmv_full(m, b, P.X(), Vv, SPMV_RESID, true, P.F(), nullptr, s);
+  if (P.v32)
+    spmv_resid32(m, b, P.X(), VArg32{reinterpret_cast<float2*>(P.V.p), vst}, P.F(), s);
+  else
+    spmv_full(m, b, P.X(), VArg{P.V.p, vst}, SPMV_RESID, true, P.F(), nullptr, s);
   {
-    ProfScope ps(prof, s, "k_norm", vec);
-    k_norm<1><<<gr, RBS, 0, s>>>(a, VArg{}, rtol, pa.mixed ? inner : 0.0);
+    ProfScope ps(prof, s, "k_norm", vecb);
+    if (P.v32)
+      k_norm<1, float2><<<gr, RBS, 0, s>>>(a, VArg{}, rtol, pa.mixed ? inner : 0.0);
+    else
+      k_norm<1, double2><<<gr, RBS, 0, s>>>(a, VArg{}, rtol, pa.mixed ? inner : 0.0);
   }
   launch_check(s);
 }
@@ -996,21 +1045,24 @@ int solve_systems(scvs_mesh m, int64_t nsys, const double* omega, const double* 
   size_t fr = 0, tot = 0;
   SCVS_HIP(hipMemGetInfo(&fr, &tot));
   const int nch_max = choose_nch(1, ndof);
-  const bool mixed = o->precision == 1;
+  const bool mixed = o->precision >= 1;
+  const bool lagged = o->orth == 1;
+  P.v32 = o->precision == 2;  // FP32 basis storage (lagged orthogonalization only; checked by the caller)
   if (mixed) make_fp32_copies(m, s);
   int mk = o->restart;
   const int64_t want = std::min<int64_t>(nsys, 8);
-  while (mk > 30 && (int64_t)((double)fr * 0.9 / (double)slot_bytes(P.ld, mk, DN, m->nv, nch_max, mixed)) < want)
+  while (mk > 30 &&
+         (int64_t)((double)fr * 0.9 / (double)slot_bytes(P.ld, mk, DN, m->nv, nch_max, mixed, P.v32)) < want)
     mk = std::max(30, mk * 3 / 4);
   if (o->verbose && mk != o->restart) fprintf(stderr, "[scvs] restart shortened to %d to fit memory\n", mk);
   P.m = mk;
-  const size_t per = slot_bytes(P.ld, mk, DN, m->nv, nch_max, mixed);
+  const size_t per = slot_bytes(P.ld, mk, DN, m->nv, nch_max, mixed, P.v32);
   int64_t fit = (int64_t)((double)fr * 0.9 / (double)per);
   SCVS_REQUIRE(fit >= 1, SCVS_E_NOMEM, "not enough device memory for one system's Krylov workspace");
   int B = (int)std::min<int64_t>(nsys, fit);
   if (o->max_batch > 0) B = std::min(B, o->max_batch);
   P.slots = B;
-  P.V.alloc((size_t)B * (mk + 1) * P.ld);
+  P.V.alloc(P.v32 ? ((size_t)B * (mk + 1) * P.ld + 1) / 2 : (size_t)B * (mk + 1) * P.ld);
   P.W.alloc((size_t)B * 4 * P.ld);
   if (mixed) {
     P.vt32.alloc((size_t)B * 4 * DN);
@@ -1079,8 +1131,18 @@ int solve_systems(scvs_mesh m, int64_t nsys, const double* omega, const double* 
     spmv_full(m, b, P.T(), P.F(), SPMV_RHS, false, VArg{}, P.trac, s);
     k_norm<0><<<g0, RBS, 0, s>>>(a0, P.F(), o->rtol);
     velocity_bounds(m, b, P.lv, s);
-    spmv_full(m, b, P.X(), VArg{P.V.p, (int64_t)(mk + 1) * P.ld}, SPMV_RESID, true, P.F(), nullptr, s);
-    k_norm<1><<<g0, RBS, 0, s>>>(a0, VArg{}, o->rtol, mixed ? o->inner_rtol : 0.0);
+    // initial residual into V_0 of every slot, and its norm
+    auto residual0 = [&](const Batch& bb, const KArgs& ka, dim3 gn) {
+      const int64_t vst = (int64_t)(mk + 1) * P.ld;
+      if (P.v32) {
+        spmv_resid32(m, bb, P.X(), VArg32{reinterpret_cast<float2*>(P.V.p), vst}, P.F(), s);
+        k_norm<1, float2><<<gn, RBS, 0, s>>>(ka, VArg{}, o->rtol, o->inner_rtol);
+      } else {
+        spmv_full(m, bb, P.X(), VArg{P.V.p, vst}, SPMV_RESID, true, P.F(), nullptr, s);
+        k_norm<1, double2><<<gn, RBS, 0, s>>>(ka, VArg{}, o->rtol, mixed ? o->inner_rtol : 0.0);
+      }
+    };
+    residual0(b, a0, g0);
     launch_check(s);
     std::vector<double> info(4 * nb);
     std::vector<int> warm(nb, x0 ? 1 : 0);
@@ -1106,15 +1168,13 @@ int solve_systems(scvs_mesh m, int64_t nsys, const double* omega, const double* 
         else
           k_init_x<3><<<gb, 256, 0, s>>>(P.X(), nullptr, 0, gp, m->ndir * D, m->dmask, m->dirnodes, m->ndir,
                                          m->n2, ndof, P.act, (int)first);
-        spmv_full(m, bb, P.X(), VArg{P.V.p, (int64_t)(mk + 1) * P.ld}, SPMV_RESID, true, P.F(), nullptr, s);
-        k_norm<1><<<gn, RBS, 0, s>>>(ab, VArg{}, o->rtol, mixed ? o->inner_rtol : 0.0);
+        residual0(bb, ab, gn);
         launch_check(s);
       }
     }
     std::vector<int> iters(nb, 0), cycles(nb, 0), done(nb, 0);
     std::map<int, std::pair<hipGraph_t, hipGraphExec_t>> graphs;
     const int chunk = std::min(mk, 30);
-    const bool lagged = o->orth == 1;
     std::vector<int> act_prev;
     for (;;) {
       download(info.data(), P.info.p, 4 * nb, s);
@@ -1200,7 +1260,7 @@ int solve_systems(scvs_mesh m, int64_t nsys, const double* omega, const double* 
           // Arnoldi launches of steps J.. returned at once (lagged: pass 2 from J, pass 1 from
           // J + 1, since pass 1 of step J found the stop): take back their bytes
           for (int jj = std::max(J, j0); jj < j1; ++jj) {
-            const double v = (double)ndof * 16.0;
+            const double v = (double)ndof * (P.v32 ? 8.0 : 16.0);
             if (lagged) {
               if (jj > J) m->ctx->prof.correct("k_lag_dots", -v * (jj + 2));
               m->ctx->prof.correct("k_lag_update", -v * (jj + 4));
@@ -1218,8 +1278,9 @@ int solve_systems(scvs_mesh m, int64_t nsys, const double* omega, const double* 
         }
       }
       for (int k : act) {
-        m->ctx->prof.correct("k_combine", -(double)ndof * 16.0 * (mk - jend[k]));
-        if (lagged && jend[k] < mk) m->ctx->prof.correct("k_lag_dots", -(double)ndof * 16.0 * (mk + 1));
+        const double vb = (double)ndof * (P.v32 ? 8.0 : 16.0);
+        m->ctx->prof.correct("k_combine", -vb * (mk - jend[k]));
+        if (lagged && jend[k] < mk) m->ctx->prof.correct("k_lag_dots", -vb * (mk + 1));
       }
       launch(-1 - na, [&](hipStream_t st) { cycle_end(m, P, bc, pa, ndof, o->rtol, o->inner_rtol, lagged, st); });
       for (int k : act) cycles[k]++;

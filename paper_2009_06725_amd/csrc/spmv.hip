@@ -248,8 +248,8 @@ __device__ __forceinline__ void g_acc(const MeshArgs& ma, int64_t A, int64_t j0,
 // With IL the input is the interleaved vector xil written by the preconditioner inside a
 // cycle: velocity pair p of node A at xil[A*G + p], pressure of system si at vertex v at
 // xil[n2*G + v*nact + si] (G = nact*D pairs); x is then unused.
-template <int D, int MODE, bool MASK, class R, bool IL = false>
-__global__ void __launch_bounds__(256) k_full(MeshArgs ma, Batch b, LaneMap lm, typename Prec<R>::V x, VArg y,
+template <int D, int MODE, bool MASK, class R, bool IL = false, class YT = double2>
+__global__ void __launch_bounds__(256) k_full(MeshArgs ma, Batch b, LaneMap lm, typename Prec<R>::V x, SV<YT> y,
                                               VArg f, const double* __restrict__ loads, int ntr,
                                               const double2* __restrict__ trac,
                                               const typename Prec<R>::C* __restrict__ xil = nullptr) {
@@ -301,7 +301,7 @@ __global__ void __launch_bounds__(256) k_full(MeshArgs ma, Batch b, LaneMap lm, 
           }
         }
       }
-      y.at(slot)[A * D + c] = yu;
+      y.at(slot)[A * D + c] = cvt2<YT>(yu);
     }
     if (isv) {
       const C ps = sum_components<D, C>(ap);
@@ -309,7 +309,7 @@ __global__ void __launch_bounds__(256) k_full(MeshArgs ma, Batch b, LaneMap lm, 
         double2 yp = make_double2(sc * (double)ps.x, sc * (double)ps.y);
         if (MODE == SPMV_RESID) yp = csub(f.at(slot)[D * ma.n2 + A], yp);
         if (MODE == SPMV_RHS) yp = make_double2(-yp.x, -yp.y);
-        y.at(slot)[D * ma.n2 + A] = yp;
+        y.at(slot)[D * ma.n2 + A] = cvt2<YT>(yp);
       }
     }
   }
@@ -356,8 +356,8 @@ struct ITemps {
 // here, pressure part copied from the FP64 Schur-block result zp).
 // With zil the result goes to the interleaved vector read by the next operator product
 // (layout of k_full's IL input); the pressure part is copied there too.
-template <int D, class R>
-__global__ void __launch_bounds__(256) k_vinit(MeshArgs ma, Batch b, LaneMap lm, VArg v, VArg zp64,
+template <int D, class R, class VI>
+__global__ void __launch_bounds__(256) k_vinit(MeshArgs ma, Batch b, LaneMap lm, SV<VI> v, VArg zp64,
                                                typename Prec<R>::V z, ITemps<typename Prec<R>::C> vt,
                                                double ratio, int kv, typename Prec<R>::C* __restrict__ zil) {
   using C = typename Prec<R>::C;
@@ -387,7 +387,7 @@ __global__ void __launch_bounds__(256) k_vinit(MeshArgs ma, Batch b, LaneMap lm,
       continue;
     }
     const double sc = in_scale(b, slot);
-    const double2 vv = v.at(slot)[k];
+    const double2 vv = to_d2(v.at(slot)[k]);
     C t;
     t.x = (R)(sc * vv.x);
     t.y = (R)(sc * vv.y);
@@ -446,14 +446,15 @@ __global__ void __launch_bounds__(256) k_vstep(MeshArgs ma, Batch b, LaneMap lm,
 // d0 = diag(L)^-1 r / theta, x = d0; with one step the Schur block is final:
 // zhat_p = -(mu Mp^-1 v_p + j w rho x). Temps r, d0, d1, x are interleaved like the
 // velocity ones: system si of the active list at vertex A sits at A*G + si.
-__global__ void k_pinit(MeshArgs ma, int D, Batch b, VArg v, VArg z, ITemps<double2> pt, double ratio, int kp) {
+template <class VI>
+__global__ void k_pinit(MeshArgs ma, int D, Batch b, SV<VI> v, VArg z, ITemps<double2> pt, double ratio, int kp) {
   const int64_t vv = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (vv >= ma.nv) return;
   const int si = blockIdx.y;
   const int slot = b.act[si];
   const int64_t DN = D * ma.n2, ki = vv * pt.G + si;
   const double sc = in_scale(b, slot);
-  const double2 vp = cscale(v.at(slot)[DN + vv], sc);
+  const double2 vp = cscale(to_d2(v.at(slot)[DN + vv]), sc);
   const double theta = 0.5 * ma.lpmax * (1.0 + 1.0 / ratio);
   const double2 dd = cscale(vp, ma.lpdinv[vv] / theta);
   pt.arr(0)[ki] = vp;
@@ -468,7 +469,8 @@ __global__ void k_pinit(MeshArgs ma, int D, Batch b, VArg v, VArg z, ITemps<doub
 // Pressure Laplacian Chebyshev step on the assembled L (one lane per system):
 // r -= L d_old; d_new = a d_old + b diag(L)^-1 r; x += d_new; on the last step
 // zhat_p = -(mu Mp^-1 v_p + j w rho x). A column's values of all systems are adjacent.
-__global__ void __launch_bounds__(256) k_pstep(MeshArgs ma, int D, Batch b, LaneMap lm, VArg v, VArg z,
+template <class VI>
+__global__ void __launch_bounds__(256) k_pstep(MeshArgs ma, int D, Batch b, LaneMap lm, SV<VI> v, VArg z,
                                                ITemps<double2> pt, double ratio, int step, int last) {
   const Lane L = lane_of(lm, ma.nv);
   const int G = pt.G;
@@ -520,7 +522,7 @@ __global__ void __launch_bounds__(256) k_pstep(MeshArgs ma, int D, Batch b, Lane
     if (last) {
       const int64_t DN = D * ma.n2;
       const double sc = in_scale(b, slot);
-      const double2 vp = cscale(v.at(slot)[DN + A], sc);
+      const double2 vp = cscale(to_d2(v.at(slot)[DN + A]), sc);
       const double wr = b.omega[slot] * ma.rho, im = ma.mu / ma.Mp[A];
       z.at(slot)[DN + A] = make_double2(-(im * vp.x - wr * xn.y), -(im * vp.y + wr * xn.x));
     }
@@ -598,8 +600,8 @@ void full_launch32(Profiler* prof, const MeshArgs& ma, const Batch& b, VArg32 x,
 }
 
 // y = A x for the interleaved preconditioner output (FP64 or FP32 values by R).
-template <int D, class R>
-void full_launch_il(Profiler* prof, const MeshArgs& ma, const Batch& b, const typename Prec<R>::C* xil, VArg y,
+template <int D, class R, class YT>
+void full_launch_il(Profiler* prof, const MeshArgs& ma, const Batch& b, const typename Prec<R>::C* xil, SV<YT> y,
                     hipStream_t s) {
   const LaneMap lm = lane_map(b.nact, D);
   const unsigned nb = row_blocks(ma.n2, lm);
@@ -607,14 +609,15 @@ void full_launch_il(Profiler* prof, const MeshArgs& ma, const Batch& b, const ty
   const double mat = (double)ma.nnz * (4.0 + 2.0 * vb) + (double)ma.nnz21 * (4.0 + vb * D) +
                      (double)ma.nnzv * vb * D + (double)ma.n2 * 24.0;
   const double ndof = (double)D * ma.n2 + ma.nv;
-  ProfScope ps(prof, s, sizeof(R) == 4 ? "k_full_apply32" : "k_full_apply", mat + b.nact * ndof * (2.0 * vb + 16.0));
-  k_full<D, SPMV_APPLY, false, R, true><<<nb, 256, 0, s>>>(ma, b, lm, typename Prec<R>::V{}, y, VArg{}, nullptr, 0,
-                                                           nullptr, xil);
+  ProfScope ps(prof, s, sizeof(R) == 4 ? "k_full_apply32" : "k_full_apply",
+               mat + b.nact * ndof * (2.0 * vb + (double)sizeof(YT)));
+  k_full<D, SPMV_APPLY, false, R, true, YT><<<nb, 256, 0, s>>>(ma, b, lm, typename Prec<R>::V{}, y, VArg{}, nullptr,
+                                                               0, nullptr, xil);
   launch_check(s);
 }
 
-template <int D>
-void precond_launch(Profiler* prof, const MeshArgs& ma, const Batch& b, const PrecondArgs& pa, VArg v, VArg z,
+template <int D, class VI>
+void precond_launch(Profiler* prof, const MeshArgs& ma, const Batch& b, const PrecondArgs& pa, SV<VI> v, VArg z,
                     void* zil, hipStream_t s) {
   const LaneMap lm = lane_map(b.nact, D), lp = lane_map(b.nact, 1);
   const unsigned nbu = row_blocks(ma.n2, lm), nbp = row_blocks(ma.nv, lp);
@@ -625,14 +628,14 @@ void precond_launch(Profiler* prof, const MeshArgs& ma, const Batch& b, const Pr
   {
     // per system: v_p read, r/d0/x written (and z_p when one step); lpdinv, Mp read
     ProfScope ps(prof, s, "k_pinit", nv * 16.0 + na * nv * 16.0 * 4.0);
-    k_pinit<<<gp, 256, 0, s>>>(ma, D, b, v, z, ptl, pa.ratio, pa.kp);
+    k_pinit<VI><<<gp, 256, 0, s>>>(ma, D, b, v, z, ptl, pa.ratio, pa.kp);
   }
   // L values and columns, row pointers, diag, Mp; per system d_old gathered,
   // r read+written, d_new written, x read+written
   const double pbytes = (double)ma.nnzl * 12.0 + nv * 24.0 + na * nv * 16.0 * 6.0;
   for (int i = 1; i < pa.kp; ++i) {
     ProfScope ps(prof, s, "k_pstep", pbytes + (i == pa.kp - 1 ? na * nv * 32.0 : 0.0));
-    k_pstep<<<nbp, 256, 0, s>>>(ma, D, b, lp, v, z, ptl, pa.ratio, i, i == pa.kp - 1);
+    k_pstep<VI><<<nbp, 256, 0, s>>>(ma, D, b, lp, v, z, ptl, pa.ratio, i, i == pa.kp - 1);
   }
   const double es = pa.mixed ? 8.0 : 16.0, vs = pa.mixed ? 4.0 : 8.0;  // complex / real element bytes
   // interleaved temporaries inside the slot pool's temp block (4 * D*n2 per slot, contiguous)
@@ -645,9 +648,9 @@ void precond_launch(Profiler* prof, const MeshArgs& ma, const Batch& b, const Pr
                  (double)ma.nnz21 * (4.0 + vs * D) + n2 * (24.0 + 2.0 * vs) +
                      na * (DN * 16.0 + nv * 16.0 + 2.0 * DN * es + (pa.mixed ? nv * es : 0.0)));
     if (pa.mixed)
-      k_vinit<D, float><<<nbu, 256, 0, s>>>(ma, b, lm, v, z, pa.z32, it32, pa.ratio, pa.kv, (float2*)zil);
+      k_vinit<D, float, VI><<<nbu, 256, 0, s>>>(ma, b, lm, v, z, pa.z32, it32, pa.ratio, pa.kv, (float2*)zil);
     else
-      k_vinit<D, double><<<nbu, 256, 0, s>>>(ma, b, lm, v, z, z, it64, pa.ratio, pa.kv, (double2*)zil);
+      k_vinit<D, double, VI><<<nbu, 256, 0, s>>>(ma, b, lm, v, z, z, it64, pa.ratio, pa.kv, (double2*)zil);
   }
   // S2 col/Ks/M, rowptr/dmask/Kd/Md; per system x_k (gathered, read once), b, x_{k-1} read, x_{k+1} written
   const double vbytes = (double)ma.nnz * (4.0 + 2.0 * vs) + n2 * (12.0 + 2.0 * vs) + na * 4.0 * DN * es;
@@ -678,27 +681,60 @@ void spmv_full(scvs_mesh m, const Batch& b, VArg x, VArg y, int mode, bool maskc
     full_launch<3>(&m->ctx->prof, ma, b, x, y, mode, maskcol, f, m->loads, ntr, trac, s);
 }
 
-void precond_apply(scvs_mesh m, const Batch& b, const PrecondArgs& pa, VArg v, VArg z, hipStream_t s, void* zil) {
+template <class VI>
+static void precond_any(scvs_mesh m, const Batch& b, const PrecondArgs& pa, SV<VI> v, VArg z, hipStream_t s,
+                        void* zil) {
   const MeshArgs ma = mesh_args(m);
   if (m->dim == 2)
-    precond_launch<2>(&m->ctx->prof, ma, b, pa, v, z, zil, s);
+    precond_launch<2, VI>(&m->ctx->prof, ma, b, pa, v, z, zil, s);
   else
-    precond_launch<3>(&m->ctx->prof, ma, b, pa, v, z, zil, s);
+    precond_launch<3, VI>(&m->ctx->prof, ma, b, pa, v, z, zil, s);
 }
 
-void spmv_apply_il(scvs_mesh m, const Batch& b, const void* xil, bool fp32, VArg y, hipStream_t s) {
+void precond_apply(scvs_mesh m, const Batch& b, const PrecondArgs& pa, VArg v, VArg z, hipStream_t s, void* zil) {
+  precond_any(m, b, pa, v, z, s, zil);
+}
+
+void precond_apply(scvs_mesh m, const Batch& b, const PrecondArgs& pa, VArg32 v, VArg z, hipStream_t s, void* zil) {
+  precond_any(m, b, pa, v, z, s, zil);
+}
+
+template <class YT>
+static void spmv_il_any(scvs_mesh m, const Batch& b, const void* xil, bool fp32, SV<YT> y, hipStream_t s) {
   const MeshArgs ma = mesh_args(m);
   if (m->dim == 2) {
     if (fp32)
-      full_launch_il<2, float>(&m->ctx->prof, ma, b, (const float2*)xil, y, s);
+      full_launch_il<2, float, YT>(&m->ctx->prof, ma, b, (const float2*)xil, y, s);
     else
-      full_launch_il<2, double>(&m->ctx->prof, ma, b, (const double2*)xil, y, s);
+      full_launch_il<2, double, YT>(&m->ctx->prof, ma, b, (const double2*)xil, y, s);
   } else {
     if (fp32)
-      full_launch_il<3, float>(&m->ctx->prof, ma, b, (const float2*)xil, y, s);
+      full_launch_il<3, float, YT>(&m->ctx->prof, ma, b, (const float2*)xil, y, s);
     else
-      full_launch_il<3, double>(&m->ctx->prof, ma, b, (const double2*)xil, y, s);
+      full_launch_il<3, double, YT>(&m->ctx->prof, ma, b, (const double2*)xil, y, s);
   }
+}
+
+void spmv_apply_il(scvs_mesh m, const Batch& b, const void* xil, bool fp32, VArg y, hipStream_t s) {
+  spmv_il_any(m, b, xil, fp32, y, s);
+}
+
+void spmv_apply_il(scvs_mesh m, const Batch& b, const void* xil, bool fp32, VArg32 y, hipStream_t s) {
+  spmv_il_any(m, b, xil, fp32, y, s);
+}
+
+void spmv_resid32(scvs_mesh m, const Batch& b, VArg x, VArg32 y, VArg f, hipStream_t s) {
+  const MeshArgs ma = mesh_args(m);
+  const int D = m->dim;
+  const LaneMap lm = lane_map(b.nact, D);
+  const unsigned nb = row_blocks(ma.n2, lm);
+  const double ndof = (double)D * ma.n2 + ma.nv;
+  ProfScope ps(&m->ctx->prof, s, "k_full_resid", full_bytes(ma, D, b.nact, SPMV_RESID) - b.nact * ndof * 8.0);
+  if (D == 2)
+    k_full<2, SPMV_RESID, true, double, false, float2><<<nb, 256, 0, s>>>(ma, b, lm, x, y, f, nullptr, 0, nullptr);
+  else
+    k_full<3, SPMV_RESID, true, double, false, float2><<<nb, 256, 0, s>>>(ma, b, lm, x, y, f, nullptr, 0, nullptr);
+  launch_check(s);
 }
 
 void spmv_apply32(scvs_mesh m, const Batch& b, VArg32 x, VArg y, hipStream_t s) {

@@ -207,15 +207,17 @@ def test_validation_errors(ctx):
         m.set_bc({1: 7})
 
 
-def test_solve_mixed_matches_lu(setup):
-    """FP32 operator and velocity polynomial inside FP64 refinement: modes
-    within 1e-8 (relative L2) of the LU solution."""
+@pytest.mark.parametrize("precision", [1, 2])
+def test_solve_mixed_matches_lu(setup, precision):
+    """FP32 operator and velocity polynomial inside FP64 refinement (2: with
+    the Krylov basis stored in FP32 as well): modes within 1e-8 (relative L2)
+    of the LU solution."""
     from paper_2009_06725_amd import scvs
     c, asm, m = setup["case"], setup["asm"], setup["m"]
     u_o, p_o, _, _ = solve_modes(asm, setup["loads"], setup["wall"], setup["dirn"], c["omega"], c["rho"],
                                  c["mu"], c["traction"], setup["g"])
     g = gpu_dirichlet(m, c, torch)
-    opts = scvs.default_opts(rtol=1e-12, precision=1)
+    opts = scvs.default_opts(rtol=1e-12, precision=precision)
     u, p, rep = m.solve(c["omega"], c["traction"], g, opts=opts)
     u, p = u.cpu().numpy(), p.cpu().numpy()
     print("[gpu]", setup["name"], "mixed iterations", [r.iterations for r in rep], flush=True)
