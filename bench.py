@@ -57,6 +57,8 @@ def parse():
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the plain per-mode FP64 GMRES comparator step")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="use the given restart and Chebyshev degrees instead of tuning them first")
     ap.add_argument("--no-error-check", action="store_true",
                     help="skip the tight-tolerance FP64 reference solve that estimates the error")
     ap.add_argument("--verbose", action="store_true")
@@ -157,6 +159,16 @@ def main():
                              precision={"fp64": 0, "mixed": 1, "mixed32": 2}[args.precision], orth=args.orth,
                              inner_rtol=args.inner_rtol)
     log(f"n2={info.n2} ndof={info.ndof} nnz_s2={info.nnz_s2} ingest+assembly {t_ingest:.2f}s")
+    tuned = None
+    if not args.no_autotune:
+        # untimed setup: the library times its candidate settings on these systems
+        log("autotune ...")
+        t0 = time.perf_counter()
+        best, best_ms = m.autotune(case["omega"], case["traction"], g, base=opts)
+        tuned = {"restart": best.restart, "cheb_vel": best.cheb_vel, "cheb_pres": best.cheb_pres,
+                 "tuning_seconds": round(time.perf_counter() - t0, 1), "candidate_ms": round(best_ms, 1)}
+        opts = best
+        log(f"autotune: {tuned}")
 
     def step():
         m.assemble(case["rho"], case["mu"])
@@ -217,8 +229,9 @@ def main():
                   }[args.precision],
         "data": "synthetic",
         "config": {"workload": f"pipe R=1 L=10, {mesh.nc} curved P2/P1 tets, {ns} modes (16 harmonics + mean)",
-                   "ndof": int(info.ndof), "modes": ns, "rtol": args.rtol, "restart": args.restart,
-                   "cheb_vel": args.cheb_vel, "cheb_pres": args.cheb_pres, "orth": args.orth, "inner_rtol": args.inner_rtol,
+                   "ndof": int(info.ndof), "modes": ns, "rtol": args.rtol, "restart": opts.restart,
+                   "cheb_vel": opts.cheb_vel, "cheb_pres": opts.cheb_pres, "autotuned": tuned,
+                   "orth": args.orth, "inner_rtol": args.inner_rtol, "precision": args.precision,
                    "ntimes": args.ntimes},
         "dof_modes_per_s": info.ndof * ns * args.steps / dt,
         "roofline": roof(dominant),
@@ -231,8 +244,8 @@ def main():
         # error of the timed solution: against an FP64 solve to a 100x tighter residual
         # (not below 1e-13, about where FP64 restarts stop gaining)
         rref = max(args.rtol * 1e-2, 1e-13)
-        ref = scvs.default_opts(rtol=rref, restart=args.restart, cheb_vel=args.cheb_vel,
-                                cheb_pres=args.cheb_pres, precision=0, verbose=1 if args.verbose else 0)
+        ref = scvs.default_opts(rtol=rref, restart=opts.restart, cheb_vel=opts.cheb_vel,
+                                cheb_pres=opts.cheb_pres, precision=0, verbose=1 if args.verbose else 0)
         ur = torch.empty_like(u)
         pr = torch.empty_like(p)
         log("error check: FP64 reference solve ...")
@@ -248,8 +261,8 @@ def main():
     if not args.no_compare:
         # comparator: plain per-mode FP64 GMRES (one system at a time, same
         # preconditioner, restart and tolerance, two-pass Gram-Schmidt)
-        plain = scvs.default_opts(rtol=args.rtol, restart=args.restart, cheb_vel=args.cheb_vel,
-                                  cheb_pres=args.cheb_pres, precision=0, max_batch=1, orth=0,
+        plain = scvs.default_opts(rtol=args.rtol, restart=opts.restart, cheb_vel=opts.cheb_vel,
+                                  cheb_pres=opts.cheb_pres, precision=0, max_batch=1, orth=0,
                                   verbose=1 if args.verbose else 0)
         u2 = torch.empty_like(u)
         p2 = torch.empty_like(p)

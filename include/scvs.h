@@ -223,6 +223,20 @@ int scvs_solve(scvs_mesh mesh, int64_t nsys, const double* omega, const double* 
                const void* g, const void* x0, void* u_out, void* p_out,
                const scvs_solve_opts* opts, scvs_report* rep);
 
+/* ---- a8: autotuner ----
+ * Times candidate solver settings on the caller's own systems (the same
+ * arguments as scvs_solve, no initial guesses) and returns the fastest in
+ * `best` (and its solve time in *best_ms, may be NULL). The candidates vary the
+ * restart length (160, 220), the pressure and velocity Chebyshev degrees
+ * (30/50, 8/10); every other field, including the precision, the tolerance and
+ * the orthogonalization, comes from `base` (NULL: the defaults). A candidate
+ * counts only if all systems converge. Each candidate is one full solve, so a
+ * call costs about 8 solves; the choice is cached in the context per (mesh,
+ * assembly, number of systems, precision, rtol) and later calls return it at
+ * once. Reassembly or new boundary conditions start a new entry. */
+int scvs_autotune(scvs_mesh mesh, int64_t nsys, const double* omega, const double* traction, const void* g,
+                  const scvs_solve_opts* base, scvs_solve_opts* best, double* best_ms);
+
 /* ---- a10: time synthesis (section 2.4, step 4, Eq. sol_reconstruct) ----
  * out[n][i] = sum_k c_k Re(modes[k][i] exp(j omega_k t_n)), c_k = 1 if
  * omega_k == 0 else 2 (real fields from the one-sided coefficients of

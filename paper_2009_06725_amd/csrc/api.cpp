@@ -1,4 +1,5 @@
 // C ABI of the SCVS library: validation, object lifetime, error reporting.
+#include <chrono>
 #include <cmath>
 #include <memory>
 
@@ -36,6 +37,21 @@ void require_ready(scvs_mesh m) {
   SCVS_REQUIRE(m, SCVS_E_INVALID, "mesh is null");
   SCVS_REQUIRE(m->bc_set, SCVS_E_STATE, "boundary conditions not set (call scvs_mesh_set_bc)");
   SCVS_REQUIRE(m->assembled, SCVS_E_STATE, "matrices not assembled (call scvs_assemble)");
+}
+
+// Options from the caller (or the defaults), validated.
+scvs_solve_opts checked_opts(const scvs_solve_opts* opts) {
+  scvs_solve_opts o;
+  if (opts)
+    o = *opts;
+  else
+    scvs_solve_opts_default(&o);
+  SCVS_REQUIRE(o.rtol > 0.0 && o.restart >= 1 && o.restart <= SCVS_MMAX && o.max_iters >= 1 && o.cheb_vel >= 1 &&
+                   o.cheb_pres >= 1 && o.cheb_ratio > 1.0 && o.max_batch >= 0 &&
+                   (o.precision >= 0 && o.precision <= 2) && (o.orth == 0 || o.orth == 1) &&
+                   (o.precision != 2 || o.orth == 1) && o.inner_rtol >= 0.0 && o.inner_rtol < 1.0,
+               SCVS_E_INVALID, "bad solve options");
+  return o;
 }
 
 }  // namespace
@@ -296,20 +312,61 @@ int scvs_solve(scvs_mesh m, int64_t nsys, const double* omega, const double* tra
     SCVS_REQUIRE(nsys > 0 && omega && u_out && p_out, SCVS_E_INVALID, "bad solve arguments");
     SCVS_REQUIRE(m->traction_tags.empty() || traction, SCVS_E_INVALID, "traction is null");
     SCVS_REQUIRE(m->ndir == 0 || g, SCVS_E_INVALID, "g is null but the mesh has Dirichlet nodes");
-    scvs_solve_opts o;
-    if (opts)
-      o = *opts;
-    else
-      scvs_solve_opts_default(&o);
-    SCVS_REQUIRE(o.rtol > 0.0 && o.restart >= 1 && o.restart <= SCVS_MMAX && o.max_iters >= 1 &&
-                     o.cheb_vel >= 1 && o.cheb_pres >= 1 && o.cheb_ratio > 1.0 && o.max_batch >= 0 &&
-                     (o.precision >= 0 && o.precision <= 2) && (o.orth == 0 || o.orth == 1) &&
-                     (o.precision != 2 || o.orth == 1) &&
-                     o.inner_rtol >= 0.0 && o.inner_rtol < 1.0,
-                 SCVS_E_INVALID, "bad solve options");
+    const scvs_solve_opts o = checked_opts(opts);
     for (int64_t k = 0; k < nsys; ++k) SCVS_REQUIRE(std::isfinite(omega[k]), SCVS_E_INVALID, "non-finite omega");
     use_device(m->ctx);
     scvs::solve_systems(m, nsys, omega, traction, m->ndir ? g : nullptr, x0, u_out, p_out, &o, rep);
+  });
+}
+
+int scvs_autotune(scvs_mesh m, int64_t nsys, const double* omega, const double* traction, const void* g,
+                  const scvs_solve_opts* base, scvs_solve_opts* best, double* best_ms) {
+  return guarded([&] {
+    require_ready(m);
+    SCVS_REQUIRE(nsys > 0 && nsys <= 4096 && omega && best, SCVS_E_INVALID, "bad autotune arguments");
+    SCVS_REQUIRE(m->traction_tags.empty() || traction, SCVS_E_INVALID, "traction is null");
+    SCVS_REQUIRE(m->ndir == 0 || g, SCVS_E_INVALID, "g is null but the mesh has Dirichlet nodes");
+    const scvs_solve_opts b = checked_opts(base);
+    for (int64_t k = 0; k < nsys; ++k) SCVS_REQUIRE(std::isfinite(omega[k]), SCVS_E_INVALID, "non-finite omega");
+    use_device(m->ctx);
+    const auto key = std::make_tuple((const void*)m, m->generation, nsys, (int)b.precision, b.rtol);
+    auto hit = m->ctx->tuned.find(key);
+    if (hit == m->ctx->tuned.end()) {
+      scvs::DBuf<double2> u, p;
+      u.alloc((size_t)nsys * m->n2 * m->dim);
+      p.alloc((size_t)nsys * m->nv);
+      std::vector<scvs_report> rep(nsys);
+      scvs_solve_opts pick = b;
+      double pick_ms = -1.0;
+      const int ms_[] = {160, 220};
+      const int kp_[] = {30, 50};
+      const int kv_[] = {8, 10};
+      for (int mm : ms_)
+        for (int kp : kp_)
+          for (int kv : kv_) {
+            scvs_solve_opts c = b;
+            c.restart = std::min(mm, SCVS_MMAX);
+            c.cheb_pres = kp;
+            c.cheb_vel = kv;
+            const auto t0 = std::chrono::steady_clock::now();
+            scvs::solve_systems(m, nsys, omega, traction, m->ndir ? g : nullptr, nullptr, u.p, p.p, &c, rep.data());
+            const double ms =
+                std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+            bool ok = true;
+            for (const auto& r : rep) ok = ok && r.status == 0;
+            if (b.verbose)
+              fprintf(stderr, "[scvs] autotune m %d Chebyshev %d/%d: %.1f ms%s\n", c.restart, kv, kp, ms,
+                      ok ? "" : " (not converged)");
+            if (ok && (pick_ms < 0.0 || ms < pick_ms)) {
+              pick = c;
+              pick_ms = ms;
+            }
+          }
+      SCVS_REQUIRE(pick_ms >= 0.0, SCVS_E_STATE, "no candidate configuration converged");
+      hit = m->ctx->tuned.emplace(key, scvs_ctx_s::Tuned{pick, pick_ms}).first;
+    }
+    *best = hit->second.opts;
+    if (best_ms) *best_ms = hit->second.ms;
   });
 }
 

@@ -11,6 +11,8 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <map>
+#include <tuple>
 #include <vector>
 
 #include "../../include/scvs.h"
@@ -128,6 +130,12 @@ struct scvs_ctx_s {
   hipStream_t stream = nullptr;   // caller's stream: all work runs here
   hipStream_t capture = nullptr;  // private stream used only to record graphs
   scvs::Profiler prof;
+  // autotuner results: (mesh, assembly generation, systems, precision, rtol) -> options, ms
+  struct Tuned {
+    scvs_solve_opts opts;
+    double ms;
+  };
+  std::map<std::tuple<const void*, uint64_t, int64_t, int, double>, Tuned> tuned;
 };
 
 constexpr int SCVS_MMAX = 256;  // largest Krylov dimension per cycle

@@ -23,7 +23,7 @@ EXPORTED = [
     "scvs_last_error", "scvs_version", "scvs_ctx_create", "scvs_ctx_destroy", "scvs_mesh_create",
     "scvs_mesh_destroy", "scvs_mesh_info", "scvs_mesh_set_midside", "scvs_mesh_set_bc", "scvs_assemble",
     "scvs_mesh_export", "scvs_spmv", "scvs_rhs", "scvs_solve_opts_default", "scvs_solve",
-    "scvs_synthesize", "scvs_probe_mfma", "scvs_profile_enable", "scvs_profile_read",
+    "scvs_autotune", "scvs_synthesize", "scvs_probe_mfma", "scvs_profile_enable", "scvs_profile_read",
     "scvs_ws_create", "scvs_ws_train", "scvs_ws_predict", "scvs_ws_refine", "scvs_ws_destroy", "scvs_ws_export",
     "scvs_ws_set_params", "scvs_ws_loss_grad", "scvs_herm_eig", "scvs_probe_mfma_bf16",
 ]
@@ -86,6 +86,8 @@ def lib() -> C.CDLL:
         L.scvs_solve_opts_default.argtypes = [C.POINTER(SolveOpts)]
         L.scvs_solve_opts_default.restype = None
         L.scvs_solve.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, C.POINTER(SolveOpts), C.POINTER(Report)]
+        L.scvs_autotune.argtypes = [vp, i64, vp, vp, vp, C.POINTER(SolveOpts), C.POINTER(SolveOpts),
+                                    C.POINTER(C.c_double)]
         L.scvs_synthesize.argtypes = [vp, i64, vp, vp, i64, i64, vp, vp]
         L.scvs_probe_mfma.argtypes = [vp, vp, vp, vp]
         L.scvs_profile_enable.argtypes = [vp, C.c_int]
@@ -266,6 +268,22 @@ class Mesh:
         _check(lib().scvs_solve(self.h, ns, po, pt, pg, px, _dev(u, "torch.complex128"),
                                 _dev(p, "torch.complex128"), C.byref(o), reps))
         return u, p, list(reps)
+
+    def autotune(self, omega, traction, g=None, base: SolveOpts | None = None):
+        """Fastest of the library's candidate settings for these systems: (opts, ms)."""
+        i = self.info
+        om, po = _host(omega, np.float64)
+        ns = om.size
+        tr = np.asarray(traction, np.complex128)
+        if i.ntraction and tr.size == ns * i.ntraction:
+            tr = tr.reshape(ns, i.ntraction)
+        tr, pt = _host(tr.view(np.float64), np.float64)
+        pg = _dev(g, "torch.complex128") if g is not None else None
+        best = SolveOpts()
+        ms = C.c_double()
+        b = base if base is not None else default_opts()
+        _check(lib().scvs_autotune(self.h, ns, po, pt, pg, C.byref(b), C.byref(best), C.byref(ms)))
+        return best, ms.value
 
 
 def synthesize(ctx: Context, omega, modes, times, out=None):

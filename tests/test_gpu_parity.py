@@ -243,3 +243,34 @@ def test_orthogonalization_variants_agree(setup):
         for s in range(len(c["omega"])):
             eu, ep = rel_l2(asm, u[s], res[0][0][s], p[s], res[0][1][s])
             assert eu <= 1e-9 and ep <= 1e-9
+
+
+def test_autotune_caches_and_solves(ctx):
+    """The autotuner picks one of its candidates, caches the choice per mesh and
+    assembly, and the chosen settings solve to LU accuracy."""
+    import time
+    from paper_2009_06725_amd import scvs
+    c = cases.channel_case()
+    m = gpu_mesh(ctx, c)
+    g = gpu_dirichlet(m, c, torch)
+    base = scvs.default_opts(rtol=1e-12)
+    t0 = time.perf_counter()
+    best, ms = m.autotune(c["omega"], c["traction"], g, base=base)
+    t1 = time.perf_counter()
+    assert best.restart in (160, 220) and best.cheb_pres in (30, 50) and best.cheb_vel in (8, 10)
+    assert best.rtol == base.rtol and best.precision == base.precision and ms > 0
+    best2, ms2 = m.autotune(c["omega"], c["traction"], g, base=base)
+    t2 = time.perf_counter()
+    assert (best2.restart, best2.cheb_pres, best2.cheb_vel, ms2) == (best.restart, best.cheb_pres, best.cheb_vel, ms)
+    assert t2 - t1 < 0.1 * (t1 - t0)
+    asm, loads, wall, dirn, gv = case_setup(c)
+    u_o, p_o, _, _ = solve_modes(asm, loads, wall, dirn, c["omega"], c["rho"], c["mu"], c["traction"], gv)
+    u, p, rep = m.solve(c["omega"], c["traction"], g, opts=best)
+    assert all(r.status == 0 for r in rep)
+    for s in range(len(c["omega"])):
+        eu, ep = rel_l2(asm, u[s].cpu().numpy(), u_o[s], p[s].cpu().numpy(), p_o[s])
+        assert eu <= 1e-9 and ep <= 1e-9
+    m.assemble(c["rho"], c["mu"])  # a new assembly is tuned afresh
+    t3 = time.perf_counter()
+    m.autotune(c["omega"], c["traction"], g, base=base)
+    assert time.perf_counter() - t3 > 5 * (t2 - t1)
