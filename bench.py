@@ -46,6 +46,10 @@ def parse():
     ap.add_argument("--restart", type=int, default=200)
     ap.add_argument("--cheb-vel", type=int, default=10)
     ap.add_argument("--cheb-pres", type=int, default=50)
+    ap.add_argument("--cheb-ratio", type=float, default=300.0,
+                    help="the polynomials target [lambda_max/ratio, lambda_max] of the Jacobi-scaled blocks")
+    ap.add_argument("--cheb-ratio-pres", type=float, default=1000.0,
+                    help="interval ratio of the pressure polynomial (0: --cheb-ratio)")
     ap.add_argument("--ntimes", type=int, default=64)
     ap.add_argument("--precision", choices=["fp64", "mixed", "mixed32"], default="mixed",
                     help="mixed: FP32 operator and velocity block in FP64 refinement; mixed32: also an FP32 "
@@ -155,7 +159,8 @@ def main():
     ut = torch.empty((args.ntimes, info.n2 * 3), dtype=torch.float64, device="cuda")
     pt = torch.empty((args.ntimes, info.nv), dtype=torch.float64, device="cuda")
     opts = scvs.default_opts(rtol=args.rtol, restart=args.restart, cheb_vel=args.cheb_vel,
-                             cheb_pres=args.cheb_pres, verbose=1 if args.verbose else 0,
+                             cheb_pres=args.cheb_pres, cheb_ratio=args.cheb_ratio,
+                             cheb_ratio_pres=args.cheb_ratio_pres, verbose=1 if args.verbose else 0,
                              precision={"fp64": 0, "mixed": 1, "mixed32": 2}[args.precision], orth=args.orth,
                              inner_rtol=args.inner_rtol)
     log(f"n2={info.n2} ndof={info.ndof} nnz_s2={info.nnz_s2} ingest+assembly {t_ingest:.2f}s")
@@ -230,7 +235,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"pipe R=1 L=10, {mesh.nc} curved P2/P1 tets, {ns} modes (16 harmonics + mean)",
                    "ndof": int(info.ndof), "modes": ns, "rtol": args.rtol, "restart": opts.restart,
-                   "cheb_vel": opts.cheb_vel, "cheb_pres": opts.cheb_pres, "autotuned": tuned,
+                   "cheb_vel": opts.cheb_vel, "cheb_pres": opts.cheb_pres, "cheb_ratio": opts.cheb_ratio,
+                   "cheb_ratio_pres": opts.cheb_ratio_pres,
+                   "autotuned": tuned,
                    "orth": args.orth, "inner_rtol": args.inner_rtol, "precision": args.precision,
                    "ntimes": args.ntimes},
         "dof_modes_per_s": info.ndof * ns * args.steps / dt,
@@ -245,7 +252,9 @@ def main():
         # (not below 1e-13, about where FP64 restarts stop gaining)
         rref = max(args.rtol * 1e-2, 1e-13)
         ref = scvs.default_opts(rtol=rref, restart=opts.restart, cheb_vel=opts.cheb_vel,
-                                cheb_pres=opts.cheb_pres, precision=0, verbose=1 if args.verbose else 0)
+                                cheb_pres=opts.cheb_pres, cheb_ratio=opts.cheb_ratio,
+                                cheb_ratio_pres=opts.cheb_ratio_pres, precision=0,
+                                verbose=1 if args.verbose else 0)
         ur = torch.empty_like(u)
         pr = torch.empty_like(p)
         log("error check: FP64 reference solve ...")
@@ -262,7 +271,9 @@ def main():
         # comparator: plain per-mode FP64 GMRES (one system at a time, same
         # preconditioner, restart and tolerance, two-pass Gram-Schmidt)
         plain = scvs.default_opts(rtol=args.rtol, restart=opts.restart, cheb_vel=opts.cheb_vel,
-                                  cheb_pres=opts.cheb_pres, precision=0, max_batch=1, orth=0,
+                                  cheb_pres=opts.cheb_pres, cheb_ratio=opts.cheb_ratio,
+                                cheb_ratio_pres=opts.cheb_ratio_pres, precision=0, max_batch=1,
+                                  orth=0,
                                   verbose=1 if args.verbose else 0)
         u2 = torch.empty_like(u)
         p2 = torch.empty_like(p)

@@ -177,7 +177,8 @@ typedef struct {
   int32_t max_iters;  /* cap on Arnoldi steps per system */
   int32_t cheb_vel;   /* Chebyshev degree of the velocity block, >= 1 */
   int32_t cheb_pres;  /* Chebyshev degree of the pressure Laplacian, >= 1 */
-  double cheb_ratio;  /* assumed lambda_max / lambda_min of the Jacobi-scaled blocks */
+  double cheb_ratio;  /* the polynomials target [lambda_max / cheb_ratio, lambda_max] of the
+                         Jacobi-scaled blocks (lambda_max from a Gershgorin bound) */
   int32_t max_batch;  /* systems solved together (0 = as many as fit) */
   int32_t use_graph;  /* replay the steps of each cycle, in chunks of 30, from captured hipGraphs */
   int32_t verbose;    /* print per-cycle residuals to stderr */
@@ -193,13 +194,15 @@ typedef struct {
                          pass of each vector lagged into the next step's single reduction
                          (DCGS2, Swirydowicz et al. 2020; two passes per step, one extra
                          closing reduction per cycle) */
+  double cheb_ratio_pres; /* interval ratio of the pressure-Laplacian polynomial (0: cheb_ratio) */
   double inner_rtol;  /* mixed precision only: a restart cycle also ends once its own residual
                          estimate has fallen by this factor (the FP32 operator cannot take the
                          true residual much further within one cycle); 0 = only at rtol or m */
 } scvs_solve_opts;
 
 /* Fill `o` with the defaults (rtol 1e-10, m 200, 20000 iterations, degrees 10/50,
- * ratio 30, batch 0, graphs on, FP64, lagged orthogonalization, inner_rtol 1e-5). */
+ * ratios 300 (velocity) / 1000 (pressure), batch 0, graphs on, FP64, lagged
+ * orthogonalization, inner_rtol 1e-5). */
 void scvs_solve_opts_default(scvs_solve_opts* o);
 
 typedef struct {

@@ -252,7 +252,8 @@ void spmv_full(scvs_mesh m, const Batch& b, VArg x, VArg y, int mode, bool maskc
 // Block upper-triangular preconditioner z = P^-1 (insc * v); temps per slot.
 struct PrecondArgs {
   int kv = 10, kp = 10;
-  double ratio = 30.0;
+  double ratio = 30.0;    // velocity block interval lmax/ratio..lmax
+  double ratio_p = 30.0;  // pressure Laplacian interval
   int mixed = 0;  // 1: velocity block in FP32 (vt32, output z32); pressure block stays FP64
   VArg32 vt32;    // FP32 velocity temps: 4 * d*n2 per slot
   VArg32 z32;     // FP32 preconditioned vector (velocity part, plus a copy of the pressure part)

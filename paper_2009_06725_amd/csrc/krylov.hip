@@ -1086,6 +1086,7 @@ int solve_systems(scvs_mesh m, int64_t nsys, const double* omega, const double* 
   pa.kv = o->cheb_vel;
   pa.kp = o->cheb_pres;
   pa.ratio = o->cheb_ratio;
+  pa.ratio_p = o->cheb_ratio_pres > 0.0 ? o->cheb_ratio_pres : o->cheb_ratio;
   pa.vt = VArg{P.vt.p, 4 * DN};
   pa.mixed = mixed ? 1 : 0;
   pa.vt32 = VArg32{P.vt32.p, 4 * DN};

@@ -316,20 +316,20 @@ __global__ void __launch_bounds__(256) k_full(MeshArgs ma, Batch b, LaneMap lm, 
 }
 
 // Chebyshev recurrence scalars for step i >= 1 on [lmax/ratio, lmax]:
-// rho_0 = 1/sigma, rho_k = 1/(2 sigma - rho_{k-1}); returns rho_{i-1}, rho_i, delta.
-__device__ __forceinline__ void cheb_coef(double lmax, double ratio, int i, double& rprev, double& rcur,
-                                          double& delta, double& theta) {
-  const double lmin = lmax / ratio;
-  theta = 0.5 * (lmax + lmin);
-  delta = 0.5 * (lmax - lmin);
-  const double sigma = theta / delta;
+// rho_0 = 1/sigma, rho_k = 1/(2 sigma - rho_{k-1}) with sigma = theta/delta =
+// (1 + 1/ratio)/(1 - 1/ratio), which does not depend on lmax; returns rho_{i-1}, rho_i.
+// (Computed once per step on the host; the kernels form theta and delta from lmax.)
+struct ChebStep {
+  double rprev, rcur;
+};
+inline ChebStep cheb_step(double ratio, int i) {
+  const double sigma = (1.0 + 1.0 / ratio) / (1.0 - 1.0 / ratio);
   double r = 1.0 / sigma, rp = r;
   for (int k = 1; k <= i; ++k) {
     rp = r;
     r = 1.0 / (2.0 * sigma - r);
   }
-  rprev = rp;
-  rcur = r;
+  return {rp, r};
 }
 
 // Velocity block, Chebyshev polynomial in diag^-1 A_r with A_r = mu Ks + |w| rho M
@@ -405,8 +405,8 @@ __global__ void __launch_bounds__(256) k_vinit(MeshArgs ma, Batch b, LaneMap lm,
 
 template <int D, class R>
 __global__ void __launch_bounds__(256) k_vstep(MeshArgs ma, Batch b, LaneMap lm, typename Prec<R>::V z,
-                                               ITemps<typename Prec<R>::C> vt, double ratio, int step, int last,
-                                               typename Prec<R>::C* __restrict__ zil) {
+                                               ITemps<typename Prec<R>::C> vt, double ratio, ChebStep cs, int step,
+                                               int last, typename Prec<R>::C* __restrict__ zil) {
   using C = typename Prec<R>::C;
   const Lane L = lane_of(lm, ma.n2);
   if (!L.rowok) return;  // uniform over the row group
@@ -429,8 +429,7 @@ __global__ void __launch_bounds__(256) k_vstep(MeshArgs ma, Batch b, LaneMap lm,
     C q = czero<C>(), unused = czero<C>();
     row_acc<D, false, R>(ma, lm.W, L.li, j0, j1, xk, lm.G, p, c, ok, wr, (R)0, true, false, q, unused);
     if (!ok) continue;
-    double rp, rc, delta, theta;
-    cheb_coef(b.lv[slot], ratio, step, rp, rc, delta, theta);
+    const double rp = cs.rprev, rc = cs.rcur, delta = 0.5 * b.lv[slot] * (1.0 - 1.0 / ratio);
     const R dinv = (R)1 / ((R)ma.mu * Prec<R>::Kd(ma)[A] + wr * Prec<R>::Md(ma)[A]);
     const C bv = vt.arr(0)[ki], xv = xk[ki];
     const C xo = (step == 1) ? czero<C>() : vt.iter(step - 1)[ki];
@@ -471,7 +470,7 @@ __global__ void k_pinit(MeshArgs ma, int D, Batch b, SV<VI> v, VArg z, ITemps<do
 // zhat_p = -(mu Mp^-1 v_p + j w rho x). A column's values of all systems are adjacent.
 template <class VI>
 __global__ void __launch_bounds__(256) k_pstep(MeshArgs ma, int D, Batch b, LaneMap lm, SV<VI> v, VArg z,
-                                               ITemps<double2> pt, double ratio, int step, int last) {
+                                               ITemps<double2> pt, double ratio, ChebStep cs, int step, int last) {
   const Lane L = lane_of(lm, ma.nv);
   const int G = pt.G;
   for (int it = 0; it < lm.iters; ++it) {
@@ -509,8 +508,7 @@ __global__ void __launch_bounds__(256) k_pstep(MeshArgs ma, int D, Batch b, Lane
       q.x += l * dv.x;
       q.y += l * dv.y;
     }
-    double rpv, rc, delta, theta;
-    cheb_coef(ma.lpmax, ratio, step, rpv, rc, delta, theta);
+    const double rpv = cs.rprev, rc = cs.rcur, delta = 0.5 * ma.lpmax * (1.0 - 1.0 / ratio);
     const double2 rn = csub(rp[ki], q);
     const double ca = rc * rpv, cb = 2.0 * rc / delta * ma.lpdinv[A];
     const double2 dk = dold[ki];
@@ -628,14 +626,15 @@ void precond_launch(Profiler* prof, const MeshArgs& ma, const Batch& b, const Pr
   {
     // per system: v_p read, r/d0/x written (and z_p when one step); lpdinv, Mp read
     ProfScope ps(prof, s, "k_pinit", nv * 16.0 + na * nv * 16.0 * 4.0);
-    k_pinit<VI><<<gp, 256, 0, s>>>(ma, D, b, v, z, ptl, pa.ratio, pa.kp);
+    k_pinit<VI><<<gp, 256, 0, s>>>(ma, D, b, v, z, ptl, pa.ratio_p, pa.kp);
   }
   // L values and columns, row pointers, diag, Mp; per system d_old gathered,
   // r read+written, d_new written, x read+written
   const double pbytes = (double)ma.nnzl * 12.0 + nv * 24.0 + na * nv * 16.0 * 6.0;
   for (int i = 1; i < pa.kp; ++i) {
     ProfScope ps(prof, s, "k_pstep", pbytes + (i == pa.kp - 1 ? na * nv * 32.0 : 0.0));
-    k_pstep<VI><<<nbp, 256, 0, s>>>(ma, D, b, lp, v, z, ptl, pa.ratio, i, i == pa.kp - 1);
+    k_pstep<VI><<<nbp, 256, 0, s>>>(ma, D, b, lp, v, z, ptl, pa.ratio_p, cheb_step(pa.ratio_p, i), i,
+                                    i == pa.kp - 1);
   }
   const double es = pa.mixed ? 8.0 : 16.0, vs = pa.mixed ? 4.0 : 8.0;  // complex / real element bytes
   // interleaved temporaries inside the slot pool's temp block (4 * D*n2 per slot, contiguous)
@@ -657,9 +656,11 @@ void precond_launch(Profiler* prof, const MeshArgs& ma, const Batch& b, const Pr
   for (int i = 1; i < pa.kv; ++i) {
     ProfScope ps(prof, s, pa.mixed ? "k_vstep32" : "k_vstep", vbytes);
     if (pa.mixed)
-      k_vstep<D, float><<<nbu, 256, 0, s>>>(ma, b, lm, pa.z32, it32, pa.ratio, i, i == pa.kv - 1, (float2*)zil);
+      k_vstep<D, float><<<nbu, 256, 0, s>>>(ma, b, lm, pa.z32, it32, pa.ratio, cheb_step(pa.ratio, i), i,
+                                            i == pa.kv - 1, (float2*)zil);
     else
-      k_vstep<D, double><<<nbu, 256, 0, s>>>(ma, b, lm, z, it64, pa.ratio, i, i == pa.kv - 1, (double2*)zil);
+      k_vstep<D, double><<<nbu, 256, 0, s>>>(ma, b, lm, z, it64, pa.ratio, cheb_step(pa.ratio, i), i,
+                                             i == pa.kv - 1, (double2*)zil);
   }
   launch_check(s);
 }
