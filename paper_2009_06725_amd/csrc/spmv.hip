@@ -465,65 +465,65 @@ __global__ void k_pinit(MeshArgs ma, int D, Batch b, SV<VI> v, VArg z, ITemps<do
   }
 }
 
-// Pressure Laplacian Chebyshev step on the assembled L (one lane per system):
-// r -= L d_old; d_new = a d_old + b diag(L)^-1 r; x += d_new; on the last step
-// zhat_p = -(mu Mp^-1 v_p + j w rho x). A column's values of all systems are adjacent.
+// Pressure Laplacian Chebyshev step on the assembled L: r -= L d_old; d_new = a d_old +
+// b diag(L)^-1 r; x += d_new; on the last step zhat_p = -(mu Mp^-1 v_p + j w rho x).
+// Lanes do not cooperate here, so threads map linearly onto (vertex, system) pairs: every
+// lane works, and the systems of one vertex sit in adjacent lanes (coalesced gathers).
 template <class VI>
-__global__ void __launch_bounds__(256) k_pstep(MeshArgs ma, int D, Batch b, LaneMap lm, SV<VI> v, VArg z,
-                                               ITemps<double2> pt, double ratio, ChebStep cs, int step, int last) {
-  const Lane L = lane_of(lm, ma.nv);
+__global__ void __launch_bounds__(256) k_pstep(MeshArgs ma, int D, Batch b, SV<VI> v, VArg z, ITemps<double2> pt,
+                                               double ratio, ChebStep cs, int step, int last) {
   const int G = pt.G;
-  for (int it = 0; it < lm.iters; ++it) {
-    const int p = L.li + it * lm.UL;
-    if (!(L.rowok && L.pairok0 && p < lm.G)) continue;
-    const int slot = b.act[p];
-    const int64_t A = L.row, ki = A * G + p;
-    double2* rp = pt.arr(0);
-    const double2* __restrict__ dold = pt.arr((step & 1) ? 1 : 2);
-    double2* dnew = pt.arr((step & 1) ? 2 : 1);
-    double2* xp = pt.arr(3);
-    double2 q = make_double2(0.0, 0.0);
-    const int64_t k0 = ma.lp_ptr[A], k1 = ma.lp_ptr[A + 1];
-    int64_t k = k0;
-    for (; k + 4 <= k1; k += 4) {
-      int32_t u[4];
-      double l[4];
-      double2 dv[4];
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= ma.nv * G) return;
+  const int64_t A = idx / G;
+  const int p = (int)(idx - A * G);
+  const int slot = b.act[p];
+  const int64_t ki = idx;  // = A * G + p
+  double2* rp = pt.arr(0);
+  const double2* __restrict__ dold = pt.arr((step & 1) ? 1 : 2);
+  double2* dnew = pt.arr((step & 1) ? 2 : 1);
+  double2* xp = pt.arr(3);
+  double2 q = make_double2(0.0, 0.0);
+  const int64_t k0 = ma.lp_ptr[A], k1 = ma.lp_ptr[A + 1];
+  int64_t k = k0;
+  for (; k + 4 <= k1; k += 4) {
+    int32_t u[4];
+    double l[4];
+    double2 dv[4];
 #pragma unroll
-      for (int t = 0; t < 4; ++t) u[t] = ma.lp_col[k + t];
+    for (int t = 0; t < 4; ++t) u[t] = ma.lp_col[k + t];
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        l[t] = ma.lp_val[k + t];
-        dv[t] = dold[(int64_t)u[t] * G + p];
-      }
+    for (int t = 0; t < 4; ++t) {
+      l[t] = ma.lp_val[k + t];
+      dv[t] = dold[(int64_t)u[t] * G + p];
+    }
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        q.x += l[t] * dv[t].x;
-        q.y += l[t] * dv[t].y;
-      }
+    for (int t = 0; t < 4; ++t) {
+      q.x += l[t] * dv[t].x;
+      q.y += l[t] * dv[t].y;
     }
-    for (; k < k1; ++k) {
-      const double l = ma.lp_val[k];
-      const double2 dv = dold[(int64_t)ma.lp_col[k] * G + p];
-      q.x += l * dv.x;
-      q.y += l * dv.y;
-    }
-    const double rpv = cs.rprev, rc = cs.rcur, delta = 0.5 * ma.lpmax * (1.0 - 1.0 / ratio);
-    const double2 rn = csub(rp[ki], q);
-    const double ca = rc * rpv, cb = 2.0 * rc / delta * ma.lpdinv[A];
-    const double2 dk = dold[ki];
-    const double2 dn = make_double2(ca * dk.x + cb * rn.x, ca * dk.y + cb * rn.y);
-    const double2 xn = cadd(xp[ki], dn);
-    rp[ki] = rn;
-    dnew[ki] = dn;
-    xp[ki] = xn;
-    if (last) {
-      const int64_t DN = D * ma.n2;
-      const double sc = in_scale(b, slot);
-      const double2 vp = cscale(to_d2(v.at(slot)[DN + A]), sc);
-      const double wr = b.omega[slot] * ma.rho, im = ma.mu / ma.Mp[A];
-      z.at(slot)[DN + A] = make_double2(-(im * vp.x - wr * xn.y), -(im * vp.y + wr * xn.x));
-    }
+  }
+  for (; k < k1; ++k) {
+    const double l = ma.lp_val[k];
+    const double2 dv = dold[(int64_t)ma.lp_col[k] * G + p];
+    q.x += l * dv.x;
+    q.y += l * dv.y;
+  }
+  const double rpv = cs.rprev, rc = cs.rcur, delta = 0.5 * ma.lpmax * (1.0 - 1.0 / ratio);
+  const double2 rn = csub(rp[ki], q);
+  const double ca = rc * rpv, cb = 2.0 * rc / delta * ma.lpdinv[A];
+  const double2 dk = dold[ki];
+  const double2 dn = make_double2(ca * dk.x + cb * rn.x, ca * dk.y + cb * rn.y);
+  const double2 xn = cadd(xp[ki], dn);
+  rp[ki] = rn;
+  dnew[ki] = dn;
+  xp[ki] = xn;
+  if (last) {
+    const int64_t DN = D * ma.n2;
+    const double sc = in_scale(b, slot);
+    const double2 vp = cscale(to_d2(v.at(slot)[DN + A]), sc);
+    const double wr = b.omega[slot] * ma.rho, im = ma.mu / ma.Mp[A];
+    z.at(slot)[DN + A] = make_double2(-(im * vp.x - wr * xn.y), -(im * vp.y + wr * xn.x));
   }
 }
 
@@ -617,8 +617,9 @@ void full_launch_il(Profiler* prof, const MeshArgs& ma, const Batch& b, const ty
 template <int D, class VI>
 void precond_launch(Profiler* prof, const MeshArgs& ma, const Batch& b, const PrecondArgs& pa, SV<VI> v, VArg z,
                     void* zil, hipStream_t s) {
-  const LaneMap lm = lane_map(b.nact, D), lp = lane_map(b.nact, 1);
-  const unsigned nbu = row_blocks(ma.n2, lm), nbp = row_blocks(ma.nv, lp);
+  const LaneMap lm = lane_map(b.nact, D);
+  const unsigned nbu = row_blocks(ma.n2, lm);
+  const unsigned nbp = (unsigned)((ma.nv * b.nact + 255) / 256);  // k_pstep: one thread per (vertex, system)
   const double n2 = (double)ma.n2, nv = (double)ma.nv, DN = (double)D * ma.n2, na = b.nact;
   dim3 gp((unsigned)((ma.nv + 255) / 256), (unsigned)b.nact);
   // interleaved pressure temporaries inside the slot pool's block (4 * nv per slot, contiguous)
@@ -633,8 +634,7 @@ void precond_launch(Profiler* prof, const MeshArgs& ma, const Batch& b, const Pr
   const double pbytes = (double)ma.nnzl * 12.0 + nv * 24.0 + na * nv * 16.0 * 6.0;
   for (int i = 1; i < pa.kp; ++i) {
     ProfScope ps(prof, s, "k_pstep", pbytes + (i == pa.kp - 1 ? na * nv * 32.0 : 0.0));
-    k_pstep<VI><<<nbp, 256, 0, s>>>(ma, D, b, lp, v, z, ptl, pa.ratio_p, cheb_step(pa.ratio_p, i), i,
-                                    i == pa.kp - 1);
+    k_pstep<VI><<<nbp, 256, 0, s>>>(ma, D, b, v, z, ptl, pa.ratio_p, cheb_step(pa.ratio_p, i), i, i == pa.kp - 1);
   }
   const double es = pa.mixed ? 8.0 : 16.0, vs = pa.mixed ? 4.0 : 8.0;  // complex / real element bytes
   // interleaved temporaries inside the slot pool's temp block (4 * D*n2 per slot, contiguous)
