@@ -99,3 +99,20 @@ def test_c21_is_vertex_prefix_of_s2():
     rows21 = np.repeat(np.arange(n2), np.diff(rp21))
     for v in range(0, m.nv, 5):
         assert np.array_equal(np.sort(rows21[col21 == v]), col[rp[v]:rp[v + 1]])
+
+
+def test_vessel_meshes_are_balls_with_tagged_openings():
+    """The voxel vessel meshes are single balls (V - E + F - T = 1), every
+    boundary facet is used by one tet, and every opening got its tag."""
+    from workloads.meshes import INLET, WALL, vessel_tree_mesh, y_bifurcation_mesh
+    for m, n_out in ((y_bifurcation_mesh(0.35), 2), (vessel_tree_mesh(0.25, 3), 8)):
+        edges, _ = p2_numbering(m.nv, m.cells)
+        F = (4 * m.nc + m.bfaces.shape[0]) // 2
+        assert m.nv - edges.shape[0] + F - m.nc == 1, m.name
+        tags = set(np.unique(m.btags).tolist())
+        assert INLET in tags and WALL in tags
+        assert len(tags - {INLET, WALL}) == n_out, (m.name, tags)
+        vol = np.abs(np.einsum("ij,ij->i", np.cross(m.xyz[m.cells[:, 1]] - m.xyz[m.cells[:, 0]],
+                                                   m.xyz[m.cells[:, 2]] - m.xyz[m.cells[:, 0]]),
+                               m.xyz[m.cells[:, 3]] - m.xyz[m.cells[:, 0]])) / 6.0
+        assert vol.min() > 0.0

@@ -83,3 +83,38 @@ def dirichlet_values(case: dict, node_xyz: np.ndarray) -> np.ndarray:
     for s, w in enumerate(case["omega"]):
         out[s] = case["inlet_amp"][s] * case["inlet"](node_xyz, float(w))
     return out
+
+
+def vessel_case(mesh, n_harm: int, seed_wave: int, period: float, rho: float = 1.0, mu: float = 0.25,
+                radius: float = 1.0) -> dict:
+    """Vessel network rooted at the origin along +z: Womersley flow-rate inlet of
+    the root's radius (Dirichlet), every outlet traction-free, no-slip walls."""
+    c = harmonic_coefficients(n_harm, seed_wave)
+    ks = np.arange(n_harm + 1)
+    nu = mu / rho
+
+    def inlet(xyz: np.ndarray, omega: float) -> np.ndarray:
+        r = np.minimum(np.hypot(xyz[:, 0], xyz[:, 1]), radius)
+        g = np.zeros((xyz.shape[0], 3), np.complex128)
+        g[:, 2] = womersley_profile(r, omega, radius, nu)
+        return g
+
+    bc = {int(t): FREE for t in np.unique(mesh.btags)}
+    bc[INLET] = DIRICHLET
+    bc[WALL] = BC_WALL
+    return dict(mesh=mesh, bc=bc, rho=rho, mu=mu, period=period, ks=ks, omega=2.0 * np.pi * ks / period,
+                traction=np.zeros((ks.size, 0), np.complex128), inlet=inlet, inlet_amp=c, radius=radius,
+                name=mesh.name)
+
+
+def y_bifurcation_case(h: float = 0.35, n_harm: int = 4, seed_wave: int = 3, seed_period: int = 3) -> dict:
+    """Y-bifurcation (radii 1.0/0.7/0.7, 60 degrees between the daughters), with its own seeded period."""
+    from .meshes import y_bifurcation_mesh
+    from .waveforms import period_set
+    return vessel_case(y_bifurcation_mesh(h), n_harm, seed_wave, float(period_set(1, seed_period)[0]))
+
+
+def vessel_tree_case(h: float = 0.25, generations: int = 3, n_harm: int = 2, seed_wave: int = 5) -> dict:
+    """Bifurcating tree (radii shrinking by sqrt 2 per generation, planes turned 90 degrees), T = 1."""
+    from .meshes import vessel_tree_mesh
+    return vessel_case(vessel_tree_mesh(h, generations), n_harm, seed_wave, 1.0)

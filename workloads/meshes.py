@@ -219,3 +219,148 @@ def p2_node_coords(mesh: Mesh, edges: np.ndarray) -> np.ndarray:
         assert np.all(key[pos] == ckey)
         mid[pos] = mesh.curved_xyz
     return np.concatenate([mesh.xyz, mid], 0)
+
+
+# ---- vessel networks: unions of cylinders, voxelized and split into tets ----
+
+def _capped_cylinder_sdf(P: np.ndarray, a: np.ndarray, b: np.ndarray, r: float) -> np.ndarray:
+    """Negative inside the finite cylinder with axis a->b, radius r and flat caps."""
+    ab = b - a
+    L = float(np.linalg.norm(ab))
+    u = ab / L
+    t = (P - a) @ u
+    radial = np.linalg.norm(P - a - t[:, None] * u, axis=1)
+    return np.maximum(radial - r, np.maximum(-t, t - L))
+
+
+# the six tets of the Kuhn split of a hex (corner bits x=1, y=2, z=4): every hex
+# uses the same 0-7 diagonal, so neighbouring hexes split their shared faces alike
+_KUHN = []
+for _p in ((0, 1, 2), (0, 2, 1), (1, 0, 2), (1, 2, 0), (2, 0, 1), (2, 1, 0)):
+    _c0, _c1 = 1 << _p[0], (1 << _p[0]) | (1 << _p[1])
+    _KUHN.append((0, _c0, _c1, 7))
+_KUHN = np.array(_KUHN)
+
+
+def vessel_mesh(segments, h: float, name: str):
+    """Tet mesh of a union of cylinders. ``segments`` is a list of dicts with
+    keys a, b (axis end points), r (radius) and role ('inlet', 'outlet' or
+    'inner'); inner end points get a junction sphere of the segment's radius.
+
+    The bounding box is cut into cubes of side h (the plane z = 0 is a grid
+    plane, so an inlet segment starting on it has a flat inlet); a cube is kept
+    when its centre lies inside the union, only the largest face-connected set
+    of cubes is kept, and each cube is split into six tets along one diagonal,
+    which makes the mesh conforming. Tags: 1 = inlet (facets on the inlet
+    segment's start plane), 2 + k = outlet of the k-th outlet segment (facets
+    within one cube of its end plane), 3 is never used for outlets; walls are
+    tag 3 and outlets are numbered from 4 when there are several."""
+    from scipy.ndimage import label
+    pts_lo = np.min([np.minimum(s["a"], s["b"]) - s["r"] for s in segments], 0) - h
+    pts_hi = np.max([np.maximum(s["a"], s["b"]) + s["r"] for s in segments], 0) + h
+    pts_lo[2] = 0.0  # the inlet starts on z = 0
+    n = np.ceil((pts_hi - pts_lo) / h).astype(int)
+    ii, jj, kk = np.meshgrid(np.arange(n[0]), np.arange(n[1]), np.arange(n[2]), indexing="ij")
+    centers = pts_lo + h * (np.stack([ii, jj, kk], -1).reshape(-1, 3) + 0.5)
+    sdf = np.full(centers.shape[0], np.inf)
+    for s in segments:
+        sdf = np.minimum(sdf, _capped_cylinder_sdf(centers, np.asarray(s["a"], float), np.asarray(s["b"], float),
+                                                   s["r"]))
+        for end in ("a", "b"):
+            if s.get(end + "_role", "inner") == "inner":
+                sdf = np.minimum(sdf, np.linalg.norm(centers - np.asarray(s[end], float), axis=1) - s["r"])
+    inside = (sdf < 0.0).reshape(n)
+    lab, nlab = label(inside)  # face connectivity (6-neighbourhood)
+    sizes = np.bincount(lab.ravel())
+    sizes[0] = 0
+    keep = lab == np.argmax(sizes)
+    hi, hj, hk = np.nonzero(keep)
+    # corner vertex ids on the (n+1)^3 grid, compacted in lexicographic order
+    nn = n + 1
+    corners = np.stack([((hi + ((c >> 0) & 1)) * nn[1] + hj + ((c >> 1) & 1)) * nn[2] + hk + ((c >> 2) & 1)
+                        for c in range(8)], 1)
+    used, inv = np.unique(corners, return_inverse=True)
+    corners = inv.reshape(corners.shape)
+    gi = used // (nn[1] * nn[2])
+    gj = (used // nn[2]) % nn[1]
+    gk = used % nn[2]
+    xyz = pts_lo + h * np.stack([gi, gj, gk], 1).astype(float)
+    cells = corners[:, _KUHN].reshape(-1, 4)
+    F = _boundary_faces_3d(cells, xyz)
+    tags = np.full(F.shape[0], WALL, np.int32)
+    fx = xyz[F]  # [nf, 3, 3]
+    outs = [s for s in segments if s["role"] == "outlet"]
+    for k, s in enumerate(outs):
+        a, b = np.asarray(s["a"], float), np.asarray(s["b"], float)
+        u = (b - a) / np.linalg.norm(b - a)
+        t = (fx - b) @ u
+        radial = np.linalg.norm(fx - b - t[..., None] * u, axis=2)
+        sel = np.all(t >= -h, 1) & np.all(radial <= s["r"] + h, 1)
+        tags[sel] = OUTLET if len(outs) == 1 else 4 + k
+    inl = [s for s in segments if s["role"] == "inlet"][0]
+    tags[np.all(fx[:, :, 2] == 0.0, 1) & np.all(np.hypot(fx[:, :, 0] - inl["a"][0], fx[:, :, 1] - inl["a"][1])
+                                                <= inl["r"] + h, 1)] = INLET
+    return Mesh(3, xyz, cells.astype(np.int32), F.astype(np.int32), tags, name=name)
+
+
+def _rot(axis: np.ndarray, angle: float) -> np.ndarray:
+    """Rotation matrix about a unit axis (Rodrigues)."""
+    ax = axis / np.linalg.norm(axis)
+    K = np.array([[0, -ax[2], ax[1]], [ax[2], 0, -ax[0]], [-ax[1], ax[0], 0]])
+    return np.eye(3) + np.sin(angle) * K + (1 - np.cos(angle)) * K @ K
+
+
+def vessel_tree_segments(generations: int, radius: float = 1.0, ratio: float = 1.0 / np.sqrt(2.0),
+                         half_angle: float = np.pi / 6, length_factor: float = 6.0):
+    """Segments of a symmetric bifurcating tree rooted at the origin along +z.
+    Each segment is length_factor times its radius long; daughters leave at
+    +-half_angle from the parent axis (the angle between them is 2 half_angle),
+    in a plane turned 90 degrees about the parent axis at every generation;
+    daughter radius = parent radius * ratio. generations = 1 is a Y-bifurcation."""
+    segs = []
+    root = dict(a=np.zeros(3), b=np.array([0.0, 0.0, length_factor * radius]), r=radius)
+    root["a_role"] = "inlet"
+    frontier = [(root, np.array([1.0, 0.0, 0.0]))]  # segment and the normal of its branching plane
+    segs.append(root)
+    for g in range(generations):
+        nxt = []
+        for s, nrm in frontier:
+            u = (s["b"] - s["a"]) / np.linalg.norm(s["b"] - s["a"])
+            r = s["r"] * ratio
+            bend = np.cross(nrm, u)  # in-plane direction perpendicular to the axis
+            for sign in (1.0, -1.0):
+                d = _rot(np.cross(u, bend), sign * half_angle) @ u
+                c = dict(a=s["b"].copy(), b=s["b"] + length_factor * r * d, r=r)
+                segs.append(c)
+                nxt.append((c, _rot(d, np.pi / 2) @ nrm))
+        frontier = nxt
+    children = {id(s): False for s in segs}
+    for s in segs:
+        for t in segs:
+            if t is not s and np.allclose(t["a"], s["b"]):
+                children[id(s)] = True
+    for s in segs:
+        if s.get("a_role") == "inlet":
+            s["role"] = "inlet"
+        elif not children[id(s)]:
+            s["role"] = "outlet"
+            s["b_role"] = "outlet"
+        else:
+            s["role"] = "inner"
+        if s["role"] == "inlet":
+            s["b_role"] = "inner"
+    return segs
+
+
+def y_bifurcation_mesh(h: float, radii=(1.0, 0.7, 0.7)) -> Mesh:
+    """Y-bifurcation: root radius radii[0], daughters radii[1], radii[2], 60 degrees between them."""
+    segs = vessel_tree_segments(1, radii[0], 1.0)
+    for s, r in zip(segs[1:], radii[1:]):
+        u = (s["b"] - s["a"]) / np.linalg.norm(s["b"] - s["a"])
+        s["r"] = r
+        s["b"] = s["a"] + 6.0 * r * u
+    return vessel_mesh(segs, h, f"ybif_h{h:g}")
+
+
+def vessel_tree_mesh(h: float, generations: int = 3) -> Mesh:
+    return vessel_mesh(vessel_tree_segments(generations), h, f"tree{generations}_h{h:g}")
