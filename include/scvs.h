@@ -226,6 +226,29 @@ int scvs_solve(scvs_mesh mesh, int64_t nsys, const double* omega, const double* 
                const void* g, const void* x0, void* u_out, void* p_out,
                const scvs_solve_opts* opts, scvs_report* rep);
 
+/* ---- a8: several meshes at once ----
+ * Solves n groups of systems, each on its own mesh, concurrently: every group
+ * runs scvs_solve (same arguments, same results) from its own host thread on
+ * its own context's stream, so the GPU overlaps the groups' kernels -- a small
+ * mesh's launches fill the gaps and tails of a large one's. The groups must use
+ * distinct contexts (create each with its own stream); 1 <= n <= 64. The call
+ * returns when every group is done; on failure it returns the first failing
+ * group's status, its message prefixed with "group k: ", and the other groups'
+ * results are still written. */
+typedef struct {
+  scvs_mesh mesh;
+  int64_t nsys;
+  const double* omega;
+  const double* traction;
+  const void* g;
+  const void* x0;
+  void* u_out;
+  void* p_out;
+  const scvs_solve_opts* opts;
+  scvs_report* rep;
+} scvs_solve_group;
+int scvs_solve_groups(int n, const scvs_solve_group* groups);
+
 /* ---- a8: autotuner ----
  * Times candidate solver settings on the caller's own systems (the same
  * arguments as scvs_solve, no initial guesses) and returns the fastest in

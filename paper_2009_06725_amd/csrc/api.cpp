@@ -2,6 +2,9 @@
 #include <chrono>
 #include <cmath>
 #include <memory>
+#include <string>
+#include <thread>
+#include <vector>
 
 #include "internal.hpp"
 
@@ -319,6 +322,42 @@ int scvs_solve(scvs_mesh m, int64_t nsys, const double* omega, const double* tra
     use_device(m->ctx);
     scvs::solve_systems(m, nsys, omega, traction, m->ndir ? g : nullptr, x0, u_out, p_out, &o, rep);
   });
+}
+
+int scvs_solve_groups(int n, const scvs_solve_group* groups) {
+  if (!(n >= 1 && n <= 64 && groups)) {
+    g_last_error = "bad group arguments";
+    return SCVS_E_INVALID;
+  }
+  for (int i = 0; i < n; ++i) {
+    if (!groups[i].mesh) {
+      g_last_error = "group mesh is null";
+      return SCVS_E_INVALID;
+    }
+    for (int k = 0; k < i; ++k)
+      if (groups[k].mesh->ctx == groups[i].mesh->ctx) {
+        g_last_error = "groups must use distinct contexts (one stream each)";
+        return SCVS_E_INVALID;
+      }
+  }
+  std::vector<int> code(n, SCVS_OK);
+  std::vector<std::string> msg(n);
+  auto run = [&](int i) {
+    const scvs_solve_group& gr = groups[i];
+    code[i] = scvs_solve(gr.mesh, gr.nsys, gr.omega, gr.traction, gr.g, gr.x0, gr.u_out, gr.p_out, gr.opts, gr.rep);
+    if (code[i] != SCVS_OK) msg[i] = g_last_error;  // this thread's message
+  };
+  std::vector<std::thread> th;
+  for (int i = 1; i < n; ++i) th.emplace_back(run, i);
+  run(0);
+  for (auto& t : th) t.join();
+  for (int i = 0; i < n; ++i)
+    if (code[i] != SCVS_OK) {
+      g_last_error = "group " + std::to_string(i) + ": " + msg[i];
+      return code[i];
+    }
+  g_last_error.clear();
+  return SCVS_OK;
 }
 
 int scvs_autotune(scvs_mesh m, int64_t nsys, const double* omega, const double* traction, const void* g,

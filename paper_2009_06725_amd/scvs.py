@@ -23,7 +23,7 @@ EXPORTED = [
     "scvs_last_error", "scvs_version", "scvs_ctx_create", "scvs_ctx_destroy", "scvs_mesh_create",
     "scvs_mesh_destroy", "scvs_mesh_info", "scvs_mesh_set_midside", "scvs_mesh_set_bc", "scvs_assemble",
     "scvs_mesh_export", "scvs_spmv", "scvs_rhs", "scvs_solve_opts_default", "scvs_solve",
-    "scvs_autotune", "scvs_synthesize", "scvs_probe_mfma", "scvs_profile_enable", "scvs_profile_read",
+    "scvs_autotune", "scvs_solve_groups", "scvs_synthesize", "scvs_probe_mfma", "scvs_profile_enable", "scvs_profile_read",
     "scvs_ws_create", "scvs_ws_train", "scvs_ws_predict", "scvs_ws_refine", "scvs_ws_destroy", "scvs_ws_export",
     "scvs_ws_set_params", "scvs_ws_loss_grad", "scvs_herm_eig", "scvs_probe_mfma_bf16",
 ]
@@ -49,6 +49,12 @@ class SolveOpts(C.Structure):
                 ("max_batch", C.c_int32), ("use_graph", C.c_int32), ("verbose", C.c_int32),
                 ("precision", C.c_int32), ("orth", C.c_int32), ("cheb_ratio_pres", C.c_double),
                 ("inner_rtol", C.c_double)]
+
+
+class SolveGroup(C.Structure):
+    _fields_ = [("mesh", C.c_void_p), ("nsys", C.c_int64), ("omega", C.c_void_p), ("traction", C.c_void_p),
+                ("g", C.c_void_p), ("x0", C.c_void_p), ("u_out", C.c_void_p), ("p_out", C.c_void_p),
+                ("opts", C.c_void_p), ("rep", C.c_void_p)]
 
 
 class KernelStat(C.Structure):
@@ -89,6 +95,7 @@ def lib() -> C.CDLL:
         L.scvs_solve.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, C.POINTER(SolveOpts), C.POINTER(Report)]
         L.scvs_autotune.argtypes = [vp, i64, vp, vp, vp, C.POINTER(SolveOpts), C.POINTER(SolveOpts),
                                     C.POINTER(C.c_double)]
+        L.scvs_solve_groups.argtypes = [C.c_int, vp]
         L.scvs_synthesize.argtypes = [vp, i64, vp, vp, i64, i64, vp, vp]
         L.scvs_probe_mfma.argtypes = [vp, vp, vp, vp]
         L.scvs_profile_enable.argtypes = [vp, C.c_int]
@@ -285,6 +292,46 @@ class Mesh:
         b = base if base is not None else default_opts()
         _check(lib().scvs_autotune(self.h, ns, po, pt, pg, C.byref(b), C.byref(best), C.byref(ms)))
         return best, ms.value
+
+
+def solve_groups(groups):
+    """Solve several meshes' systems concurrently (each mesh on its own context and
+    stream). groups: list of dicts with keys mesh, omega, traction, and optionally g,
+    x0, u, p, opts. Returns [(u, p, reports)] in the same order."""
+    import torch
+    keep, out = [], []
+    arr = (SolveGroup * len(groups))()
+    for k, gr in enumerate(groups):
+        m = gr["mesh"]
+        i = m.info
+        om, po = _host(gr["omega"], np.float64)
+        ns = om.size
+        tr = np.asarray(gr["traction"], np.complex128)
+        if i.ntraction and tr.size == ns * i.ntraction:
+            tr = tr.reshape(ns, i.ntraction)
+        tr, pt = _host(tr.view(np.float64), np.float64)
+        dev = torch.device("cuda", m.ctx.device)
+        u = gr.get("u")
+        p = gr.get("p")
+        if u is None:
+            u = torch.empty((ns, i.n2, i.dim), dtype=torch.complex128, device=dev)
+        if p is None:
+            p = torch.empty((ns, i.nv), dtype=torch.complex128, device=dev)
+        reps = (Report * ns)()
+        o = gr.get("opts") or default_opts()
+        g = gr.get("g")
+        x0 = gr.get("x0")
+        arr[k] = SolveGroup(m.h.value if hasattr(m.h, "value") else m.h, ns, po, pt,
+                            _dev(g, "torch.complex128") if g is not None else None,
+                            _dev(x0, "torch.complex128") if x0 is not None else None,
+                            _dev(u, "torch.complex128"), _dev(p, "torch.complex128"),
+                            C.cast(C.pointer(o), C.c_void_p), C.cast(reps, C.c_void_p))
+        keep += [om, tr, o, reps]
+        out.append((u, p, reps))
+    # every group's context stream must see the inputs the caller wrote on torch's stream
+    torch.cuda.synchronize()
+    _check(lib().scvs_solve_groups(len(groups), C.byref(arr)))
+    return [(u, p, list(r)) for u, p, r in out]
 
 
 def synthesize(ctx: Context, omega, modes, times, out=None):

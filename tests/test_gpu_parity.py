@@ -285,3 +285,33 @@ def test_autotune_caches_and_solves(ctx):
     t3 = time.perf_counter()
     m.autotune(c["omega"], c["traction"], g, base=base)
     assert time.perf_counter() - t3 > 5 * (t2 - t1)
+
+
+def test_solve_groups_equal_single_solves():
+    """Several meshes solved concurrently (one context and stream each) give the
+    same modes, bit for bit, as their separate solves."""
+    import time
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2009_06725_amd import scvs
+    cs = [cases.channel_case(), cases.y_bifurcation_case(h=0.45, n_harm=2),
+          cases.pipe_case(h=0.5, length=2.0, n_harm=2)]
+    ctxs = [scvs.Context(0, stream=torch.cuda.Stream()) for _ in cs]
+    ms = [gpu_mesh(cx, c) for cx, c in zip(ctxs, cs)]
+    gs = [gpu_dirichlet(m, c, torch) for m, c in zip(ms, cs)]
+    opts = scvs.default_opts(rtol=1e-11)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    single = [m.solve(c["omega"], c["traction"], g, opts=opts) for m, c, g in zip(ms, cs, gs)]
+    t1 = time.perf_counter()
+    grouped = scvs.solve_groups([dict(mesh=m, omega=c["omega"], traction=c["traction"], g=g, opts=opts)
+                                 for m, c, g in zip(ms, cs, gs)])
+    t2 = time.perf_counter()
+    print(f"[gpu] three meshes: one after another {t1 - t0:.3f}s, concurrently {t2 - t1:.3f}s", flush=True)
+    for (u1, p1, r1), (u2, p2, r2) in zip(single, grouped):
+        assert all(r.status == 0 for r in r2)
+        assert [r.iterations for r in r1] == [r.iterations for r in r2]
+        assert torch.equal(u1, u2) and torch.equal(p1, p2)
+    with pytest.raises(scvs.ScvsError):  # one context for two groups is refused
+        scvs.solve_groups([dict(mesh=ms[0], omega=cs[0]["omega"], traction=cs[0]["traction"], opts=opts),
+                           dict(mesh=ms[0], omega=cs[0]["omega"], traction=cs[0]["traction"], opts=opts)])
