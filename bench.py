@@ -54,6 +54,8 @@ def parse():
     ap.add_argument("--precision", choices=["fp64", "mixed", "mixed32"], default="mixed",
                     help="mixed: FP32 operator and velocity block in FP64 refinement; mixed32: also an FP32 "
                          "Krylov basis (FP64 arithmetic)")
+    ap.add_argument("--penalty", type=float, default=0.0,
+                    help="penalized variant: continuity block -(penalty/mu) Mp (0: the method itself)")
     ap.add_argument("--inner-rtol", type=float, default=1e-5,
                     help="mixed precision: end a cycle once its own residual fell by this factor")
     ap.add_argument("--orth", type=int, choices=[0, 1], default=1,
@@ -243,7 +245,7 @@ def main():
                              cheb_pres=args.cheb_pres, cheb_ratio=args.cheb_ratio,
                              cheb_ratio_pres=args.cheb_ratio_pres, verbose=1 if args.verbose else 0,
                              precision={"fp64": 0, "mixed": 1, "mixed32": 2}[args.precision], orth=args.orth,
-                             inner_rtol=args.inner_rtol)
+                             inner_rtol=args.inner_rtol, penalty=args.penalty)
     log(f"n2={info.n2} ndof={info.ndof} nnz_s2={info.nnz_s2} ingest+assembly {t_ingest:.2f}s")
     tuned = None
     if args.autotune:
@@ -320,6 +322,7 @@ def main():
                    "cheb_ratio_pres": opts.cheb_ratio_pres,
                    "autotuned": tuned,
                    "orth": args.orth, "inner_rtol": args.inner_rtol, "precision": args.precision,
+                   "penalty": args.penalty,
                    "ntimes": args.ntimes},
         "dof_modes_per_s": info.ndof * ns * args.steps / dt,
         "roofline": roof(dominant),

@@ -176,7 +176,8 @@ typedef struct {
                          memory would hold fewer than min(nsys, 8) systems' workspaces) */
   int32_t max_iters;  /* cap on Arnoldi steps per system */
   int32_t cheb_vel;   /* Chebyshev degree of the velocity block, >= 1 */
-  int32_t cheb_pres;  /* Chebyshev degree of the pressure Laplacian, >= 1 */
+  int32_t cheb_pres;  /* Chebyshev degree of the pressure Laplacian, >= 1; 0 drops the j w rho L^-1
+                         term (Schur block = mu Mp^-1, the pressure mass alone) */
   double cheb_ratio;  /* the polynomials target [lambda_max / cheb_ratio, lambda_max] of the
                          Jacobi-scaled blocks (lambda_max from a Gershgorin bound) */
   int32_t max_batch;  /* systems solved together (0 = as many as fit) */
@@ -195,6 +196,9 @@ typedef struct {
                          (DCGS2, Swirydowicz et al. 2020; two passes per step, one extra
                          closing reduction per cycle) */
   double cheb_ratio_pres; /* interval ratio of the pressure-Laplacian polynomial (0: cheb_ratio) */
+  double penalty;     /* epsilon >= 0: solve the penalized system whose continuity block is
+                         -(epsilon / mu) Mp (lumped pressure mass) instead of 0; 0 = the
+                         unstabilized method */
   double inner_rtol;  /* mixed precision only: a restart cycle also ends once its own residual
                          estimate has fallen by this factor (the FP32 operator cannot take the
                          true residual much further within one cycle); 0 = only at rtol or m */

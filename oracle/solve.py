@@ -13,7 +13,11 @@ Section 2.3, Eqs. linear_sys_def / LS_construction, with these readings:
   -G^T g that the paper's R = [B; 0] omits when g != 0;
 * traction boundaries carry a normal pressure: h = -P n per tag, so the load
   is sum_tau (-P_tau) int M_A n dGamma;
-* each mode is solved by SciPy's sparse LU (SuperLU).
+* each mode is solved by SciPy's sparse LU (SuperLU);
+* penalized variant (the paper's future work names penalty methods as a way to
+  ease the saddle point): with epsilon > 0 the continuity block becomes
+  -(epsilon / mu) Mp, Mp the lumped P1 pressure mass, i.e. the discrete
+  constraint G^T u = (epsilon / mu) Mp p; epsilon = 0 is the method itself.
 """
 from __future__ import annotations
 
@@ -24,8 +28,8 @@ from scipy.sparse.linalg import splu
 from .assemble import assemble, boundary_loads, bc_nodes
 
 
-def system_matrix(asm: dict, omega: float, rho: float, mu: float) -> sp.csr_matrix:
-    """Unconstrained complex matrix [[I_d (x) (mu Ks + j w rho M), G], [G^T, 0]]."""
+def system_matrix(asm: dict, omega: float, rho: float, mu: float, penalty: float = 0.0) -> sp.csr_matrix:
+    """Unconstrained complex matrix [[I_d (x) (mu Ks + j w rho M), G], [G^T, -(penalty/mu) Mp]]."""
     d, n2, nv = asm["dim"], asm["n2"], asm["nv"]
     rp2, col2 = asm["S2"]
     rp21, col21 = asm["C21"]
@@ -37,6 +41,11 @@ def system_matrix(asm: dict, omega: float, rho: float, mu: float) -> sp.csr_matr
         rows += [d * r2 + c, d * r21 + c, d * n2 + col21]
         cols += [d * col2 + c, d * n2 + col21, d * r21 + c]
         vals += [kv, asm["G"][c].astype(np.complex128), asm["G"][c].astype(np.complex128)]
+    if penalty != 0.0:
+        pv = np.arange(nv)
+        rows.append(d * n2 + pv)
+        cols.append(d * n2 + pv)
+        vals.append((-(penalty / mu) * asm["Mp"]).astype(np.complex128))
     N = d * n2 + nv
     A = sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
                       shape=(N, N)).tocsr()
@@ -73,7 +82,7 @@ def constrained_matrix(A: sp.csr_matrix, cidx: np.ndarray) -> sp.csr_matrix:
     return (Df @ A @ Df + sp.diags(1.0 - free)).tocsr()
 
 
-def solve_modes(asm, loads, wall, dirn, omegas, rho, mu, traction, gvals):
+def solve_modes(asm, loads, wall, dirn, omegas, rho, mu, traction, gvals, penalty: float = 0.0):
     """Solve every mode by LU. traction [nsys, ntags], gvals [nsys, ndir, d].
 
     Returns u [nsys, n2, d], p [nsys, nv], relative residuals [nsys] and the
@@ -85,7 +94,7 @@ def solve_modes(asm, loads, wall, dirn, omegas, rho, mu, traction, gvals):
     res = np.zeros(ns)
     F = []
     for s, w in enumerate(omegas):
-        A = system_matrix(asm, float(w), rho, mu)
+        A = system_matrix(asm, float(w), rho, mu, penalty)
         cidx, cval = constrained_dofs(asm, wall, dirn, gvals[s])
         f = system_rhs(asm, loads, traction[s], cidx, cval, A)
         Ac = constrained_matrix(A, cidx)

@@ -50,10 +50,11 @@ scvs_solve_opts checked_opts(const scvs_solve_opts* opts) {
   else
     scvs_solve_opts_default(&o);
   SCVS_REQUIRE(o.rtol > 0.0 && o.restart >= 1 && o.restart <= SCVS_MMAX && o.max_iters >= 1 && o.cheb_vel >= 1 &&
-                   o.cheb_pres >= 1 && o.cheb_ratio > 1.0 && o.max_batch >= 0 &&
+                   o.cheb_pres >= 0 && o.cheb_ratio > 1.0 && o.max_batch >= 0 &&
                    (o.precision >= 0 && o.precision <= 2) && (o.orth == 0 || o.orth == 1) &&
                    (o.precision != 2 || o.orth == 1) && o.inner_rtol >= 0.0 && o.inner_rtol < 1.0 &&
-                   (o.cheb_ratio_pres == 0.0 || o.cheb_ratio_pres > 1.0),
+                   (o.cheb_ratio_pres == 0.0 || o.cheb_ratio_pres > 1.0) && o.penalty >= 0.0 &&
+                   std::isfinite(o.penalty),
                SCVS_E_INVALID, "bad solve options");
   return o;
 }
@@ -307,6 +308,7 @@ void scvs_solve_opts_default(scvs_solve_opts* o) {
   o->precision = 0;
   o->orth = 1;
   o->cheb_ratio_pres = 1000.0;
+  o->penalty = 0.0;
   o->inner_rtol = 1e-5;
 }
 

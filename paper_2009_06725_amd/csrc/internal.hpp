@@ -244,6 +244,7 @@ struct Batch {
   const double* lv = nullptr;     // device [slots] Chebyshev upper bound, velocity block
   const double* insc = nullptr;   // device [slots * insc_st] input scale (nullptr = 1)
   int insc_st = 0, insc_idx = 0;
+  double pen = 0.0;  // penalty: continuity block -pen * Mp (lumped), pen = epsilon / mu
 };
 enum { SPMV_APPLY = 0, SPMV_RESID = 1, SPMV_RHS = 2 };
 // y = A x (APPLY), y = f - A x (RESID), y = [-sum P n - A x ; x on Dirichlet rows ; -G^T x] (RHS).

@@ -1108,6 +1108,7 @@ int solve_systems(scvs_mesh m, int64_t nsys, const double* omega, const double* 
     b.act = P.act_all;
     b.omega = P.omega;
     b.lv = P.lv;
+    b.pen = o->penalty / m->mu;
     k_init_state<<<(nb + 63) / 64, 64, 0, s>>>(P.st, P.act_all, nb);
     const int nch0 = choose_nch(nb, ndof);
     KArgs a0 = kargs(P, ndof, nch0);

@@ -307,6 +307,12 @@ __global__ void __launch_bounds__(256) k_full(MeshArgs ma, Batch b, LaneMap lm, 
       const C ps = sum_components<D, C>(ap);
       if (ok && c == 0) {
         double2 yp = make_double2(sc * (double)ps.x, sc * (double)ps.y);
+        if (MODE != SPMV_RHS && b.pen != 0.0) {  // penalized continuity block -pen Mp p
+          const C xp = IL ? xil[ma.n2 * lm.G + A * b.nact + si] : xs[D * ma.n2 + A];
+          const double w = b.pen * ma.Mp[A] * sc;
+          yp.x -= w * (double)xp.x;
+          yp.y -= w * (double)xp.y;
+        }
         if (MODE == SPMV_RESID) yp = csub(f.at(slot)[D * ma.n2 + A], yp);
         if (MODE == SPMV_RHS) yp = make_double2(-yp.x, -yp.y);
         y.at(slot)[D * ma.n2 + A] = cvt2<YT>(yp);
@@ -459,9 +465,11 @@ __global__ void k_pinit(MeshArgs ma, int D, Batch b, SV<VI> v, VArg z, ITemps<do
   pt.arr(0)[ki] = vp;
   pt.arr(1)[ki] = dd;
   pt.arr(3)[ki] = dd;
-  if (kp == 1) {
+  if (kp <= 1) {
+    // kp == 0: the Schur block is the pressure mass alone, zhat_p = -mu Mp^-1 v_p
+    const double2 xl = kp == 0 ? make_double2(0.0, 0.0) : dd;
     const double wr = b.omega[slot] * ma.rho, im = ma.mu / ma.Mp[vv];
-    z.at(slot)[DN + vv] = make_double2(-(im * vp.x - wr * dd.y), -(im * vp.y + wr * dd.x));
+    z.at(slot)[DN + vv] = make_double2(-(im * vp.x - wr * xl.y), -(im * vp.y + wr * xl.x));
   }
 }
 

@@ -47,7 +47,7 @@ class SolveOpts(C.Structure):
     _fields_ = [("rtol", C.c_double), ("restart", C.c_int32), ("max_iters", C.c_int32),
                 ("cheb_vel", C.c_int32), ("cheb_pres", C.c_int32), ("cheb_ratio", C.c_double),
                 ("max_batch", C.c_int32), ("use_graph", C.c_int32), ("verbose", C.c_int32),
-                ("precision", C.c_int32), ("orth", C.c_int32), ("cheb_ratio_pres", C.c_double),
+                ("precision", C.c_int32), ("orth", C.c_int32), ("cheb_ratio_pres", C.c_double), ("penalty", C.c_double),
                 ("inner_rtol", C.c_double)]
 
 

@@ -315,3 +315,23 @@ def test_solve_groups_equal_single_solves():
     with pytest.raises(scvs.ScvsError):  # one context for two groups is refused
         scvs.solve_groups([dict(mesh=ms[0], omega=cs[0]["omega"], traction=cs[0]["traction"], opts=opts),
                            dict(mesh=ms[0], omega=cs[0]["omega"], traction=cs[0]["traction"], opts=opts)])
+
+
+def test_solve_penalty_matches_lu(setup):
+    """The penalized variant (continuity block -(eps/mu) Mp) against the oracle's
+    LU of the same penalized system, FP64 and mixed precision."""
+    if setup["name"] not in ("channel", "pipe"):
+        pytest.skip("two representative cases keep the LU time down")
+    from paper_2009_06725_amd import scvs
+    c, asm, m = setup["case"], setup["asm"], setup["m"]
+    eps = 1e-3
+    u_o, p_o, _, _ = solve_modes(asm, setup["loads"], setup["wall"], setup["dirn"], c["omega"], c["rho"],
+                                 c["mu"], c["traction"], setup["g"], penalty=eps)
+    g = gpu_dirichlet(m, c, torch)
+    for precision, tol in ((0, 1e-10), (1, 1e-8)):
+        opts = scvs.default_opts(rtol=1e-13 if precision == 0 else 1e-12, penalty=eps, precision=precision)
+        u, p, rep = m.solve(c["omega"], c["traction"], g, opts=opts)
+        assert all(r.status == 0 for r in rep)
+        for s in range(len(c["omega"])):
+            eu, ep = rel_l2(asm, u[s].cpu().numpy(), u_o[s], p[s].cpu().numpy(), p_o[s])
+            assert eu <= tol and ep <= tol, (precision, s, eu, ep)

@@ -120,3 +120,22 @@ def test_channel_traction_sign():
     u, _, _, _ = solve_modes(asm, loads, wall, dirn, c["omega"][:1], c["rho"], c["mu"],
                              c["traction"][:1], g[:1])
     assert u[0, :, 0].real.max() > 0 and u[0, :, 0].real.min() >= -1e-14
+
+
+def test_penalty_converges_linearly_to_the_method():
+    """The penalized solutions approach the unpenalized one at first order in
+    epsilon (consistency of the penalty variant); each penalized system is
+    solved to LU accuracy."""
+    from oracle.solve import case_setup, solve_modes
+    from workloads import cases
+    c = cases.channel_case(nx=16, ny=4, n_harm=1)
+    asm, loads, wall, dirn, g = case_setup(c)
+    args = (asm, loads, wall, dirn, c["omega"], c["rho"], c["mu"], c["traction"], g)
+    u0, p0, _, _ = solve_modes(*args)
+    errs = []
+    for eps in (1e-3, 1e-4):
+        ue, pe, res, _ = solve_modes(*args, penalty=eps)
+        assert res.max() < 1e-12
+        errs.append(np.linalg.norm(ue - u0) / np.linalg.norm(u0))
+    assert 8.0 < errs[0] / errs[1] < 12.0  # first order in epsilon
+    assert errs[0] < 1e-1
