@@ -331,6 +331,32 @@ def main():
         "iterations": iters,
         "kernels": kernels,
     }
+    # mode selection on this workload: a-priori truncation error of the boundary data
+    # (Eq. mode_error) against the a-posteriori change of each added mode
+    hn2, gn2 = m.boundary_norms(case["omega"], case["traction"], g)
+    un2, _ = m.mode_norms(u, p)
+    wk = np.where(np.asarray(case["omega"]) == 0.0, 1.0, 2.0)  # Parseval weights, two-sided modes
+
+    def e_first(n):  # e_M when the first n modes are kept (relative to all ns modes)
+        e2 = 0.0
+        for q in (np.asarray(hn2), np.asarray(gn2)):
+            tot = float(np.sum(wk * q))
+            if tot > 0:
+                e2 += float(np.sum(wk[n:] * q[n:])) / tot
+        return float(np.sqrt(e2))
+
+    full = [e_first(n + 1) for n in range(ns)]
+    inc = scvs.mode_increments(case["omega"], un2)
+    picks = {}
+    for eps in (1e-1, 1e-2, 1e-3):
+        oc, nc, ec = scvs.select_modes(case["omega"], hn2, gn2, eps, True)
+        oa, na, ea = scvs.select_modes(case["omega"], hn2, gn2, eps, False)
+        picks[f"{eps:g}"] = {"consecutive": int(nc), "by_amplitude": int(na),
+                             "by_amplitude_modes": [int(k) for k in oa[:na]]}
+    out["mode_selection"] = {
+        "a_priori_error_first_n_modes": full,
+        "a_posteriori_increment_of_mode_n": [float(x) for x in inc],
+        "modes_needed": picks}
     if not args.no_error_check:
         # error of the timed solution: against an FP64 solve to a 100x tighter residual
         # (not below 1e-13, about where FP64 restarts stop gaining)

@@ -267,6 +267,32 @@ int scvs_solve_groups(int n, const scvs_solve_group* groups);
 int scvs_autotune(scvs_mesh mesh, int64_t nsys, const double* omega, const double* traction, const void* g,
                   const scvs_solve_opts* base, scvs_solve_opts* best, double* best_ms);
 
+/* ---- f2: mode selection (section 2.4, step 2, Eq. mode_error, and its closing remarks) ----
+ * For real periodic data given by two-sided coefficients, Parseval turns the
+ * L2(Gamma x T) norms of Eq. mode_error into mode sums with weight 1 for
+ * omega = 0 and 2 otherwise.
+ *   scvs_boundary_norms  per system: hn2 = int |h|^2 over the traction facets
+ *       (h = -P n per traction tag) and gn2 = int |g_h|^2 over the Dirichlet
+ *       facets (g_h the quadratic interpolant of the nodal data, walls zero);
+ *       arguments as scvs_solve; host outputs double[nsys].
+ *   scvs_mode_norms  per solved mode: un2 = u^H (I_d (x) M) u and pn2 = p^H Mp p
+ *       (lumped pressure mass); u, p device as written by scvs_solve.
+ *   scvs_select_modes  host only (needs no GPU): the fewest modes whose relative
+ *       truncation error e_M (the square root of Eq. mode_error's left side)
+ *       is below eps. Modes enter in the given order (consecutive = 1) or by
+ *       their share of the data energy (consecutive = 0, the non-consecutive
+ *       choice the paper suggests). Outputs: order[nk] (a permutation), *count,
+ *       *err = e_M of the chosen set.
+ *   scvs_mode_increments  host only: inc[k] = relative L2(Omega x T) change of
+ *       the reconstruction when mode k is added to modes 0..k-1 (the
+ *       a-posteriori stopping quantity). */
+int scvs_boundary_norms(scvs_mesh mesh, int64_t nsys, const double* traction, const void* g, double* hn2,
+                        double* gn2);
+int scvs_mode_norms(scvs_mesh mesh, int64_t nsys, const void* u, const void* p, double* un2, double* pn2);
+int scvs_select_modes(int64_t nk, const double* omega, const double* hn2, const double* gn2, double eps,
+                      int consecutive, int64_t* order, int64_t* count, double* err);
+int scvs_mode_increments(int64_t n, const double* omega, const double* un2, double* inc);
+
 /* ---- a10: time synthesis (section 2.4, step 4, Eq. sol_reconstruct) ----
  * out[n][i] = sum_k c_k Re(modes[k][i] exp(j omega_k t_n)), c_k = 1 if
  * omega_k == 0 else 2 (real fields from the one-sided coefficients of

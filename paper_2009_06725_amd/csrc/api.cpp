@@ -413,6 +413,70 @@ int scvs_autotune(scvs_mesh m, int64_t nsys, const double* omega, const double* 
   });
 }
 
+int scvs_boundary_norms(scvs_mesh m, int64_t nsys, const double* traction, const void* g, double* hn2,
+                        double* gn2) {
+  return guarded([&] {
+    require_ready(m);
+    SCVS_REQUIRE(nsys > 0 && nsys <= 4096 && hn2 && gn2, SCVS_E_INVALID, "bad boundary-norm arguments");
+    SCVS_REQUIRE(m->traction_tags.empty() || traction, SCVS_E_INVALID, "traction is null");
+    SCVS_REQUIRE(m->ndir == 0 || g, SCVS_E_INVALID, "g is null but the mesh has Dirichlet nodes");
+    use_device(m->ctx);
+    scvs::boundary_norms(m, nsys, traction, m->ndir ? g : nullptr, hn2, gn2);
+  });
+}
+
+int scvs_mode_norms(scvs_mesh m, int64_t nsys, const void* u, const void* p, double* un2, double* pn2) {
+  return guarded([&] {
+    require_ready(m);
+    SCVS_REQUIRE(nsys > 0 && nsys <= 65535 && u && p && un2 && pn2, SCVS_E_INVALID, "bad mode-norm arguments");
+    use_device(m->ctx);
+    scvs::mode_norms(m, nsys, u, p, un2, pn2);
+  });
+}
+
+int scvs_select_modes(int64_t nk, const double* omega, const double* hn2, const double* gn2, double eps,
+                      int consecutive, int64_t* order, int64_t* count, double* err) {
+  return guarded([&] {
+    SCVS_REQUIRE(nk > 0 && omega && hn2 && gn2 && order && count && eps >= 0.0, SCVS_E_INVALID,
+                 "bad mode-selection arguments");
+    // two-sided weights: the zeroth mode once, every other mode twice (Parseval)
+    std::vector<double> w(nk);
+    double H = 0.0, Gs = 0.0;
+    for (int64_t k = 0; k < nk; ++k) {
+      SCVS_REQUIRE(std::isfinite(omega[k]) && hn2[k] >= 0.0 && gn2[k] >= 0.0, SCVS_E_INVALID, "bad mode norms");
+      w[k] = omega[k] == 0.0 ? 1.0 : 2.0;
+      H += w[k] * hn2[k];
+      Gs += w[k] * gn2[k];
+    }
+    auto share = [&](int64_t k) { return (H > 0.0 ? w[k] * hn2[k] / H : 0.0) + (Gs > 0.0 ? w[k] * gn2[k] / Gs : 0.0); };
+    std::vector<int64_t> ord(nk);
+    for (int64_t k = 0; k < nk; ++k) ord[k] = k;
+    if (!consecutive)
+      std::stable_sort(ord.begin(), ord.end(), [&](int64_t a, int64_t b) { return share(a) > share(b); });
+    // e_M^2 = (truncated traction energy) + (truncated Dirichlet energy), both relative
+    double rest = 0.0;
+    for (int64_t k = 0; k < nk; ++k) rest += share(k);
+    int64_t n = 0;
+    while (n < nk && !(rest < eps * eps)) rest -= share(ord[n++]);
+    if (n == 0) ++n, rest -= share(ord[0]);  // at least one mode
+    for (int64_t k = 0; k < nk; ++k) order[k] = ord[k];
+    *count = n;
+    if (err) *err = std::sqrt(std::max(rest, 0.0));
+  });
+}
+
+int scvs_mode_increments(int64_t n, const double* omega, const double* un2, double* inc) {
+  return guarded([&] {
+    SCVS_REQUIRE(n > 0 && omega && un2 && inc, SCVS_E_INVALID, "bad increment arguments");
+    double tot = 0.0;
+    for (int64_t k = 0; k < n; ++k) {
+      const double wk = (omega[k] == 0.0 ? 1.0 : 2.0) * un2[k];
+      tot += wk;
+      inc[k] = tot > 0.0 ? std::sqrt(wk / tot) : 0.0;
+    }
+  });
+}
+
 int scvs_synthesize(scvs_ctx ctx, int64_t nk, const double* omega, const void* modes, int64_t nvals, int64_t nt,
                     const double* times, void* out) {
   return guarded([&] {

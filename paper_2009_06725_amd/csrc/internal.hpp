@@ -288,6 +288,15 @@ int solve_systems(scvs_mesh m, int64_t nsys, const double* omega, const double* 
                   const scvs_solve_opts* o, scvs_report* rep);
 void rhs_systems(scvs_mesh m, int64_t nsys, const double* omega, const double* traction,
                  const void* g, void* f);
+// x[slot act[k]] = Dirichlet data g[k] on the Dirichlet nodes, zero elsewhere (walls too).
+void scatter_dirichlet(scvs_mesh m, int64_t nsys, const void* g, VArg x, const int* act, hipStream_t s);
+
+// ---- modes.hip ----
+// Per system: squared L2(Gamma) norms of the traction data (hn2) and of the
+// Dirichlet data on the Dirichlet facets (gn2); host outputs.
+void boundary_norms(scvs_mesh m, int64_t nsys, const double* traction, const void* g, double* hn2, double* gn2);
+// Per system: u^H (I_d (x) M) u and p^H Mp p (lumped pressure mass); host outputs.
+void mode_norms(scvs_mesh m, int64_t nsys, const void* u, const void* p, double* un2, double* pn2);
 
 // ---- learned.hip ----
 struct Mlp;

@@ -998,6 +998,20 @@ void cycle_end(scvs_mesh m, Pool& P, const Batch& b, const PrecondArgs& pa, int6
 
 }  // namespace
 
+void scatter_dirichlet(scvs_mesh m, int64_t nsys, const void* g, VArg x, const int* act, hipStream_t s) {
+  const int D = m->dim;
+  const int64_t ndof = D * m->n2 + m->nv;
+  const dim3 gi(256, (unsigned)nsys);
+  const double2* gp = (const double2*)g;
+  if (D == 2)
+    k_init_x<2><<<gi, 256, 0, s>>>(x, nullptr, 0, gp, m->ndir * D, m->dmask, m->dirnodes, m->ndir, m->n2, ndof, act,
+                                   0);
+  else
+    k_init_x<3><<<gi, 256, 0, s>>>(x, nullptr, 0, gp, m->ndir * D, m->dmask, m->dirnodes, m->ndir, m->n2, ndof, act,
+                                   0);
+  launch_check(s);
+}
+
 void rhs_systems(scvs_mesh m, int64_t nsys, const double* omega, const double* traction, const void* g, void* f) {
   hipStream_t s = m->ctx->stream;
   const int D = m->dim;

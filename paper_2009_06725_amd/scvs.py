@@ -23,7 +23,8 @@ EXPORTED = [
     "scvs_last_error", "scvs_version", "scvs_ctx_create", "scvs_ctx_destroy", "scvs_mesh_create",
     "scvs_mesh_destroy", "scvs_mesh_info", "scvs_mesh_set_midside", "scvs_mesh_set_bc", "scvs_assemble",
     "scvs_mesh_export", "scvs_spmv", "scvs_rhs", "scvs_solve_opts_default", "scvs_solve",
-    "scvs_autotune", "scvs_solve_groups", "scvs_synthesize", "scvs_probe_mfma", "scvs_profile_enable", "scvs_profile_read",
+    "scvs_autotune", "scvs_solve_groups", "scvs_boundary_norms", "scvs_mode_norms", "scvs_select_modes",
+    "scvs_mode_increments", "scvs_synthesize", "scvs_probe_mfma", "scvs_profile_enable", "scvs_profile_read",
     "scvs_ws_create", "scvs_ws_train", "scvs_ws_predict", "scvs_ws_refine", "scvs_ws_destroy", "scvs_ws_export",
     "scvs_ws_set_params", "scvs_ws_loss_grad", "scvs_herm_eig", "scvs_probe_mfma_bf16",
 ]
@@ -96,6 +97,10 @@ def lib() -> C.CDLL:
         L.scvs_autotune.argtypes = [vp, i64, vp, vp, vp, C.POINTER(SolveOpts), C.POINTER(SolveOpts),
                                     C.POINTER(C.c_double)]
         L.scvs_solve_groups.argtypes = [C.c_int, vp]
+        L.scvs_boundary_norms.argtypes = [vp, i64, vp, vp, vp, vp]
+        L.scvs_mode_norms.argtypes = [vp, i64, vp, vp, vp, vp]
+        L.scvs_select_modes.argtypes = [i64, vp, vp, vp, C.c_double, C.c_int, vp, vp, vp]
+        L.scvs_mode_increments.argtypes = [i64, vp, vp, vp]
         L.scvs_synthesize.argtypes = [vp, i64, vp, vp, i64, i64, vp, vp]
         L.scvs_probe_mfma.argtypes = [vp, vp, vp, vp]
         L.scvs_profile_enable.argtypes = [vp, C.c_int]
@@ -277,6 +282,29 @@ class Mesh:
                                 _dev(p, "torch.complex128"), C.byref(o), reps))
         return u, p, list(reps)
 
+    def boundary_norms(self, omega, traction, g=None):
+        """Per system (traction L2(Gamma) norm^2, Dirichlet-data L2(Gamma) norm^2)."""
+        i = self.info
+        ns = np.asarray(omega).size
+        tr = np.asarray(traction, np.complex128)
+        if i.ntraction and tr.size == ns * i.ntraction:
+            tr = tr.reshape(ns, i.ntraction)
+        tr, pt = _host(tr.view(np.float64), np.float64)
+        hn2 = np.zeros(ns)
+        gn2 = np.zeros(ns)
+        _check(lib().scvs_boundary_norms(self.h, ns, pt, _dev(g, "torch.complex128") if g is not None else None,
+                                         hn2.ctypes.data_as(C.c_void_p), gn2.ctypes.data_as(C.c_void_p)))
+        return hn2, gn2
+
+    def mode_norms(self, u, p):
+        """Per solved mode (u^H (I x M) u, p^H Mp p)."""
+        ns = u.shape[0]
+        un2 = np.zeros(ns)
+        pn2 = np.zeros(ns)
+        _check(lib().scvs_mode_norms(self.h, ns, _dev(u, "torch.complex128"), _dev(p, "torch.complex128"),
+                                     un2.ctypes.data_as(C.c_void_p), pn2.ctypes.data_as(C.c_void_p)))
+        return un2, pn2
+
     def autotune(self, omega, traction, g=None, base: SolveOpts | None = None):
         """Fastest of the library's candidate settings for these systems: (opts, ms)."""
         i = self.info
@@ -292,6 +320,28 @@ class Mesh:
         b = base if base is not None else default_opts()
         _check(lib().scvs_autotune(self.h, ns, po, pt, pg, C.byref(b), C.byref(best), C.byref(ms)))
         return best, ms.value
+
+
+def select_modes(omega, hn2, gn2, eps, consecutive=True):
+    """(order, count, e_M): the fewest modes with truncation error below eps."""
+    om, po = _host(omega, np.float64)
+    h, ph = _host(hn2, np.float64)
+    gg, pg = _host(gn2, np.float64)
+    order = np.zeros(om.size, np.int64)
+    cnt = C.c_int64()
+    err = C.c_double()
+    _check(lib().scvs_select_modes(om.size, po, ph, pg, eps, 1 if consecutive else 0,
+                                   order.ctypes.data_as(C.c_void_p), C.byref(cnt), C.byref(err)))
+    return order, cnt.value, err.value
+
+
+def mode_increments(omega, un2):
+    """Relative L2(Omega x T) change when each mode is added to the ones before it."""
+    om, po = _host(omega, np.float64)
+    u, pu = _host(un2, np.float64)
+    inc = np.zeros(om.size)
+    _check(lib().scvs_mode_increments(om.size, po, pu, inc.ctypes.data_as(C.c_void_p)))
+    return inc
 
 
 def solve_groups(groups):

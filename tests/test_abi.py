@@ -17,14 +17,6 @@ def _declared():
     return sorted(set(re.findall(r"\b(scvs_[a-z_0-9]+)\s*\(", src)))
 
 
-@pytest.fixture(scope="module")
-def lib():
-    if not os.path.exists(LIB):
-        pytest.fail("libscvs.so is not built (run paper_2009_06725_amd/build.py)")
-    from paper_2009_06725_amd import scvs
-    return scvs.lib()
-
-
 def test_header_symbols_exported(lib):
     names = _declared()
     assert len(names) >= 15

@@ -335,3 +335,28 @@ def test_solve_penalty_matches_lu(setup):
         for s in range(len(c["omega"])):
             eu, ep = rel_l2(asm, u[s].cpu().numpy(), u_o[s], p[s].cpu().numpy(), p_o[s])
             assert eu <= tol and ep <= tol, (precision, s, eu, ep)
+
+
+def test_boundary_and_mode_norms(setup):
+    """Per-mode L2(Gamma) norms of the boundary data and L2(Omega) norms of the
+    modes against the oracle's facet quadrature and mass matrices."""
+    from oracle.modes import boundary_field_l2_sq, dirichlet_facets, mode_l2_sq, nodal_dirichlet, tag_area
+    c, asm, m = setup["case"], setup["asm"], setup["m"]
+    mesh, nk = c["mesh"], len(c["omega"])
+    g = gpu_dirichlet(m, c, torch)
+    hn2, gn2 = m.boundary_norms(c["omega"], c["traction"], g)
+    ttags = sorted(t for t, k in c["bc"].items() if k == 3)
+    areas = np.array([tag_area(mesh, asm, t) for t in ttags])
+    P = np.asarray(c["traction"]).reshape(nk, len(ttags))
+    ref_h = np.sum(np.abs(P) ** 2 * areas[None, :], axis=1) if ttags else np.zeros(nk)
+    F = dirichlet_facets(mesh, c["bc"])
+    ref_g = np.array([boundary_field_l2_sq(mesh, asm, F, nodal_dirichlet(asm, setup["wall"], setup["dirn"],
+                                                                         setup["g"][k]))
+                      if setup["dirn"].size else 0.0 for k in range(nk)])
+    assert np.allclose(hn2, ref_h, rtol=1e-12, atol=1e-14 * max(1.0, ref_h.max()))
+    assert np.allclose(gn2, ref_g, rtol=1e-12, atol=1e-14 * max(1.0, ref_g.max()))
+    u_o, p_o = _lu(setup)
+    un2, pn2 = m.mode_norms(torch.from_numpy(np.ascontiguousarray(u_o)).to("cuda"),
+                            torch.from_numpy(np.ascontiguousarray(p_o)).to("cuda"))
+    ref = np.array([mode_l2_sq(asm, u_o[k], p_o[k]) for k in range(nk)])
+    assert np.allclose(un2, ref[:, 0], rtol=1e-12) and np.allclose(pn2, ref[:, 1], rtol=1e-12)
