@@ -17,7 +17,14 @@ Section 2.3, Eqs. linear_sys_def / LS_construction, with these readings:
 * penalized variant (the paper's future work names penalty methods as a way to
   ease the saddle point): with epsilon > 0 the continuity block becomes
   -(epsilon / mu) Mp, Mp the lumped P1 pressure mass, i.e. the discrete
-  constraint G^T u = (epsilon / mu) Mp p; epsilon = 0 is the method itself.
+  constraint G^T u = (epsilon / mu) Mp p; epsilon = 0 is the method itself;
+* lumped (Windkessel) outlets (section 3.6 puts one on each outflow face of
+  the Glenn case without giving its form): a traction tag may carry a
+  three-element model, proximal resistance Rp in series with a capacitance C
+  parallel to a distal resistance Rd. Its pressure is P = Z(w) Q + P0 with the
+  outlet flow Q = int u.n dGamma, Z(w) = Rp + Rd / (1 + j w Rd C) and P0 the
+  tag's traction coefficient. With b the tag's load vector int M_A n dGamma,
+  Q = b^T u, so the momentum rows gain Z b b^T u (a rank-one term per outlet).
 """
 from __future__ import annotations
 
@@ -28,8 +35,16 @@ from scipy.sparse.linalg import splu
 from .assemble import assemble, boundary_loads, bc_nodes
 
 
-def system_matrix(asm: dict, omega: float, rho: float, mu: float, penalty: float = 0.0) -> sp.csr_matrix:
-    """Unconstrained complex matrix [[I_d (x) (mu Ks + j w rho M), G], [G^T, -(penalty/mu) Mp]]."""
+def windkessel_impedance(omega: float, rp: float, c: float, rd: float) -> complex:
+    """Z(w) of the three-element model: P = rp Q + Pc with c dPc/dt = Q - Pc / rd, so that
+    in a mode exp(j w t) Pc = rd Q / (1 + j w rd c)."""
+    return complex(rp + rd / (1.0 + 1j * omega * rd * c))
+
+
+def system_matrix(asm: dict, omega: float, rho: float, mu: float, penalty: float = 0.0,
+                  lumped=()) -> sp.csr_matrix:
+    """Unconstrained complex matrix [[I_d (x) (mu Ks + j w rho M) + sum Z b b^T, G],
+    [G^T, -(penalty/mu) Mp]]; lumped is a list of (b [n2, d], Z)."""
     d, n2, nv = asm["dim"], asm["n2"], asm["nv"]
     rp2, col2 = asm["S2"]
     rp21, col21 = asm["C21"]
@@ -46,6 +61,12 @@ def system_matrix(asm: dict, omega: float, rho: float, mu: float, penalty: float
         rows.append(d * n2 + pv)
         cols.append(d * n2 + pv)
         vals.append((-(penalty / mu) * asm["Mp"]).astype(np.complex128))
+    for b, Z in lumped:
+        bv = np.asarray(b, float).ravel()
+        nz = np.flatnonzero(bv)
+        rows.append(np.repeat(nz, nz.size))
+        cols.append(np.tile(nz, nz.size))
+        vals.append(Z * np.outer(bv[nz], bv[nz]).ravel())
     N = d * n2 + nv
     A = sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
                       shape=(N, N)).tocsr()
@@ -82,8 +103,10 @@ def constrained_matrix(A: sp.csr_matrix, cidx: np.ndarray) -> sp.csr_matrix:
     return (Df @ A @ Df + sp.diags(1.0 - free)).tocsr()
 
 
-def solve_modes(asm, loads, wall, dirn, omegas, rho, mu, traction, gvals, penalty: float = 0.0):
+def solve_modes(asm, loads, wall, dirn, omegas, rho, mu, traction, gvals, penalty: float = 0.0,
+                windkessel=None):
     """Solve every mode by LU. traction [nsys, ntags], gvals [nsys, ndir, d].
+    windkessel: {traction-tag index: (rp, c, rd)} for lumped outlets.
 
     Returns u [nsys, n2, d], p [nsys, nv], relative residuals [nsys] and the
     right-hand sides [nsys, N]."""
@@ -94,7 +117,8 @@ def solve_modes(asm, loads, wall, dirn, omegas, rho, mu, traction, gvals, penalt
     res = np.zeros(ns)
     F = []
     for s, w in enumerate(omegas):
-        A = system_matrix(asm, float(w), rho, mu, penalty)
+        lumped = [(loads[t], windkessel_impedance(float(w), *prm)) for t, prm in (windkessel or {}).items()]
+        A = system_matrix(asm, float(w), rho, mu, penalty, lumped)
         cidx, cval = constrained_dofs(asm, wall, dirn, gvals[s])
         f = system_rhs(asm, loads, traction[s], cidx, cval, A)
         Ac = constrained_matrix(A, cidx)
