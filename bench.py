@@ -56,6 +56,8 @@ def parse():
                          "Krylov basis (FP64 arithmetic)")
     ap.add_argument("--penalty", type=float, default=0.0,
                     help="penalized variant: continuity block -(penalty/mu) Mp (0: the method itself)")
+    ap.add_argument("--windkessel", type=str, default=None, metavar="RP,C,RD",
+                    help="three-element lumped model on the outlet instead of a traction-free outlet")
     ap.add_argument("--inner-rtol", type=float, default=1e-5,
                     help="mixed precision: end a cycle once its own residual fell by this factor")
     ap.add_argument("--orth", type=int, choices=[0, 1], default=1,
@@ -155,7 +157,7 @@ def warm_start_leg(args, case, m, g, opts, ns, ur, pr):
                                   cheb_ratio_pres=opts.cheb_ratio_pres, precision=opts.precision,
                                   verbose=opts.verbose)
     log(f"warm start: {nsn} snapshot solves ...")
-    us, ps, reps = m.solve(om, np.zeros((nsn, 0), np.complex128), gs, opts=snap_opts)
+    us, ps, reps = m.solve(om, np.zeros((nsn, m.info.ntraction), np.complex128), gs, opts=snap_opts)
     X = torch.cat([us.reshape(nsn, -1), ps], dim=1).contiguous()
     del us, ps, gs
     torch.cuda.synchronize()
@@ -224,7 +226,15 @@ def main():
     ctx = scvs.Context(0)
     t0 = time.perf_counter()
     m = scvs.Mesh.from_workload(ctx, mesh)
+    wk = None
+    if args.windkessel:
+        from workloads.meshes import OUTLET
+        wk = tuple(float(v) for v in args.windkessel.split(","))
+        case["bc"][OUTLET] = 3  # traction tag carrying the lumped model, zero offset pressure
+        case["traction"] = np.zeros((len(case["omega"]), 1), np.complex128)
     m.set_bc(case["bc"])
+    if wk:
+        m.set_windkessel({OUTLET: wk})
     m.assemble(case["rho"], case["mu"])
     torch.cuda.synchronize()
     t_ingest = time.perf_counter() - t0
@@ -323,6 +333,8 @@ def main():
                    "autotuned": tuned,
                    "orth": args.orth, "inner_rtol": args.inner_rtol, "precision": args.precision,
                    "penalty": args.penalty,
+                   "outlet": "traction-free" if wk is None else
+                   {"lumped": "three-element", "rp": wk[0], "c": wk[1], "rd": wk[2]},
                    "ntimes": args.ntimes},
         "dof_modes_per_s": info.ndof * ns * args.steps / dt,
         "roofline": roof(dominant),

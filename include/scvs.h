@@ -115,6 +115,22 @@ int scvs_mesh_set_midside(scvs_mesh mesh, int64_t n, const int32_t* edge_vertice
  * order), n^tau_A = int_{Gamma_tau} M_A n dGamma. May be called again. */
 int scvs_mesh_set_bc(scvs_mesh mesh, int n, const int32_t* tags, const int32_t* kinds);
 
+/* Lumped (Windkessel) outlets, as on the outflow faces of the Glenn case
+ * (section 3.6, which names the model without its form). Each listed tag must
+ * already be a TRACTION tag; its pressure becomes P = Z(w) Q + P0, where
+ * Q = int u.n over the tag (outward flow), P0 is the tag's traction coefficient
+ * of the system, and Z(w) = rp + rd / (1 + j w rd c) is the three-element model
+ * (rp in series with c parallel to rd; c = 0 or rd = 0 gives a resistance). The
+ * momentum rows gain Z b b^T with b = n^tau_A, one rank-one term per outlet,
+ * in every solve, residual and scvs_spmv; a distal pressure Pd behind rd enters
+ * as P0 = Pd / (1 + j w rd c). The preconditioner does not include these terms.
+ * tags, rp, c, rd: host arrays of n (n <= 64); n = 0 removes every lumped
+ * outlet; scvs_mesh_set_bc removes them too. Errors: SCVS_E_STATE before
+ * scvs_mesh_set_bc, SCVS_E_INVALID for a tag that is not TRACTION, a repeated
+ * tag, or a negative or non-finite parameter. */
+int scvs_mesh_set_windkessel(scvs_mesh mesh, int n, const int32_t* tags, const double* rp,
+                             const double* c, const double* rd);
+
 /* ---- a2: element assembly (section 2.3, Eq. LS_construction) ----
  * Assembles the mode-independent matrices
  *   Ks_AB = int grad M_A . grad M_B,  M_AB = int M_A M_B   (S2 order)

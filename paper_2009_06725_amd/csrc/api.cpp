@@ -1,4 +1,5 @@
 // C ABI of the SCVS library: validation, object lifetime, error reporting.
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <memory>
@@ -200,9 +201,31 @@ int scvs_mesh_set_bc(scvs_mesh m, int n, const int32_t* tags, const int32_t* kin
     use_device(m->ctx);
     m->bc_tags.assign(tags, tags + n);
     m->bc_kinds.assign(kinds, kinds + n);
+    scvs::mesh_windkessel(m, 0, nullptr, nullptr, nullptr, nullptr, m->ctx->stream);
     scvs::mesh_boundary(m, m->ctx->stream);
     m->generation++;
     if (m->assembled) scvs::mesh_precond_setup(m, m->ctx->stream);
+  });
+}
+
+int scvs_mesh_set_windkessel(scvs_mesh m, int n, const int32_t* tags, const double* rp, const double* c,
+                             const double* rd) {
+  return guarded([&] {
+    SCVS_REQUIRE(m, SCVS_E_INVALID, "mesh is null");
+    SCVS_REQUIRE(m->bc_set, SCVS_E_STATE, "boundary conditions not set (call scvs_mesh_set_bc)");
+    SCVS_REQUIRE(n >= 0 && n <= scvs::SCVS_WK_MAX && (n == 0 || (tags && rp && c && rd)), SCVS_E_INVALID,
+                 "bad lumped-outlet arguments");
+    for (int i = 0; i < n; ++i) {
+      SCVS_REQUIRE(std::find(m->traction_tags.begin(), m->traction_tags.end(), tags[i]) != m->traction_tags.end(),
+                   SCVS_E_INVALID, "a lumped outlet must be a TRACTION tag");
+      for (int k = 0; k < i; ++k) SCVS_REQUIRE(tags[k] != tags[i], SCVS_E_INVALID, "tag listed twice");
+      SCVS_REQUIRE(std::isfinite(rp[i]) && std::isfinite(c[i]) && std::isfinite(rd[i]) && rp[i] >= 0.0 &&
+                       c[i] >= 0.0 && rd[i] >= 0.0,
+                   SCVS_E_INVALID, "Windkessel parameters must be finite and >= 0");
+    }
+    use_device(m->ctx);
+    scvs::mesh_windkessel(m, n, tags, rp, c, rd, m->ctx->stream);
+    m->generation++;
   });
 }
 

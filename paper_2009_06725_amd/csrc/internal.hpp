@@ -173,6 +173,18 @@ struct scvs_mesh_s {
   double lp_lmax = 0.0;
   bool bc_set = false, assembled = false;
   double rho = 0.0, mu = 0.0;
+  // lumped (Windkessel) outlets: outlet o adds Z_o(w) b_o b_o^T to the momentum rows,
+  // b_o = int M_A n over the outlet (the load vector of its traction tag)
+  int nwk = 0;
+  std::vector<double> wk_par;          // [nwk][3]: rp, c, rd
+  scvs::DBuf<double> wk_dpar;          // device copy
+  scvs::DBuf<int64_t> wk_qoff;         // [2*nwk+1]: outlet o's free entries, then its Dirichlet entries
+  scvs::DBuf<int32_t> wk_qdof;         // velocity unknown d*A + c of each entry
+  scvs::DBuf<double> wk_qb;            // b at that unknown
+  int64_t wk_nrow = 0;                 // distinct free rows of all outlets
+  scvs::DBuf<int64_t> wk_roff;         // [wk_nrow+1] -> (outlet, b) pairs of each row
+  scvs::DBuf<int32_t> wk_rdof, wk_rout;
+  scvs::DBuf<double> wk_rb;
 };
 
 namespace scvs {
@@ -207,6 +219,10 @@ void download(T* host, const T* dev, size_t n, hipStream_t s) {
 void mesh_build(scvs_mesh m, hipStream_t s);
 void mesh_boundary(scvs_mesh m, hipStream_t s);
 void mesh_precond_setup(scvs_mesh m, hipStream_t s);
+// Lumped outlets on traction tags (tags already validated); n = 0 removes them.
+void mesh_windkessel(scvs_mesh m, int n, const int32_t* tags, const double* rp, const double* c, const double* rd,
+                     hipStream_t s);
+constexpr int SCVS_WK_MAX = 64;  // lumped outlets per mesh
 
 // ---- assemble.hip ----
 void assemble_mesh(scvs_mesh m, hipStream_t s);
@@ -245,6 +261,7 @@ struct Batch {
   const double* insc = nullptr;   // device [slots * insc_st] input scale (nullptr = 1)
   int insc_st = 0, insc_idx = 0;
   double pen = 0.0;  // penalty: continuity block -pen * Mp (lumped), pen = epsilon / mu
+  bool no_lumped = false;  // leave out the lumped-outlet terms
 };
 enum { SPMV_APPLY = 0, SPMV_RESID = 1, SPMV_RHS = 2 };
 // y = A x (APPLY), y = f - A x (RESID), y = [-sum P n - A x ; x on Dirichlet rows ; -G^T x] (RHS).
@@ -274,7 +291,9 @@ void precond_apply(scvs_mesh m, const Batch& b, const PrecondArgs& pa, VArg32 v,
 void spmv_apply_il(scvs_mesh m, const Batch& b, const void* xil, bool fp32, VArg y, hipStream_t s);
 void spmv_apply_il(scvs_mesh m, const Batch& b, const void* xil, bool fp32, VArg32 y, hipStream_t s);
 // y = f - A x (masked columns, as SPMV_RESID) with an FP32 output.
-void spmv_resid32(scvs_mesh m, const Batch& b, VArg x, VArg32 y, VArg f, hipStream_t s);
+// tmp: an FP64 vector per slot, used (when lumped outlets are present) to form the
+// residual in FP64 before it is rounded.
+void spmv_resid32(scvs_mesh m, const Batch& b, VArg x, VArg32 y, VArg f, hipStream_t s, VArg tmp = VArg{});
 // y = A x with FP32 matrix copies, FP32 input and FP32 accumulation; FP64 output.
 void spmv_apply32(scvs_mesh m, const Batch& b, VArg32 x, VArg y, hipStream_t s);
 // FP32 copies of the matrix values for mixed-precision solves (made once per assembly).
@@ -400,11 +419,13 @@ struct scvs_ws_s {
   scvs::Mlp net;
   scvs::MlpWork work;
   scvs::DBuf<float> X, T;         // training inputs/targets on the device
-  // reduced operator for the subspace correction: Q = [Q0; Q1] ([2r][ndof]) with
-  // A(w) phi_i = Q0_i + j w Q1_i on unconstrained rows, and its Gram matrix H (host)
+  // reduced operator for the subspace correction: Q = [Q0; Q1; B] ([2r+nb][ndof]) with
+  // A(w) phi_i = Q0_i + j w Q1_i + sum_o Z_o(w) Cb[o][i] B_o on unconstrained rows
+  // (B_o the load vector of lumped outlet o, Cb = B^T Phi), and its Gram matrix H (host)
   uint64_t red_gen = ~0ull;
+  int nb = 0;
   scvs::DBuf<double2> Q;
-  std::vector<std::complex<double>> H;
+  std::vector<std::complex<double>> H, Cb;
 };
 
 

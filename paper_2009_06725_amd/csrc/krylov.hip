@@ -983,7 +983,7 @@ void cycle_end(scvs_mesh m, Pool& P, const Batch& b, const PrecondArgs& pa, int6
       k_axpy<<<dim3(256, nact), 256, 0, s>>>(a, P.X(), P.Z());
   }
   if (P.v32)
-    spmv_resid32(m, b, P.X(), VArg32{reinterpret_cast<float2*>(P.V.p), vst}, P.F(), s);
+    spmv_resid32(m, b, P.X(), VArg32{reinterpret_cast<float2*>(P.V.p), vst}, P.F(), s, P.T());
   else
     spmv_full(m, b, P.X(), VArg{P.V.p, vst}, SPMV_RESID, true, P.F(), nullptr, s);
   {
@@ -1151,7 +1151,7 @@ int solve_systems(scvs_mesh m, int64_t nsys, const double* omega, const double* 
     auto residual0 = [&](const Batch& bb, const KArgs& ka, dim3 gn) {
       const int64_t vst = (int64_t)(mk + 1) * P.ld;
       if (P.v32) {
-        spmv_resid32(m, bb, P.X(), VArg32{reinterpret_cast<float2*>(P.V.p), vst}, P.F(), s);
+        spmv_resid32(m, bb, P.X(), VArg32{reinterpret_cast<float2*>(P.V.p), vst}, P.F(), s, P.T());
         k_norm<1, float2><<<gn, RBS, 0, s>>>(ka, VArg{}, o->rtol, o->inner_rtol);
       } else {
         spmv_full(m, bb, P.X(), VArg{P.V.p, vst}, SPMV_RESID, true, P.F(), nullptr, s);

@@ -161,6 +161,16 @@ __global__ void k_reduced_split(double2* __restrict__ Q, int r, int64_t N, const
   }
 }
 
+// B_o[dof] = b for the free entries of lumped outlet o (B zeroed before)
+__global__ void k_lumped_columns(const int64_t* __restrict__ qoff, const int32_t* __restrict__ qdof,
+                                 const double* __restrict__ qb, double2* __restrict__ B, int64_t N) {
+  const int o = blockIdx.y;
+  double2* col = B + (int64_t)o * N;
+  for (int64_t e = qoff[2 * o] + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < qoff[2 * o + 1];
+       e += (int64_t)gridDim.x * blockDim.x)
+    col[qdof[e]] = make_double2(qb[e], 0.0);
+}
+
 // zero rows of constrained dofs in R [n][N]
 __global__ void k_mask_rows(double2* __restrict__ R, int64_t N, const int32_t* __restrict__ dmask, int64_t DN,
                             int D) {
@@ -509,14 +519,17 @@ void ws_predict(scvs_ws w, int64_t n, const double* omega, const double* amp, do
 }
 
 // Reduced operator of the current assembly: Q0 = A(0) Phi, Q1 = (A(1) - A(0)) Phi / j on
-// unconstrained rows (A is affine in w), and H = [Q0; Q1]^H [Q0; Q1].
+// unconstrained rows, both without the lumped-outlet terms (the rest of A is affine
+// in w); B holds each lumped outlet's load vector on unconstrained rows, Cb = B^T Phi;
+// H = [Q0; Q1; B]^H [Q0; Q1; B].
 static void ws_reduced(scvs_ws w) {
   scvs_mesh m = w->mesh;
   if (w->red_gen == m->generation) return;
   hipStream_t s = m->ctx->stream;
   const int r = w->r;
+  const int nb = m->nwk;
   const int64_t N = w->ndof;
-  w->Q.alloc((size_t)2 * r * N);
+  w->Q.alloc((size_t)(2 * r + nb) * N);
   std::vector<double> om(2 * r, 0.0);
   for (int i = r; i < 2 * r; ++i) om[i] = 1.0;
   std::vector<int> a(2 * r);
@@ -531,13 +544,23 @@ static void ws_reduced(scvs_ws w) {
     b.nact = r;
     b.act = act.p + half * r;
     b.omega = omd.p + half * r;
+    b.no_lumped = true;
     spmv_full(m, b, VArg{w->basis.p, N}, VArg{w->Q.p + (int64_t)half * r * N, N}, SPMV_APPLY, true,
               VArg{}, nullptr, s);
   }
   const int64_t DN = (int64_t)m->dim * m->n2;
   k_reduced_split<<<dim3(512, (unsigned)r), 256, 0, s>>>(w->Q, r, N, m->dmask, DN, m->dim);
   launch_check(s);
-  w->H = cross(m->ctx, w->Q, 2 * r, w->Q, 2 * r, N, "k_gram");
+  w->Cb.clear();
+  if (nb) {
+    double2* B = w->Q.p + (int64_t)2 * r * N;
+    SCVS_HIP(hipMemsetAsync(B, 0, (size_t)nb * N * sizeof(double2), s));
+    k_lumped_columns<<<dim3(64, (unsigned)nb), 256, 0, s>>>(m->wk_qoff, m->wk_qdof, m->wk_qb, B, N);
+    launch_check(s);
+    w->Cb = cross(m->ctx, B, nb, w->basis, r, N, "k_ws_lumped");
+  }
+  w->nb = nb;
+  w->H = cross(m->ctx, w->Q, 2 * r + nb, w->Q, 2 * r + nb, N, "k_gram");
   w->red_gen = m->generation;
 }
 
@@ -569,20 +592,37 @@ void ws_refine(scvs_ws w, int64_t n, const double* omega, const double* traction
     launch_check(s);
     SCVS_HIP(hipStreamSynchronize(s));
   }
-  const std::vector<cd> B = cross(m->ctx, w->Q, 2 * r, R, (int)n, N, "k_ws_project");  // [2r][n]
-  // per system: min || R - (Q0 + j w Q1) d ||, normal equations solved by eigen-decomposition
+  const int nw = 2 * r + w->nb;
+  const std::vector<cd> B = cross(m->ctx, w->Q, nw, R, (int)n, N, "k_ws_project");  // [nw][n]
+  // per system: min || R - [Q0; Q1; B] E d || with E = [I; j w I; diag(Z(w)) Cb], normal
+  // equations E^H H E d = E^H B solved by eigen-decomposition
   std::vector<cd> coef((size_t)n * r);
-  const int r2 = 2 * r;
   for (int64_t k = 0; k < n; ++k) {
     const double wk = omega[k];
-    const cd jw(0.0, wk);
-    std::vector<cd> Mk((size_t)r * r), V;
-    std::vector<cd> rhs(r);
+    std::vector<cd> E((size_t)nw * r, cd(0.0));
     for (int i = 0; i < r; ++i) {
-      for (int j = 0; j < r; ++j)
-        Mk[(size_t)i * r + j] = w->H[(size_t)i * r2 + j] + jw * w->H[(size_t)i * r2 + r + j] -
-                                jw * w->H[(size_t)(r + i) * r2 + j] + wk * wk * w->H[(size_t)(r + i) * r2 + r + j];
-      rhs[i] = B[(size_t)i * n + k] - jw * B[(size_t)(r + i) * n + k];
+      E[(size_t)i * r + i] = 1.0;
+      E[(size_t)(r + i) * r + i] = cd(0.0, wk);
+    }
+    for (int o = 0; o < w->nb; ++o) {
+      const double rp = m->wk_par[3 * o], cc = m->wk_par[3 * o + 1], rd = m->wk_par[3 * o + 2];
+      const cd Z = rp + rd / cd(1.0, wk * rd * cc);
+      for (int i = 0; i < r; ++i) E[(size_t)(2 * r + o) * r + i] = Z * w->Cb[(size_t)o * r + i];
+    }
+    std::vector<cd> HE((size_t)nw * r, cd(0.0)), Mk((size_t)r * r, cd(0.0)), V;
+    std::vector<cd> rhs(r, cd(0.0));
+    for (int a = 0; a < nw; ++a)
+      for (int c = 0; c < nw; ++c) {
+        const cd h = w->H[(size_t)a * nw + c];
+        for (int j = 0; j < r; ++j) HE[(size_t)a * r + j] += h * E[(size_t)c * r + j];
+      }
+    for (int i = 0; i < r; ++i) {
+      for (int a = 0; a < nw; ++a) {
+        const cd e = std::conj(E[(size_t)a * r + i]);
+        if (e == cd(0.0)) continue;
+        for (int j = 0; j < r; ++j) Mk[(size_t)i * r + j] += e * HE[(size_t)a * r + j];
+        rhs[i] += e * B[(size_t)a * n + k];
+      }
     }
     std::vector<double> lam;
     herm_eig(r, Mk, lam, V);

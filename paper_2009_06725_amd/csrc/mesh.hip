@@ -657,4 +657,107 @@ void mesh_precond_setup(scvs_mesh m, hipStream_t s) {
   m->lp_lmax = v > 0.0 ? v : 1.0;
 }
 
+namespace {
+
+// Entries of one load vector b [n2*D] on unknowns whose node has mask value `want`
+// (0 free, 2 prescribed inflow): flag, then compact (dof, b) in unknown order.
+__global__ void k_wk_flag(const double* __restrict__ b, const int32_t* __restrict__ dmask, int64_t n, int D,
+                          int32_t want, int32_t* __restrict__ flag) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) flag[i] = (b[i] != 0.0 && dmask[i / D] == want);
+}
+
+__global__ void k_wk_compact(const int32_t* __restrict__ flag, const int64_t* __restrict__ pos,
+                             const double* __restrict__ b, int64_t n, int32_t* __restrict__ dof,
+                             double* __restrict__ val) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n && flag[i]) {
+    dof[pos[i]] = (int32_t)i;
+    val[pos[i]] = b[i];
+  }
+}
+
+}  // namespace
+
+void mesh_windkessel(scvs_mesh m, int n, const int32_t* tags, const double* rp, const double* c, const double* rd,
+                     hipStream_t s) {
+  m->nwk = 0;
+  m->wk_par.clear();
+  m->wk_nrow = 0;
+  if (n == 0) return;
+  const int D = m->dim;
+  const int64_t N = m->n2 * D;
+  DBuf<int32_t> flag;
+  DBuf<int64_t> pos;
+  flag.alloc(N);
+  pos.alloc(N + 1);
+  std::vector<int64_t> qoff(1, 0);
+  std::vector<int32_t> qdof;
+  std::vector<double> qb;
+  struct Ent {
+    int32_t dof, out;
+    double b;
+  };
+  std::vector<Ent> rows;
+  for (int o = 0; o < n; ++o) {
+    const int t = (int)(std::find(m->traction_tags.begin(), m->traction_tags.end(), tags[o]) -
+                        m->traction_tags.begin());
+    const double* bt = m->loads.p + (size_t)t * N;
+    for (int want : {0, 2}) {  // free unknowns, then prescribed-inflow unknowns
+      k_wk_flag<<<nblk(N), 256, 0, s>>>(bt, m->dmask, N, D, want, flag);
+      SCVS_HIP(hipGetLastError());
+      const int64_t cnt = exclusive_scan32(flag, pos, N, s);
+      if (cnt) {
+        DBuf<int32_t> dd;
+        DBuf<double> dv;
+        dd.alloc(cnt);
+        dv.alloc(cnt);
+        k_wk_compact<<<nblk(N), 256, 0, s>>>(flag, pos, bt, N, dd, dv);
+        SCVS_HIP(hipGetLastError());
+        const size_t at = qdof.size();
+        qdof.resize(at + cnt);
+        qb.resize(at + cnt);
+        download(qdof.data() + at, dd.p, cnt, s);
+        download(qb.data() + at, dv.p, cnt, s);
+        if (want == 0)
+          for (int64_t e = 0; e < cnt; ++e) rows.push_back({qdof[at + e], o, qb[at + e]});
+      }
+      qoff.push_back((int64_t)qdof.size());
+    }
+    m->wk_par.insert(m->wk_par.end(), {rp[o], c[o], rd[o]});
+  }
+  // rows: distinct free unknowns, each with its (outlet, b) pairs in outlet order
+  std::stable_sort(rows.begin(), rows.end(), [](const Ent& a, const Ent& b) { return a.dof < b.dof; });
+  std::vector<int64_t> roff(1, 0);
+  std::vector<int32_t> rdof, rout;
+  std::vector<double> rb;
+  for (size_t e = 0; e < rows.size(); ++e) {
+    if (e == 0 || rows[e].dof != rows[e - 1].dof) {
+      if (e) roff.push_back((int64_t)e);
+      rdof.push_back(rows[e].dof);
+    }
+    rout.push_back(rows[e].out);
+    rb.push_back(rows[e].b);
+  }
+  roff.push_back((int64_t)rows.size());
+  if (rows.empty()) roff.assign(1, 0);
+  auto up = [&](auto& buf, const auto& v) {
+    if (v.empty())
+      buf.alloc(1);
+    else
+      buf.upload(v.data(), v.size(), s);
+  };
+  up(m->wk_dpar, m->wk_par);
+  up(m->wk_qoff, qoff);
+  up(m->wk_qdof, qdof);
+  up(m->wk_qb, qb);
+  up(m->wk_roff, roff);
+  up(m->wk_rdof, rdof);
+  up(m->wk_rout, rout);
+  up(m->wk_rb, rb);
+  SCVS_HIP(hipStreamSynchronize(s));
+  m->wk_nrow = (int64_t)rdof.size();
+  m->nwk = n;
+}
+
 }  // namespace scvs

@@ -321,6 +321,91 @@ __global__ void __launch_bounds__(256) k_full(MeshArgs ma, Batch b, LaneMap lm, 
   }
 }
 
+// Lumped outlets: after the operator kernel, y += s * sc * Z_o(w) (b_o^T x) b_o on the
+// free momentum rows of every outlet o, s = +1 for y = A x and -1 for y = f - A x and
+// for the right-hand side (where x is the Dirichlet lift and b_o^T x runs over the
+// prescribed-inflow unknowns, as the symmetric elimination moves them). One block
+// per system: fixed-order block sums for the flows, then the rank-one updates.
+struct WkArgs {
+  int n;
+  const double* par;
+  const int64_t* qoff;
+  const int32_t* qdof;
+  const double* qb;
+  int64_t nrow;
+  const int64_t* roff;
+  const int32_t* rdof;
+  const int32_t* rout;
+  const double* rb;
+};
+
+WkArgs wk_args(scvs_mesh m) {
+  return {m->nwk,  m->wk_dpar, m->wk_qoff, m->wk_qdof, m->wk_qb,
+          m->wk_nrow, m->wk_roff, m->wk_rdof, m->wk_rout, m->wk_rb};
+}
+
+template <int D, class XC, bool IL, class YT>
+__global__ void __launch_bounds__(256) k_wk(WkArgs w, Batch b, int mode, SV<XC> x, const XC* __restrict__ xil,
+                                            int G, SV<YT> y) {
+  __shared__ double2 part[4];
+  __shared__ double2 zq[SCVS_WK_MAX];
+  const int si = blockIdx.x;
+  const int slot = b.act[si];
+  const XC* __restrict__ xs = IL ? nullptr : x.at(slot);
+  const int half = mode == SPMV_RHS ? 1 : 0;
+  for (int o = 0; o < w.n; ++o) {
+    double2 acc = make_double2(0.0, 0.0);
+    for (int64_t e = w.qoff[2 * o + half] + threadIdx.x; e < w.qoff[2 * o + half + 1]; e += blockDim.x) {
+      const int32_t dof = w.qdof[e];
+      const XC v = IL ? xil[(int64_t)(dof / D) * G + si * D + dof % D] : xs[dof];
+      acc.x += w.qb[e] * (double)v.x;
+      acc.y += w.qb[e] * (double)v.y;
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+      acc.x += __shfl_down(acc.x, off);
+      acc.y += __shfl_down(acc.y, off);
+    }
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const double2 q = make_double2(part[0].x + part[1].x + part[2].x + part[3].x,
+                                     part[0].y + part[1].y + part[2].y + part[3].y);
+      // Z = rp + rd / (1 + j w rd c)
+      const double rp = w.par[3 * o], cc = w.par[3 * o + 1], rd = w.par[3 * o + 2];
+      const double t = b.omega[slot] * rd * cc, den = 1.0 + t * t;
+      const double zr = rp + rd / den, zi = -rd * t / den;
+      const double sg = (mode == SPMV_APPLY ? 1.0 : -1.0) * in_scale(b, slot);
+      zq[o] = make_double2(sg * (zr * q.x - zi * q.y), sg * (zr * q.y + zi * q.x));
+    }
+    __syncthreads();
+  }
+  YT* __restrict__ ys = y.at(slot);
+  for (int64_t r = threadIdx.x; r < w.nrow; r += blockDim.x) {
+    double2 add = make_double2(0.0, 0.0);
+    for (int64_t e = w.roff[r]; e < w.roff[r + 1]; ++e) {
+      const double2 q = zq[w.rout[e]];
+      add.x += q.x * w.rb[e];
+      add.y += q.y * w.rb[e];
+    }
+    const int32_t dof = w.rdof[r];
+    const YT old = ys[dof];
+    ys[dof] = cvt2<YT>(make_double2((double)old.x + add.x, (double)old.y + add.y));
+  }
+}
+
+template <class XC, bool IL, class YT>
+void wk_launch(scvs_mesh m, const Batch& b, int mode, SV<XC> x, const XC* xil, SV<YT> y, hipStream_t s) {
+  if (m->nwk == 0 || b.no_lumped || b.nact == 0) return;
+  const WkArgs w = wk_args(m);
+  const int D = m->dim;
+  ProfScope ps(&m->ctx->prof, s, "k_wk", 0.0);
+  if (D == 2)
+    k_wk<2, XC, IL, YT><<<b.nact, 256, 0, s>>>(w, b, mode, x, xil, b.nact * 2, y);
+  else
+    k_wk<3, XC, IL, YT><<<b.nact, 256, 0, s>>>(w, b, mode, x, xil, b.nact * 3, y);
+  launch_check(s);
+}
+
 // Chebyshev recurrence scalars for step i >= 1 on [lmax/ratio, lmax]:
 // rho_0 = 1/sigma, rho_k = 1/(2 sigma - rho_{k-1}) with sigma = theta/delta =
 // (1 + 1/ratio)/(1 - 1/ratio), which does not depend on lmax; returns rho_{i-1}, rho_i.
@@ -673,6 +758,15 @@ void precond_launch(Profiler* prof, const MeshArgs& ma, const Batch& b, const Pr
   launch_check(s);
 }
 
+// y_slot = (float) x_slot for the active systems
+__global__ void k_round32(const int* __restrict__ act, VArg x, VArg32 y, int64_t n) {
+  const int slot = act[blockIdx.y];
+  const double2* xs = x.at(slot);
+  float2* ys = y.at(slot);
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    ys[i] = make_float2((float)xs[i].x, (float)xs[i].y);
+}
+
 __global__ void k_to_f32(const double* __restrict__ a, float* __restrict__ b, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     b[i] = (float)a[i];
@@ -688,6 +782,7 @@ void spmv_full(scvs_mesh m, const Batch& b, VArg x, VArg y, int mode, bool maskc
     full_launch<2>(&m->ctx->prof, ma, b, x, y, mode, maskcol, f, m->loads, ntr, trac, s);
   else
     full_launch<3>(&m->ctx->prof, ma, b, x, y, mode, maskcol, f, m->loads, ntr, trac, s);
+  wk_launch<double2, false, double2>(m, b, mode, x, nullptr, y, s);
 }
 
 template <class VI>
@@ -722,6 +817,10 @@ static void spmv_il_any(scvs_mesh m, const Batch& b, const void* xil, bool fp32,
     else
       full_launch_il<3, double, YT>(&m->ctx->prof, ma, b, (const double2*)xil, y, s);
   }
+  if (fp32)
+    wk_launch<float2, true, YT>(m, b, SPMV_APPLY, SV<float2>{}, (const float2*)xil, y, s);
+  else
+    wk_launch<double2, true, YT>(m, b, SPMV_APPLY, SV<double2>{}, (const double2*)xil, y, s);
 }
 
 void spmv_apply_il(scvs_mesh m, const Batch& b, const void* xil, bool fp32, VArg y, hipStream_t s) {
@@ -732,7 +831,16 @@ void spmv_apply_il(scvs_mesh m, const Batch& b, const void* xil, bool fp32, VArg
   spmv_il_any(m, b, xil, fp32, y, s);
 }
 
-void spmv_resid32(scvs_mesh m, const Batch& b, VArg x, VArg32 y, VArg f, hipStream_t s) {
+void spmv_resid32(scvs_mesh m, const Batch& b, VArg x, VArg32 y, VArg f, hipStream_t s, VArg tmp) {
+  if (m->nwk > 0 && !b.no_lumped && tmp.p) {
+    // with lumped outlets the operator part and the rank-one part nearly cancel near
+    // convergence: form the residual in FP64 and round it once
+    spmv_full(m, b, x, tmp, SPMV_RESID, true, f, nullptr, s);
+    const int64_t ndof = (int64_t)m->dim * m->n2 + m->nv;
+    k_round32<<<dim3(256, (unsigned)b.nact), 256, 0, s>>>(b.act, tmp, y, ndof);
+    launch_check(s);
+    return;
+  }
   const MeshArgs ma = mesh_args(m);
   const int D = m->dim;
   const LaneMap lm = lane_map(b.nact, D);
@@ -744,6 +852,7 @@ void spmv_resid32(scvs_mesh m, const Batch& b, VArg x, VArg32 y, VArg f, hipStre
   else
     k_full<3, SPMV_RESID, true, double, false, float2><<<nb, 256, 0, s>>>(ma, b, lm, x, y, f, nullptr, 0, nullptr);
   launch_check(s);
+  wk_launch<double2, false, float2>(m, b, SPMV_RESID, x, nullptr, y, s);
 }
 
 void spmv_apply32(scvs_mesh m, const Batch& b, VArg32 x, VArg y, hipStream_t s) {
@@ -752,6 +861,7 @@ void spmv_apply32(scvs_mesh m, const Batch& b, VArg32 x, VArg y, hipStream_t s) 
     full_launch32<2>(&m->ctx->prof, ma, b, x, y, s);
   else
     full_launch32<3>(&m->ctx->prof, ma, b, x, y, s);
+  wk_launch<float2, false, double2>(m, b, SPMV_APPLY, x, nullptr, y, s);
 }
 
 void make_fp32_copies(scvs_mesh m, hipStream_t s) {

@@ -21,7 +21,8 @@ X_EDGES, X_C2N, X_ROWPTR, X_COL, X_KS, X_M, X_G, X_MP, X_DIRNODES, X_DMASK, X_LO
 
 EXPORTED = [
     "scvs_last_error", "scvs_version", "scvs_ctx_create", "scvs_ctx_destroy", "scvs_mesh_create",
-    "scvs_mesh_destroy", "scvs_mesh_info", "scvs_mesh_set_midside", "scvs_mesh_set_bc", "scvs_assemble",
+    "scvs_mesh_destroy", "scvs_mesh_info", "scvs_mesh_set_midside", "scvs_mesh_set_bc", "scvs_mesh_set_windkessel",
+    "scvs_assemble",
     "scvs_mesh_export", "scvs_spmv", "scvs_rhs", "scvs_solve_opts_default", "scvs_solve",
     "scvs_autotune", "scvs_solve_groups", "scvs_boundary_norms", "scvs_mode_norms", "scvs_select_modes",
     "scvs_mode_increments", "scvs_synthesize", "scvs_probe_mfma", "scvs_profile_enable", "scvs_profile_read",
@@ -87,6 +88,7 @@ def lib() -> C.CDLL:
         L.scvs_mesh_info.argtypes = [vp, C.POINTER(MeshInfo)]
         L.scvs_mesh_set_midside.argtypes = [vp, i64, vp, vp]
         L.scvs_mesh_set_bc.argtypes = [vp, C.c_int, vp, vp]
+        L.scvs_mesh_set_windkessel.argtypes = [vp, C.c_int, vp, vp, vp, vp]
         L.scvs_assemble.argtypes = [vp, C.c_double, C.c_double]
         L.scvs_mesh_export.argtypes = [vp, C.c_int, vp]
         L.scvs_spmv.argtypes = [vp, i64, vp, vp, vp]
@@ -230,6 +232,15 @@ class Mesh:
         tags, pt = _host(list(bc.keys()), np.int32)
         kinds, pk = _host(list(bc.values()), np.int32)
         _check(lib().scvs_mesh_set_bc(self.h, tags.size, pt, pk))
+
+    def set_windkessel(self, outlets: dict):
+        """Lumped outlets {traction tag: (rp, c, rd)}; an empty dict removes them."""
+        tags, pt = _host(list(outlets.keys()), np.int32)
+        prm = np.array(list(outlets.values()), np.float64).reshape(-1, 3)
+        rp, pr = _host(prm[:, 0], np.float64)
+        cc, pc = _host(prm[:, 1], np.float64)
+        rd, pd = _host(prm[:, 2], np.float64)
+        _check(lib().scvs_mesh_set_windkessel(self.h, tags.size, pt, pr, pc, pd))
 
     def assemble(self, rho: float, mu: float):
         _check(lib().scvs_assemble(self.h, rho, mu))
