@@ -168,6 +168,7 @@ struct scvs_mesh_s {
   scvs::DBuf<int64_t> lp_ptr;
   scvs::DBuf<int32_t> lp_col;
   scvs::DBuf<double> lp_val;
+  scvs::DBuf<float> lp_val32;  // FP32 copy for the mixed-precision Schur block
   int64_t nnzl = 0;
   int64_t ndir = 0;
   double lp_lmax = 0.0;

@@ -248,6 +248,11 @@ __global__ void k_mark(const int32_t* __restrict__ fnodes, const int32_t* __rest
   if (fkind[i / nfn] == kind) dmask[fnodes[i]] = value;
 }
 
+__global__ void k_d2f(const double* __restrict__ a, float* __restrict__ b, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = (float)a[i];
+}
+
 __global__ void k_flag_eq(const int32_t* __restrict__ a, int64_t n, int32_t v, int32_t* __restrict__ flag) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) flag[i] = (a[i] == v);
@@ -639,6 +644,9 @@ void mesh_precond_setup(scvs_mesh m, hipStream_t s) {
     k_lp_vals<3><<<nblk(m->nnzl), 256, 0, s>>>(m->lp_ptr, m->lp_col, m->nnzl, m->nv, m->rowptr, m->col, m->nvc,
                                               m->rowptr21, m->G, m->Gt, m->nnz21, m->nnzv, m->Md, m->dmask,
                                               m->lp_val);
+  SCVS_HIP(hipGetLastError());
+  m->lp_val32.alloc(m->nnzl);
+  k_d2f<<<nblk(m->nnzl), 256, 0, s>>>(m->lp_val, m->lp_val32, m->nnzl);
   SCVS_HIP(hipGetLastError());
   DBuf<double> ratio;
   ratio.alloc(m->nv);

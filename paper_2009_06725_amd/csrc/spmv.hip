@@ -44,6 +44,7 @@ struct MeshArgs {
   const int64_t* lp_ptr;
   const int32_t* lp_col;
   const double* lp_val;
+  const float* lp_val32;
   double mu, rho, lpmax;
 };
 
@@ -77,6 +78,7 @@ MeshArgs mesh_args(scvs_mesh m) {
   a.lp_ptr = m->lp_ptr;
   a.lp_col = m->lp_col;
   a.lp_val = m->lp_val;
+  a.lp_val32 = m->lp_val32;
   a.mu = m->mu;
   a.rho = m->rho;
   a.lpmax = m->lp_lmax;
@@ -96,6 +98,7 @@ struct Prec<double> {
   __device__ static const double* Gt(const MeshArgs& a) { return a.Gt; }
   __device__ static const double* Kd(const MeshArgs& a) { return a.Kd; }
   __device__ static const double* Md(const MeshArgs& a) { return a.Md; }
+  __device__ static const double* Lp(const MeshArgs& a) { return a.lp_val; }
 };
 template <>
 struct Prec<float> {
@@ -107,6 +110,7 @@ struct Prec<float> {
   __device__ static const float* Gt(const MeshArgs& a) { return a.Gt32; }
   __device__ static const float* Kd(const MeshArgs& a) { return a.Kd32; }
   __device__ static const float* Md(const MeshArgs& a) { return a.Md32; }
+  __device__ static const float* Lp(const MeshArgs& a) { return a.lp_val32; }
 };
 
 template <class C>
@@ -536,8 +540,10 @@ __global__ void __launch_bounds__(256) k_vstep(MeshArgs ma, Batch b, LaneMap lm,
 // d0 = diag(L)^-1 r / theta, x = d0; with one step the Schur block is final:
 // zhat_p = -(mu Mp^-1 v_p + j w rho x). Temps r, d0, d1, x are interleaved like the
 // velocity ones: system si of the active list at vertex A sits at A*G + si.
-template <class VI>
-__global__ void k_pinit(MeshArgs ma, int D, Batch b, SV<VI> v, VArg z, ITemps<double2> pt, double ratio, int kp) {
+template <class VI, class R>
+__global__ void k_pinit(MeshArgs ma, int D, Batch b, SV<VI> v, VArg z, ITemps<typename Prec<R>::C> pt, double ratio,
+                        int kp) {
+  using C = typename Prec<R>::C;
   const int64_t vv = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (vv >= ma.nv) return;
   const int si = blockIdx.y;
@@ -547,9 +553,9 @@ __global__ void k_pinit(MeshArgs ma, int D, Batch b, SV<VI> v, VArg z, ITemps<do
   const double2 vp = cscale(to_d2(v.at(slot)[DN + vv]), sc);
   const double theta = 0.5 * ma.lpmax * (1.0 + 1.0 / ratio);
   const double2 dd = cscale(vp, ma.lpdinv[vv] / theta);
-  pt.arr(0)[ki] = vp;
-  pt.arr(1)[ki] = dd;
-  pt.arr(3)[ki] = dd;
+  pt.arr(0)[ki] = cvt2<C>(vp);
+  pt.arr(1)[ki] = cvt2<C>(dd);
+  pt.arr(3)[ki] = cvt2<C>(dd);
   if (kp <= 1) {
     // kp == 0: the Schur block is the pressure mass alone, zhat_p = -mu Mp^-1 v_p
     const double2 xl = kp == 0 ? make_double2(0.0, 0.0) : dd;
@@ -562,9 +568,12 @@ __global__ void k_pinit(MeshArgs ma, int D, Batch b, SV<VI> v, VArg z, ITemps<do
 // b diag(L)^-1 r; x += d_new; on the last step zhat_p = -(mu Mp^-1 v_p + j w rho x).
 // Lanes do not cooperate here, so threads map linearly onto (vertex, system) pairs: every
 // lane works, and the systems of one vertex sit in adjacent lanes (coalesced gathers).
-template <class VI>
-__global__ void __launch_bounds__(256) k_pstep(MeshArgs ma, int D, Batch b, SV<VI> v, VArg z, ITemps<double2> pt,
-                                               double ratio, ChebStep cs, int step, int last) {
+template <class VI, class R>
+__global__ void __launch_bounds__(256) k_pstep(MeshArgs ma, int D, Batch b, SV<VI> v, VArg z,
+                                               ITemps<typename Prec<R>::C> pt, double ratio, ChebStep cs, int step,
+                                               int last) {
+  using C = typename Prec<R>::C;
+  const R* __restrict__ lval = Prec<R>::Lp(ma);
   const int G = pt.G;
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= ma.nv * G) return;
@@ -572,22 +581,22 @@ __global__ void __launch_bounds__(256) k_pstep(MeshArgs ma, int D, Batch b, SV<V
   const int p = (int)(idx - A * G);
   const int slot = b.act[p];
   const int64_t ki = idx;  // = A * G + p
-  double2* rp = pt.arr(0);
-  const double2* __restrict__ dold = pt.arr((step & 1) ? 1 : 2);
-  double2* dnew = pt.arr((step & 1) ? 2 : 1);
-  double2* xp = pt.arr(3);
-  double2 q = make_double2(0.0, 0.0);
+  C* rp = pt.arr(0);
+  const C* __restrict__ dold = pt.arr((step & 1) ? 1 : 2);
+  C* dnew = pt.arr((step & 1) ? 2 : 1);
+  C* xp = pt.arr(3);
+  C q = czero<C>();
   const int64_t k0 = ma.lp_ptr[A], k1 = ma.lp_ptr[A + 1];
   int64_t k = k0;
   for (; k + 4 <= k1; k += 4) {
     int32_t u[4];
-    double l[4];
-    double2 dv[4];
+    R l[4];
+    C dv[4];
 #pragma unroll
     for (int t = 0; t < 4; ++t) u[t] = ma.lp_col[k + t];
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
-      l[t] = ma.lp_val[k + t];
+      l[t] = lval[k + t];
       dv[t] = dold[(int64_t)u[t] * G + p];
     }
 #pragma unroll
@@ -597,17 +606,21 @@ __global__ void __launch_bounds__(256) k_pstep(MeshArgs ma, int D, Batch b, SV<V
     }
   }
   for (; k < k1; ++k) {
-    const double l = ma.lp_val[k];
-    const double2 dv = dold[(int64_t)ma.lp_col[k] * G + p];
+    const R l = lval[k];
+    const C dv = dold[(int64_t)ma.lp_col[k] * G + p];
     q.x += l * dv.x;
     q.y += l * dv.y;
   }
   const double rpv = cs.rprev, rc = cs.rcur, delta = 0.5 * ma.lpmax * (1.0 - 1.0 / ratio);
-  const double2 rn = csub(rp[ki], q);
-  const double ca = rc * rpv, cb = 2.0 * rc / delta * ma.lpdinv[A];
-  const double2 dk = dold[ki];
-  const double2 dn = make_double2(ca * dk.x + cb * rn.x, ca * dk.y + cb * rn.y);
-  const double2 xn = cadd(xp[ki], dn);
+  const C r0 = rp[ki], dk = dold[ki], x0 = xp[ki];
+  const R ca = (R)(rc * rpv), cb = (R)(2.0 * rc / delta * ma.lpdinv[A]);
+  C rn, dn, xn;
+  rn.x = r0.x - q.x;
+  rn.y = r0.y - q.y;
+  dn.x = ca * dk.x + cb * rn.x;
+  dn.y = ca * dk.y + cb * rn.y;
+  xn.x = x0.x + dn.x;
+  xn.y = x0.y + dn.y;
   rp[ki] = rn;
   dnew[ki] = dn;
   xp[ki] = xn;
@@ -616,7 +629,9 @@ __global__ void __launch_bounds__(256) k_pstep(MeshArgs ma, int D, Batch b, SV<V
     const double sc = in_scale(b, slot);
     const double2 vp = cscale(to_d2(v.at(slot)[DN + A]), sc);
     const double wr = b.omega[slot] * ma.rho, im = ma.mu / ma.Mp[A];
-    z.at(slot)[DN + A] = make_double2(-(im * vp.x - wr * xn.y), -(im * vp.y + wr * xn.x));
+    // the pressure-mass Schur scaling and the combination stay FP64
+    const double2 xd = to_d2(xn);
+    z.at(slot)[DN + A] = make_double2(-(im * vp.x - wr * xd.y), -(im * vp.y + wr * xd.x));
   }
 }
 
@@ -716,18 +731,29 @@ void precond_launch(Profiler* prof, const MeshArgs& ma, const Batch& b, const Pr
   const double n2 = (double)ma.n2, nv = (double)ma.nv, DN = (double)D * ma.n2, na = b.nact;
   dim3 gp((unsigned)((ma.nv + 255) / 256), (unsigned)b.nact);
   // interleaved pressure temporaries inside the slot pool's block (4 * nv per slot, contiguous)
+  // (FP32 recurrence in mixed mode: the same temporaries hold float2 values)
   const ITemps<double2> ptl{pa.pt.p, ma.nv, b.nact};
+  const ITemps<float2> ptl32{reinterpret_cast<float2*>(pa.pt.p), ma.nv, b.nact};
+  const double pes = pa.mixed ? 8.0 : 16.0, pvs = pa.mixed ? 4.0 : 8.0;  // complex / real temp bytes
   {
     // per system: v_p read, r/d0/x written (and z_p when one step); lpdinv, Mp read
-    ProfScope ps(prof, s, "k_pinit", nv * 16.0 + na * nv * 16.0 * 4.0);
-    k_pinit<VI><<<gp, 256, 0, s>>>(ma, D, b, v, z, ptl, pa.ratio_p, pa.kp);
+    ProfScope ps(prof, s, pa.mixed ? "k_pinit32" : "k_pinit", nv * 16.0 + na * nv * (16.0 + 3.0 * pes));
+    if (pa.mixed)
+      k_pinit<VI, float><<<gp, 256, 0, s>>>(ma, D, b, v, z, ptl32, pa.ratio_p, pa.kp);
+    else
+      k_pinit<VI, double><<<gp, 256, 0, s>>>(ma, D, b, v, z, ptl, pa.ratio_p, pa.kp);
   }
   // L values and columns, row pointers, diag, Mp; per system d_old gathered,
   // r read+written, d_new written, x read+written
-  const double pbytes = (double)ma.nnzl * 12.0 + nv * 24.0 + na * nv * 16.0 * 6.0;
+  const double pbytes = (double)ma.nnzl * (4.0 + pvs) + nv * 24.0 + na * nv * pes * 6.0;
   for (int i = 1; i < pa.kp; ++i) {
-    ProfScope ps(prof, s, "k_pstep", pbytes + (i == pa.kp - 1 ? na * nv * 32.0 : 0.0));
-    k_pstep<VI><<<nbp, 256, 0, s>>>(ma, D, b, v, z, ptl, pa.ratio_p, cheb_step(pa.ratio_p, i), i, i == pa.kp - 1);
+    ProfScope ps(prof, s, pa.mixed ? "k_pstep32" : "k_pstep", pbytes + (i == pa.kp - 1 ? na * nv * 32.0 : 0.0));
+    if (pa.mixed)
+      k_pstep<VI, float><<<nbp, 256, 0, s>>>(ma, D, b, v, z, ptl32, pa.ratio_p, cheb_step(pa.ratio_p, i), i,
+                                             i == pa.kp - 1);
+    else
+      k_pstep<VI, double><<<nbp, 256, 0, s>>>(ma, D, b, v, z, ptl, pa.ratio_p, cheb_step(pa.ratio_p, i), i,
+                                              i == pa.kp - 1);
   }
   const double es = pa.mixed ? 8.0 : 16.0, vs = pa.mixed ? 4.0 : 8.0;  // complex / real element bytes
   // interleaved temporaries inside the slot pool's temp block (4 * D*n2 per slot, contiguous)
