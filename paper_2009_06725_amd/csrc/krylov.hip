@@ -621,20 +621,42 @@ __global__ void __launch_bounds__(RBS) k_lag_update(KArgs a, int j) {
   VT* __restrict__ w = vecT<VT>(a, slot, j + 1);
   const VT* __restrict__ V0 = vecT<VT>(a, slot, 0);
   double2 acc[1] = {make_double2(0.0, 0.0)};
-  for (int64_t n = b0 + threadIdx.x; n < b1; n += RBS) {
-    double2 sq = make_double2(0.0, 0.0), sw = make_double2(0.0, 0.0);
-#pragma unroll 8
+  // each wavefront takes E * 64 consecutive elements, so every basis vector is read in
+  // runs of E * 64 values (longer DRAM bursts than one value per lane per vector)
+  constexpr int E = 8;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int64_t nb = b0 + (int64_t)wave * 64 * E; nb < b1; nb += (int64_t)RBS * E) {
+    double2 sq[E], sw[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) sq[e] = sw[e] = make_double2(0.0, 0.0);
+#pragma unroll 2
     for (int i = 0; i < j; ++i) {
-      const double2 v = to_d2(V0[(int64_t)i * a.ld + n]);
-      sq = cadd(sq, cmul(cq[i], v));
-      sw = cadd(sw, cmul(cw[i], v));
+      const VT* __restrict__ vi = V0 + (int64_t)i * a.ld;
+      double2 v[E];
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const int64_t n = nb + lane + 64 * e;
+        v[e] = n < b1 ? to_d2(vi[n]) : make_double2(0.0, 0.0);
+      }
+      const double2 ci = cq[i], wi = cw[i];
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        sq[e] = cadd(sq[e], cmul(ci, v[e]));
+        sw[e] = cadd(sw[e], cmul(wi, v[e]));
+      }
     }
-    const double2 uv = to_d2(u[n]), wv = to_d2(w[n]);
-    const double2 q = cscale(csub(cscale(uv, hsj), sq), inv);
-    const double2 wn = cscale(csub(csub(wv, sw), cmul(gq, q)), inv);
-    u[n] = cvt2<VT>(q);
-    w[n] = cvt2<VT>(wn);
-    acc[0].x += wn.x * wn.x + wn.y * wn.y;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int64_t n = nb + lane + 64 * e;
+      if (n < b1) {
+        const double2 uv = to_d2(u[n]), wv = to_d2(w[n]);
+        const double2 q = cscale(csub(cscale(uv, hsj), sq[e]), inv);
+        const double2 wn = cscale(csub(csub(wv, sw[e]), cmul(gq, q)), inv);
+        u[n] = cvt2<VT>(q);
+        w[n] = cvt2<VT>(wn);
+        acc[0].x += wn.x * wn.x + wn.y * wn.y;
+      }
+    }
   }
   const double2 r = block_sum<1>(acc, sh);
   double2* part = a.part + ((int64_t)slot * a.nch + blockIdx.x) * PSTRIDE;

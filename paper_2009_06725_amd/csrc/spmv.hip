@@ -129,12 +129,24 @@ struct Lane {
   bool pairok0;
 };
 
+// Workgroups are dealt to the 8 XCDs in turn. Within every group of 8 * XRUN
+// consecutive workgroups, XCD x takes the XRUN consecutive row blocks starting at
+// x * XRUN, so that neighbouring rows (whose gathers overlap) share one XCD's L2 while
+// all XCDs stay in the same stretch of rows; a ragged last group keeps its order.
+constexpr int64_t XRUN = 16;
+__device__ __forceinline__ int64_t row_block() {
+  const int64_t b = blockIdx.x, S = 8 * XRUN, g = b / S;
+  if ((g + 1) * S > (int64_t)gridDim.x) return b;
+  const int64_t off = b - g * S;
+  return g * S + (off % 8) * XRUN + off / 8;
+}
+
 __device__ __forceinline__ Lane lane_of(const LaneMap& lm, int64_t nrows) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   Lane L;
   L.li = lane & (lm.W - 1);
   L.p0 = L.li;
-  L.row = ((int64_t)blockIdx.x * 4 + wave) * lm.R + lane / lm.W;
+  L.row = (row_block() * 4 + wave) * lm.R + lane / lm.W;
   L.rowok = L.row < nrows;
   L.pairok0 = L.li < lm.UL;
   return L;
