@@ -568,7 +568,9 @@ __global__ void k_pinit(MeshArgs ma, int D, Batch b, SV<VI> v, VArg z, ITemps<ty
   pt.arr(0)[ki] = cvt2<C>(vp);
   pt.arr(1)[ki] = cvt2<C>(dd);
   pt.arr(3)[ki] = cvt2<C>(dd);
-  if (kp <= 1) {
+  // at w = 0 the Laplacian term j w rho L^-1 v_p vanishes: the block is final here and
+  // the Chebyshev steps skip this system
+  if (kp <= 1 || b.omega[slot] == 0.0) {
     // kp == 0: the Schur block is the pressure mass alone, zhat_p = -mu Mp^-1 v_p
     const double2 xl = kp == 0 ? make_double2(0.0, 0.0) : dd;
     const double wr = b.omega[slot] * ma.rho, im = ma.mu / ma.Mp[vv];
@@ -592,6 +594,7 @@ __global__ void __launch_bounds__(256) k_pstep(MeshArgs ma, int D, Batch b, SV<V
   const int64_t A = idx / G;
   const int p = (int)(idx - A * G);
   const int slot = b.act[p];
+  if (b.omega[slot] == 0.0) return;  // Schur block already final (k_pinit)
   const int64_t ki = idx;  // = A * G + p
   C* rp = pt.arr(0);
   const C* __restrict__ dold = pt.arr((step & 1) ? 1 : 2);
