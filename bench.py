@@ -44,7 +44,7 @@ def parse():
     ap.add_argument("--rtol", type=float, default=4e-12,
                     help="relative residual; 4e-12 keeps the modes within 1e-8 of the reference here")
     ap.add_argument("--restart", type=int, default=220)
-    ap.add_argument("--cheb-vel", type=int, default=10)
+    ap.add_argument("--cheb-vel", type=int, default=12)
     ap.add_argument("--cheb-pres", type=int, default=50)
     ap.add_argument("--cheb-ratio", type=float, default=300.0,
                     help="the polynomials target [lambda_max/ratio, lambda_max] of the Jacobi-scaled blocks")

@@ -220,7 +220,7 @@ typedef struct {
                          true residual much further within one cycle); 0 = only at rtol or m */
 } scvs_solve_opts;
 
-/* Fill `o` with the defaults (rtol 1e-10, m 200, 20000 iterations, degrees 10/50,
+/* Fill `o` with the defaults (rtol 1e-10, m 200, 20000 iterations, degrees 12/50,
  * ratios 300 (velocity) / 1000 (pressure), batch 0, graphs on, FP64, lagged
  * orthogonalization, inner_rtol 1e-5). */
 void scvs_solve_opts_default(scvs_solve_opts* o);
@@ -274,7 +274,7 @@ int scvs_solve_groups(int n, const scvs_solve_group* groups);
  * arguments as scvs_solve, no initial guesses) and returns the fastest in
  * `best` (and its solve time in *best_ms, may be NULL). The candidates vary the
  * restart length (160, 220), the pressure and velocity Chebyshev degrees
- * (30/50, 8/10); every other field, including the precision, the tolerance and
+ * (30/50, 10/12); every other field, including the precision, the tolerance and
  * the orthogonalization, comes from `base` (NULL: the defaults). A candidate
  * counts only if all systems converge. Each candidate is one full solve, so a
  * call costs about 8 solves; the choice is cached in the context per (mesh,

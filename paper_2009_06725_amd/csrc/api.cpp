@@ -322,7 +322,7 @@ void scvs_solve_opts_default(scvs_solve_opts* o) {
   o->rtol = 1e-10;
   o->restart = 200;
   o->max_iters = 20000;
-  o->cheb_vel = 10;
+  o->cheb_vel = 12;
   o->cheb_pres = 50;
   o->cheb_ratio = 300.0;
   o->max_batch = 0;
@@ -406,7 +406,7 @@ int scvs_autotune(scvs_mesh m, int64_t nsys, const double* omega, const double* 
       double pick_ms = -1.0;
       const int ms_[] = {160, 220};
       const int kp_[] = {30, 50};
-      const int kv_[] = {8, 10};
+      const int kv_[] = {10, 12};
       for (int mm : ms_)
         for (int kp : kp_)
           for (int kv : kv_) {

@@ -43,7 +43,7 @@ def test_version_and_errors_without_gpu(lib):
     # null mesh: rejected by validation
     assert lib.scvs_mesh_info(None, None) == -1
     o = scvs.default_opts()
-    assert o.restart == 200 and o.rtol == 1e-10 and o.cheb_vel == 10 and o.cheb_pres == 50
+    assert o.restart == 200 and o.rtol == 1e-10 and o.cheb_vel == 12 and o.cheb_pres == 50
     assert lib.scvs_solve(None, 1, None, None, None, None, None, None, C.byref(o), None) == -1
 
 
