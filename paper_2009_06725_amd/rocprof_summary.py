@@ -47,6 +47,8 @@ def short_name(demangled: str) -> str:
         return {"0": "k_full_apply", "1": "k_full_resid", "2": "k_full_rhs"}.get(mode, "k_full") + ("32" if f32 else "")
     if base in ("k_vstep", "k_vinit"):
         return base + ("32" if f32 else "")
+    if base in ("k_pstep", "k_pinit"):  # <input type, recurrence real type>
+        return base + ("32" if targs.split(",")[-1].strip() == "float" else "")
     if base == "k_dots" and targs.strip() == "1":
         return "k_dots1"
     if base == "k_update" and targs.strip() == "2":
