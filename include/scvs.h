@@ -313,7 +313,8 @@ int scvs_mode_increments(int64_t n, const double* omega, const double* un2, doub
  * out[n][i] = sum_k c_k Re(modes[k][i] exp(j omega_k t_n)), c_k = 1 if
  * omega_k == 0 else 2 (real fields from the one-sided coefficients of
  * Eq. SCVS_bc). omega: host double[nk] (>= 0); modes: device c128[nk][nvals];
- * times: host double[nt]; out: device double[nt][nvals]. nk <= 256. */
+ * times: host double[nt]; out: device double[nt][nvals]. nk <= 256. With nt = 0 or
+ * nvals = 0 nothing is written and modes/out may be NULL. */
 int scvs_synthesize(scvs_ctx ctx, int64_t nk, const double* omega, const void* modes,
                     int64_t nvals, int64_t nt, const double* times, void* out);
 

@@ -503,7 +503,8 @@ int scvs_mode_increments(int64_t n, const double* omega, const double* un2, doub
 int scvs_synthesize(scvs_ctx ctx, int64_t nk, const double* omega, const void* modes, int64_t nvals, int64_t nt,
                     const double* times, void* out) {
   return guarded([&] {
-    SCVS_REQUIRE(ctx && omega && modes && out && (nt == 0 || times), SCVS_E_INVALID, "bad synthesis arguments");
+    SCVS_REQUIRE(ctx && omega && (nt == 0 || times) && ((modes && out) || nt == 0 || nvals == 0), SCVS_E_INVALID,
+                 "bad synthesis arguments");
     SCVS_REQUIRE(nk >= 1 && nk <= 256 && nvals >= 0 && nt >= 0, SCVS_E_INVALID, "bad synthesis sizes");
     for (int64_t k = 0; k < nk; ++k)
       SCVS_REQUIRE(std::isfinite(omega[k]) && omega[k] >= 0.0, SCVS_E_INVALID, "omega must be finite and >= 0");

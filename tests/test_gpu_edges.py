@@ -1,0 +1,139 @@
+"""Edge cases of the GPU path against the oracle, through the C ABI.
+
+* batches wide enough that a row's (system, component) pairs take several
+  passes of a wavefront (more than 63 pairs: 26 systems in 3D, 40 in 2D);
+* ragged batch splits (max_batch not dividing the system count);
+* the largest Krylov dimension (256) and the largest synthesis (256 modes);
+* zero data, empty calls and sizes beyond the limits (clean errors)."""
+import numpy as np
+import pytest
+
+from oracle.solve import case_setup, solve_modes, system_matrix, constrained_dofs, constrained_matrix
+from oracle.synth import synthesize as oracle_synth
+from workloads import cases
+
+from helpers import gpu_dirichlet, gpu_mesh, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2009_06725_amd import scvs
+    return scvs.Context(0)
+
+
+def _wide(which):
+    rng = np.random.default_rng(11)
+    if which == "pipe26":
+        c = cases.pipe_case(h=0.6, length=1.5, n_harm=25)
+        c["inlet_amp"] = rng.standard_normal(26) + 1j * rng.standard_normal(26)
+    else:
+        c = cases.channel_case(nx=16, ny=4, n_harm=39)
+        c["traction"] = (rng.standard_normal((40, 1)) + 1j * rng.standard_normal((40, 1))).astype(np.complex128)
+    c["omega"] = 2 * np.pi * 0.37 * np.arange(len(c["omega"]))
+    return c
+
+
+@pytest.fixture(scope="module", params=["pipe26", "channel40"])
+def wide(request, ctx):
+    print(f"[gpu] wide batch {request.param}", flush=True)
+    c = _wide(request.param)
+    asm, loads, wall, dirn, g = case_setup(c)
+    m = gpu_mesh(ctx, c)
+    u_o, p_o, _, _ = solve_modes(asm, loads, wall, dirn, c["omega"], c["rho"], c["mu"], c["traction"], g)
+    return dict(name=request.param, case=c, asm=asm, wall=wall, dirn=dirn, g=g, m=m, lu=(u_o, p_o))
+
+
+def test_wide_batch_spmv(wide):
+    c, asm, m = wide["case"], wide["asm"], wide["m"]
+    info = m.info
+    ns = len(c["omega"])
+    rng = np.random.default_rng(12)
+    x = rng.standard_normal((ns, info.ndof)) + 1j * rng.standard_normal((ns, info.ndof))
+    yd = torch.zeros((ns, info.ndof), dtype=torch.complex128, device="cuda")
+    m.spmv(c["omega"], torch.from_numpy(x).to("cuda"), yd)
+    y = yd.cpu().numpy()
+    for s in (0, 1, ns // 2, ns - 1):
+        A = system_matrix(asm, float(c["omega"][s]), c["rho"], c["mu"])
+        cidx, _ = constrained_dofs(asm, wide["wall"], wide["dirn"], wide["g"][s])
+        ref = constrained_matrix(A, cidx) @ x[s]
+        assert np.abs(y[s] - ref).max() <= 1e-13 * np.abs(ref).max(), s
+
+
+@pytest.mark.parametrize("precision,max_batch", [(0, 0), (1, 0), (1, 7)])
+def test_wide_and_ragged_batches_match_lu(wide, precision, max_batch):
+    from paper_2009_06725_amd import scvs
+    c, asm, m = wide["case"], wide["asm"], wide["m"]
+    u_o, p_o = wide["lu"]
+    g = gpu_dirichlet(m, c, torch)
+    opts = scvs.default_opts(rtol=1e-13 if precision == 0 else 1e-12, precision=precision, max_batch=max_batch)
+    u, p, rep = m.solve(c["omega"], c["traction"], g, opts=opts)
+    u, p = u.cpu().numpy(), p.cpu().numpy()
+    tol = 1e-10 if precision == 0 else 1e-8
+    for s in range(len(c["omega"])):
+        assert rep[s].status == 0, (s, rep[s].status, rep[s].rel_residual)
+        eu, ep = rel_l2(asm, u[s], u_o[s], p[s], p_o[s])
+        assert eu <= tol and ep <= tol, (s, eu, ep)
+
+
+def test_largest_krylov_dimension(ctx):
+    from paper_2009_06725_amd import scvs
+    c = cases.channel_case(n_harm=2)
+    asm, loads, wall, dirn, g = case_setup(c)
+    u_o, p_o, _, _ = solve_modes(asm, loads, wall, dirn, c["omega"], c["rho"], c["mu"], c["traction"], g)
+    m = gpu_mesh(ctx, c)
+    u, p, rep = m.solve(c["omega"], c["traction"], opts=scvs.default_opts(rtol=1e-13, restart=256, precision=0))
+    u, p = u.cpu().numpy(), p.cpu().numpy()
+    for s in range(len(c["omega"])):
+        assert rep[s].status == 0
+        eu, ep = rel_l2(asm, u[s], u_o[s], p[s], p_o[s])
+        assert eu <= 1e-10 and ep <= 1e-10
+    with pytest.raises(scvs.ScvsError):
+        m.solve(c["omega"], c["traction"], opts=scvs.default_opts(restart=257))
+
+
+def test_zero_data_gives_zero_modes(ctx):
+    from paper_2009_06725_amd import scvs
+    c = cases.pipe_case(h=0.6, length=1.5, n_harm=2)
+    m = gpu_mesh(ctx, c)
+    ns = len(c["omega"])
+    g = torch.zeros((ns, m.info.ndir, 3), dtype=torch.complex128, device="cuda")
+    for precision in (0, 1):
+        u, p, rep = m.solve(c["omega"], c["traction"], g, opts=scvs.default_opts(precision=precision))
+        assert all(r.status == 0 and r.iterations == 0 for r in rep)
+        assert torch.count_nonzero(u).item() == 0 and torch.count_nonzero(p).item() == 0
+
+
+def test_synthesis_limits(ctx):
+    from paper_2009_06725_amd import scvs
+    rng = np.random.default_rng(13)
+    nk, nv, nt = 256, 777, 9
+    modes = rng.standard_normal((nk, nv)) + 1j * rng.standard_normal((nk, nv))
+    om = 2 * np.pi * np.arange(nk) / 0.9
+    t = np.sort(rng.uniform(0, 1.8, nt))
+    md = torch.from_numpy(modes).to("cuda")
+    out = scvs.synthesize(ctx, om, md, t).cpu().numpy()
+    ref = oracle_synth(modes, om, t)
+    assert np.abs(out - ref).max() <= 1e-12 * np.abs(ref).max()
+    empty = scvs.synthesize(ctx, om, md, np.zeros(0))
+    assert tuple(empty.shape) == (0, nv)
+    with pytest.raises(scvs.ScvsError):
+        big = torch.zeros((257, 4), dtype=torch.complex128, device="cuda")
+        scvs.synthesize(ctx, np.arange(257.0), big, t)
+
+
+def test_empty_and_oversized_calls_are_rejected(ctx):
+    from paper_2009_06725_amd import scvs
+    c = cases.channel_case(n_harm=1)
+    m = gpu_mesh(ctx, c)
+    with pytest.raises(scvs.ScvsError):
+        m.solve(np.zeros(0), np.zeros((0, 1), np.complex128))
+    n = 4097
+    x = torch.zeros((n, m.info.ndof), dtype=torch.complex128, device="cuda")
+    with pytest.raises(scvs.ScvsError):
+        m.spmv(np.zeros(n), x, torch.zeros_like(x))
