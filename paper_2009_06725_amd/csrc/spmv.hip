@@ -548,10 +548,11 @@ __global__ void __launch_bounds__(256) k_vstep(MeshArgs ma, Batch b, LaneMap lm,
   }
 }
 
-// Pressure block, first step (elementwise over vertices): r = insc*v_p,
-// d0 = diag(L)^-1 r / theta, x = d0; with one step the Schur block is final:
-// zhat_p = -(mu Mp^-1 v_p + j w rho x). Temps r, d0, d1, x are interleaved like the
-// velocity ones: system si of the active list at vertex A sits at A*G + si.
+// Pressure block, first step (elementwise over vertices): b = insc*v_p and the first
+// Chebyshev iterate x_1 = diag(L)^-1 b / theta; with one step the Schur block is final:
+// zhat_p = -(mu Mp^-1 v_p + j w rho x_1). Temps (b, then rotating iterates) are
+// interleaved like the velocity ones: system si of the active list at vertex A sits at
+// A*G + si.
 template <class VI, class R>
 __global__ void k_pinit(MeshArgs ma, int D, Batch b, SV<VI> v, VArg z, ITemps<typename Prec<R>::C> pt, double ratio,
                         int kp) {
@@ -566,8 +567,7 @@ __global__ void k_pinit(MeshArgs ma, int D, Batch b, SV<VI> v, VArg z, ITemps<ty
   const double theta = 0.5 * ma.lpmax * (1.0 + 1.0 / ratio);
   const double2 dd = cscale(vp, ma.lpdinv[vv] / theta);
   pt.arr(0)[ki] = cvt2<C>(vp);
-  pt.arr(1)[ki] = cvt2<C>(dd);
-  pt.arr(3)[ki] = cvt2<C>(dd);
+  pt.iter(1)[ki] = cvt2<C>(dd);
   // at w = 0 the Laplacian term j w rho L^-1 v_p vanishes: the block is final here and
   // the Chebyshev steps skip this system
   if (kp <= 1 || b.omega[slot] == 0.0) {
@@ -578,8 +578,9 @@ __global__ void k_pinit(MeshArgs ma, int D, Batch b, SV<VI> v, VArg z, ITemps<ty
   }
 }
 
-// Pressure Laplacian Chebyshev step on the assembled L: r -= L d_old; d_new = a d_old +
-// b diag(L)^-1 r; x += d_new; on the last step zhat_p = -(mu Mp^-1 v_p + j w rho x).
+// Pressure Laplacian Chebyshev step i on the assembled L, three-term form:
+// x_{i+1} = x_i + rho_i rho_{i-1} (x_i - x_{i-1}) + (2 rho_i / delta) diag(L)^-1 (b - L x_i)
+// (x_0 = 0); on the last step zhat_p = -(mu Mp^-1 v_p + j w rho x_kp) instead of a store.
 // Lanes do not cooperate here, so threads map linearly onto (vertex, system) pairs: every
 // lane works, and the systems of one vertex sit in adjacent lanes (coalesced gathers).
 template <class VI, class R>
@@ -596,10 +597,7 @@ __global__ void __launch_bounds__(256) k_pstep(MeshArgs ma, int D, Batch b, SV<V
   const int slot = b.act[p];
   if (b.omega[slot] == 0.0) return;  // Schur block already final (k_pinit)
   const int64_t ki = idx;  // = A * G + p
-  C* rp = pt.arr(0);
-  const C* __restrict__ dold = pt.arr((step & 1) ? 1 : 2);
-  C* dnew = pt.arr((step & 1) ? 2 : 1);
-  C* xp = pt.arr(3);
+  const C* __restrict__ xk = pt.iter(step);
   C q = czero<C>();
   const int64_t k0 = ma.lp_ptr[A], k1 = ma.lp_ptr[A + 1];
   int64_t k = k0;
@@ -612,7 +610,7 @@ __global__ void __launch_bounds__(256) k_pstep(MeshArgs ma, int D, Batch b, SV<V
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       l[t] = lval[k + t];
-      dv[t] = dold[(int64_t)u[t] * G + p];
+      dv[t] = xk[(int64_t)u[t] * G + p];
     }
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
@@ -622,29 +620,25 @@ __global__ void __launch_bounds__(256) k_pstep(MeshArgs ma, int D, Batch b, SV<V
   }
   for (; k < k1; ++k) {
     const R l = lval[k];
-    const C dv = dold[(int64_t)ma.lp_col[k] * G + p];
+    const C dv = xk[(int64_t)ma.lp_col[k] * G + p];
     q.x += l * dv.x;
     q.y += l * dv.y;
   }
-  const double rpv = cs.rprev, rc = cs.rcur, delta = 0.5 * ma.lpmax * (1.0 - 1.0 / ratio);
-  const C r0 = rp[ki], dk = dold[ki], x0 = xp[ki];
-  const R ca = (R)(rc * rpv), cb = (R)(2.0 * rc / delta * ma.lpdinv[A]);
-  C rn, dn, xn;
-  rn.x = r0.x - q.x;
-  rn.y = r0.y - q.y;
-  dn.x = ca * dk.x + cb * rn.x;
-  dn.y = ca * dk.y + cb * rn.y;
-  xn.x = x0.x + dn.x;
-  xn.y = x0.y + dn.y;
-  rp[ki] = rn;
-  dnew[ki] = dn;
-  xp[ki] = xn;
-  if (last) {
+  const double delta = 0.5 * ma.lpmax * (1.0 - 1.0 / ratio);
+  const C bv = pt.arr(0)[ki], xv = xk[ki];
+  const C xo = step == 1 ? czero<C>() : pt.iter(step - 1)[ki];
+  const R ca = (R)(cs.rcur * cs.rprev), cb = (R)(2.0 * cs.rcur / delta * ma.lpdinv[A]);
+  C xn;
+  xn.x = xv.x + ca * (xv.x - xo.x) + cb * (bv.x - q.x);
+  xn.y = xv.y + ca * (xv.y - xo.y) + cb * (bv.y - q.y);
+  if (!last) {
+    pt.iter(step + 1)[ki] = xn;
+  } else {
+    // the pressure-mass Schur scaling and the combination stay FP64
     const int64_t DN = D * ma.n2;
     const double sc = in_scale(b, slot);
     const double2 vp = cscale(to_d2(v.at(slot)[DN + A]), sc);
     const double wr = b.omega[slot] * ma.rho, im = ma.mu / ma.Mp[A];
-    // the pressure-mass Schur scaling and the combination stay FP64
     const double2 xd = to_d2(xn);
     z.at(slot)[DN + A] = make_double2(-(im * vp.x - wr * xd.y), -(im * vp.y + wr * xd.x));
   }
@@ -752,17 +746,18 @@ void precond_launch(Profiler* prof, const MeshArgs& ma, const Batch& b, const Pr
   const double pes = pa.mixed ? 8.0 : 16.0, pvs = pa.mixed ? 4.0 : 8.0;  // complex / real temp bytes
   {
     // per system: v_p read, r/d0/x written (and z_p when one step); lpdinv, Mp read
-    ProfScope ps(prof, s, pa.mixed ? "k_pinit32" : "k_pinit", nv * 16.0 + na * nv * (16.0 + 3.0 * pes));
+    ProfScope ps(prof, s, pa.mixed ? "k_pinit32" : "k_pinit", nv * 16.0 + na * nv * (16.0 + 2.0 * pes));
     if (pa.mixed)
       k_pinit<VI, float><<<gp, 256, 0, s>>>(ma, D, b, v, z, ptl32, pa.ratio_p, pa.kp);
     else
       k_pinit<VI, double><<<gp, 256, 0, s>>>(ma, D, b, v, z, ptl, pa.ratio_p, pa.kp);
   }
-  // L values and columns, row pointers, diag, Mp; per system d_old gathered,
-  // r read+written, d_new written, x read+written
-  const double pbytes = (double)ma.nnzl * (4.0 + pvs) + nv * 24.0 + na * nv * pes * 6.0;
+  // L values and columns, row pointers, diag, Mp; per system x_i gathered (read once),
+  // b and x_{i-1} read, x_{i+1} written (last step: v_p read and z_p written instead)
+  const double pbytes = (double)ma.nnzl * (4.0 + pvs) + nv * 24.0 + na * nv * pes * 4.0;
   for (int i = 1; i < pa.kp; ++i) {
-    ProfScope ps(prof, s, pa.mixed ? "k_pstep32" : "k_pstep", pbytes + (i == pa.kp - 1 ? na * nv * 32.0 : 0.0));
+    ProfScope ps(prof, s, pa.mixed ? "k_pstep32" : "k_pstep",
+                 pbytes + (i == pa.kp - 1 ? na * nv * (32.0 - pes) : 0.0));
     if (pa.mixed)
       k_pstep<VI, float><<<nbp, 256, 0, s>>>(ma, D, b, v, z, ptl32, pa.ratio_p, cheb_step(pa.ratio_p, i), i,
                                              i == pa.kp - 1);
