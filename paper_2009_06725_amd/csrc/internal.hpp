@@ -98,6 +98,7 @@ struct Profiler {
     std::string name;
     hipEvent_t a, b;
     double bytes;
+    int count;  // launches inside the span
   };
   bool on = false;
   std::vector<hipEvent_t> pool;
@@ -112,10 +113,12 @@ struct Profiler {
   }
   ~Profiler();
 };
-// Brackets one launch with events when profiling is on.
+// Brackets one launch with events when profiling is on; a scope around `count`
+// back-to-back launches of one kernel (no host work between them) times them as one
+// span, so its per-launch average includes the gaps between those launches.
 class ProfScope {
  public:
-  ProfScope(Profiler* p, hipStream_t s, const char* name, double bytes);
+  ProfScope(Profiler* p, hipStream_t s, const char* name, double bytes, int count = 1);
   ~ProfScope();
 
  private:

@@ -755,15 +755,18 @@ void precond_launch(Profiler* prof, const MeshArgs& ma, const Batch& b, const Pr
   // L values and columns, row pointers, diag, Mp; per system x_i gathered (read once),
   // b and x_{i-1} read, x_{i+1} written (last step: v_p read and z_p written instead)
   const double pbytes = (double)ma.nnzl * (4.0 + pvs) + nv * 24.0 + na * nv * pes * 4.0;
-  for (int i = 1; i < pa.kp; ++i) {
-    ProfScope ps(prof, s, pa.mixed ? "k_pstep32" : "k_pstep",
-                 pbytes + (i == pa.kp - 1 ? na * nv * (32.0 - pes) : 0.0));
-    if (pa.mixed)
-      k_pstep<VI, float><<<nbp, 256, 0, s>>>(ma, D, b, v, z, ptl32, pa.ratio_p, cheb_step(pa.ratio_p, i), i,
-                                             i == pa.kp - 1);
-    else
-      k_pstep<VI, double><<<nbp, 256, 0, s>>>(ma, D, b, v, z, ptl, pa.ratio_p, cheb_step(pa.ratio_p, i), i,
-                                              i == pa.kp - 1);
+  if (pa.kp > 1) {
+    // the steps run back to back: one timed span for all of them
+    ProfScope ps(prof, s, pa.mixed ? "k_pstep32" : "k_pstep", pbytes * (pa.kp - 1) + na * nv * (32.0 - pes),
+                 pa.kp - 1);
+    for (int i = 1; i < pa.kp; ++i) {
+      if (pa.mixed)
+        k_pstep<VI, float><<<nbp, 256, 0, s>>>(ma, D, b, v, z, ptl32, pa.ratio_p, cheb_step(pa.ratio_p, i), i,
+                                               i == pa.kp - 1);
+      else
+        k_pstep<VI, double><<<nbp, 256, 0, s>>>(ma, D, b, v, z, ptl, pa.ratio_p, cheb_step(pa.ratio_p, i), i,
+                                                i == pa.kp - 1);
+    }
   }
   const double es = pa.mixed ? 8.0 : 16.0, vs = pa.mixed ? 4.0 : 8.0;  // complex / real element bytes
   // interleaved temporaries inside the slot pool's temp block (4 * D*n2 per slot, contiguous)
@@ -782,14 +785,16 @@ void precond_launch(Profiler* prof, const MeshArgs& ma, const Batch& b, const Pr
   }
   // S2 col/Ks/M, rowptr/dmask/Kd/Md; per system x_k (gathered, read once), b, x_{k-1} read, x_{k+1} written
   const double vbytes = (double)ma.nnz * (4.0 + 2.0 * vs) + n2 * (12.0 + 2.0 * vs) + na * 4.0 * DN * es;
-  for (int i = 1; i < pa.kv; ++i) {
-    ProfScope ps(prof, s, pa.mixed ? "k_vstep32" : "k_vstep", vbytes);
-    if (pa.mixed)
-      k_vstep<D, float><<<nbu, 256, 0, s>>>(ma, b, lm, pa.z32, it32, pa.ratio, cheb_step(pa.ratio, i), i,
-                                            i == pa.kv - 1, (float2*)zil);
-    else
-      k_vstep<D, double><<<nbu, 256, 0, s>>>(ma, b, lm, z, it64, pa.ratio, cheb_step(pa.ratio, i), i,
-                                             i == pa.kv - 1, (double2*)zil);
+  if (pa.kv > 1) {
+    ProfScope ps(prof, s, pa.mixed ? "k_vstep32" : "k_vstep", vbytes * (pa.kv - 1), pa.kv - 1);
+    for (int i = 1; i < pa.kv; ++i) {
+      if (pa.mixed)
+        k_vstep<D, float><<<nbu, 256, 0, s>>>(ma, b, lm, pa.z32, it32, pa.ratio, cheb_step(pa.ratio, i), i,
+                                              i == pa.kv - 1, (float2*)zil);
+      else
+        k_vstep<D, double><<<nbu, 256, 0, s>>>(ma, b, lm, z, it64, pa.ratio, cheb_step(pa.ratio, i), i,
+                                               i == pa.kv - 1, (double2*)zil);
+    }
   }
   launch_check(s);
 }

@@ -25,7 +25,7 @@ void Profiler::resolve() {
       stats.push_back({pd.name, Stat{}});
       it = stats.end() - 1;
     }
-    it->second.launches += 1;
+    it->second.launches += pd.count;
     it->second.ms += ms;
     it->second.bytes += pd.bytes;
   }
@@ -41,14 +41,14 @@ Profiler::~Profiler() {
   for (auto e : pool) (void)hipEventDestroy(e);
 }
 
-ProfScope::ProfScope(Profiler* p, hipStream_t s, const char* name, double bytes) : p_(p), s_(s) {
+ProfScope::ProfScope(Profiler* p, hipStream_t s, const char* name, double bytes, int count) : p_(p), s_(s) {
   if (!p_ || !p_->on || capturing(s)) {
     p_ = nullptr;
     return;
   }
   hipEvent_t a = p_->get(), b = p_->get();
   SCVS_HIP(hipEventRecord(a, s));
-  p_->pending.push_back({name, a, b, bytes});
+  p_->pending.push_back({name, a, b, bytes, count});
   idx_ = p_->pending.size() - 1;
 }
 
