@@ -476,15 +476,15 @@ int scvs_select_modes(int64_t nk, const double* omega, const double* hn2, const 
     for (int64_t k = 0; k < nk; ++k) ord[k] = k;
     if (!consecutive)
       std::stable_sort(ord.begin(), ord.end(), [&](int64_t a, int64_t b) { return share(a) > share(b); });
-    // e_M^2 = (truncated traction energy) + (truncated Dirichlet energy), both relative
-    double rest = 0.0;
-    for (int64_t k = 0; k < nk; ++k) rest += share(k);
-    int64_t n = 0;
-    while (n < nk && !(rest < eps * eps)) rest -= share(ord[n++]);
-    if (n == 0) ++n, rest -= share(ord[0]);  // at least one mode
+    // e_M^2 = (truncated traction energy) + (truncated Dirichlet energy), both relative;
+    // tail[i] = sum of the shares of ord[i..nk), summed directly (no cancellation)
+    std::vector<double> tail(nk + 1, 0.0);
+    for (int64_t i = nk - 1; i >= 0; --i) tail[i] = tail[i + 1] + share(ord[i]);
+    int64_t n = 1;  // at least one mode
+    while (n < nk && !(tail[n] < eps * eps)) ++n;
     for (int64_t k = 0; k < nk; ++k) order[k] = ord[k];
     *count = n;
-    if (err) *err = std::sqrt(std::max(rest, 0.0));
+    if (err) *err = std::sqrt(tail[n]);
   });
 }
 

@@ -99,3 +99,26 @@ def test_facet_and_mode_norms_closed_forms():
     uu, pp = mode_l2_sq(a3, lin(a3["node_xyz"]), np.full(pm.nv, 1 - 2j))
     assert uu == pytest.approx(np.sum(vol * (-vs / 20 + es / 5)), rel=1e-12)
     assert pp == pytest.approx(5 * vol.sum(), rel=1e-12)  # lumped P1 mass sums to the volume; |1-2j|^2 = 5
+
+
+def test_select_modes_edge_cases(lib):
+    """eps = 0 keeps every mode; eps >= 1 keeps one; all-zero data keeps one with zero error;
+    the increments of a single mode and of zero modes; bad arguments are rejected."""
+    from paper_2009_06725_amd import scvs
+    om = 2 * np.pi * np.arange(5)
+    hn2 = np.zeros(5)
+    gn2 = np.array([4.0, 1.0, 0.5, 0.25, 0.125])
+    order, n, err = scvs.select_modes(om, hn2, gn2, 0.0)
+    assert n == 5 and err == 0.0
+    order, n, err = scvs.select_modes(om, hn2, gn2, 1.0)
+    w = np.where(om == 0, 1.0, 2.0)
+    assert n == 1 and err == pytest.approx(np.sqrt(np.sum(w[1:] * gn2[1:]) / np.sum(w * gn2)), rel=1e-14)
+    order, n, err = scvs.select_modes(om, np.zeros(5), np.zeros(5), 1e-3, False)
+    assert n == 1 and err == 0.0 and sorted(order.tolist()) == list(range(5))
+    inc = scvs.mode_increments(om[:1], np.array([2.5]))
+    assert inc[0] == pytest.approx(1.0)
+    assert np.all(scvs.mode_increments(om, np.zeros(5)) == 0.0)
+    with pytest.raises(scvs.ScvsError):
+        scvs.select_modes(om, hn2, gn2, -1.0)
+    with pytest.raises(scvs.ScvsError):
+        scvs.select_modes(om, hn2, -gn2, 0.1)
