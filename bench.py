@@ -58,7 +58,7 @@ def parse():
                     help="penalized variant: continuity block -(penalty/mu) Mp (0: the method itself)")
     ap.add_argument("--windkessel", type=str, default=None, metavar="RP,C,RD",
                     help="three-element lumped model on the outlet instead of a traction-free outlet")
-    ap.add_argument("--inner-rtol", type=float, default=1e-5,
+    ap.add_argument("--inner-rtol", type=float, default=3e-5,
                     help="mixed precision: end a cycle once its own residual fell by this factor")
     ap.add_argument("--orth", type=int, choices=[0, 1], default=1,
                     help="0: two-pass classical Gram-Schmidt, 1: lagged second pass (DCGS2)")

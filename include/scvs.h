@@ -222,7 +222,7 @@ typedef struct {
 
 /* Fill `o` with the defaults (rtol 1e-10, m 200, 20000 iterations, degrees 12/50,
  * ratios 300 (velocity) / 1000 (pressure), batch 0, graphs on, FP64, lagged
- * orthogonalization, inner_rtol 1e-5). */
+ * orthogonalization, inner_rtol 3e-5). */
 void scvs_solve_opts_default(scvs_solve_opts* o);
 
 typedef struct {

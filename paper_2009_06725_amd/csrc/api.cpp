@@ -332,7 +332,7 @@ void scvs_solve_opts_default(scvs_solve_opts* o) {
   o->orth = 1;
   o->cheb_ratio_pres = 1000.0;
   o->penalty = 0.0;
-  o->inner_rtol = 1e-5;
+  o->inner_rtol = 3e-5;
 }
 
 int scvs_solve(scvs_mesh m, int64_t nsys, const double* omega, const double* traction, const void* g,
