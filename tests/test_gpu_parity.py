@@ -268,7 +268,7 @@ def test_autotune_caches_and_solves(ctx):
     t0 = time.perf_counter()
     best, ms = m.autotune(c["omega"], c["traction"], g, base=base)
     t1 = time.perf_counter()
-    assert best.restart in (160, 220) and best.cheb_pres in (30, 50) and best.cheb_vel in (8, 10)
+    assert best.restart in (160, 220) and best.cheb_pres in (30, 50) and best.cheb_vel in (10, 12)
     assert best.rtol == base.rtol and best.precision == base.precision and ms > 0
     best2, ms2 = m.autotune(c["omega"], c["traction"], g, base=base)
     t2 = time.perf_counter()
