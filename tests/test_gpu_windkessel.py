@@ -184,3 +184,24 @@ def test_warm_start_refine_with_lumped_outlets(ctx):
     ws.refine(c["omega"], c["traction"], g, x0)
     err = (torch.linalg.vector_norm(x0 - X, dim=1) / torch.linalg.vector_norm(X, dim=1)).max().item()
     assert err < 1e-9, err
+
+
+def test_solve_groups_with_a_lumped_mesh():
+    """A mesh with lumped outlets solved concurrently with an ordinary one gives the same
+    modes, bit for bit, as the separate solves."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2009_06725_amd import scvs
+    cs = [_pipe(), cases.channel_case(n_harm=2)]
+    ctxs = [scvs.Context(0, stream=torch.cuda.Stream()) for _ in cs]
+    ms = [gpu_mesh(cx, c) for cx, c in zip(ctxs, cs)]
+    ms[0].set_windkessel(cs[0]["wk"])
+    gs = [gpu_dirichlet(m, c, torch) for m, c in zip(ms, cs)]
+    opts = scvs.default_opts(rtol=1e-11)
+    single = [m.solve(c["omega"], c["traction"], g, opts=opts) for m, c, g in zip(ms, cs, gs)]
+    grouped = scvs.solve_groups([dict(mesh=m, omega=c["omega"], traction=c["traction"], g=g, opts=opts)
+                                 for m, c, g in zip(ms, cs, gs)])
+    for (u1, p1, r1), (u2, p2, r2) in zip(single, grouped):
+        assert all(r.status == 0 for r in r2)
+        assert [r.iterations for r in r1] == [r.iterations for r in r2]
+        assert torch.equal(u1, u2) and torch.equal(p1, p2)
