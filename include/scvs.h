@@ -200,12 +200,15 @@ typedef struct {
   int32_t use_graph;  /* replay the steps of each cycle, in chunks of 30, from captured hipGraphs */
   int32_t verbose;    /* print per-cycle residuals to stderr */
   int32_t precision;  /* 0: all FP64. 1: mixed -- inside each restart cycle the operator
-                         product and the velocity-block polynomial run on FP32 matrix copies
-                         and FP32 vectors with FP32 accumulation; the true residual f - A x
-                         recomputed at every restart (iterative refinement), the Arnoldi
-                         orthogonalization, Givens/least-squares, the pressure Schur block
-                         and the solution update stay FP64. 2: as 1, with the Krylov basis
-                         stored as FP32 pairs (its arithmetic stays FP64; needs orth = 1) */
+                         product, the velocity-block polynomial and the pressure-Laplacian
+                         recurrence run on FP32 matrix copies and FP32 vectors with FP32
+                         accumulation; the true residual f - A x recomputed at every restart
+                         (iterative refinement), the Arnoldi orthogonalization,
+                         Givens/least-squares, the pressure-mass Schur scaling and the
+                         solution update stay FP64. 2: as 1, with the Krylov basis stored as
+                         FP32 pairs (its arithmetic stays FP64; needs orth = 1). 3: as 1, with
+                         the operator product in FP64 matrix values and accumulation on the
+                         FP32 preconditioned vector */
   int32_t orth;       /* 0: classical Gram-Schmidt, second pass when the first loses more than
                          30% of the norm (three passes over the basis per step). 1: the second
                          pass of each vector lagged into the next step's single reduction
