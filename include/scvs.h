@@ -206,9 +206,7 @@ typedef struct {
                          (iterative refinement), the Arnoldi orthogonalization,
                          Givens/least-squares, the pressure-mass Schur scaling and the
                          solution update stay FP64. 2: as 1, with the Krylov basis stored as
-                         FP32 pairs (its arithmetic stays FP64; needs orth = 1). 3: as 1, with
-                         the operator product in FP64 matrix values and accumulation on the
-                         FP32 preconditioned vector */
+                         FP32 pairs (its arithmetic stays FP64; needs orth = 1) */
   int32_t orth;       /* 0: classical Gram-Schmidt, second pass when the first loses more than
                          30% of the norm (three passes over the basis per step). 1: the second
                          pass of each vector lagged into the next step's single reduction
