@@ -322,8 +322,9 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"fp64": "c128", "mixed": "c64 operator+velocity precond / c128 refinement",
-                  "mixed32": "c64 operator+velocity precond+Krylov basis storage / c128 arithmetic+refinement"
+        "dtype": {"fp64": "c128", "mixed": "c64 operator and preconditioner polynomials / c128 Krylov basis, Schur scaling, refinement",
+                  "mixed32": "c64 operator, preconditioner polynomials and Krylov basis storage / c128 arithmetic, "
+                             "Schur scaling, refinement"
                   }[args.precision],
         "data": "synthetic",
         "config": {"workload": f"pipe R=1 L=10, {mesh.nc} curved P2/P1 tets, {ns} modes (16 harmonics + mean)",
