@@ -34,7 +34,7 @@ HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_pipe200k.json")
 
 
-def parse():
+def parse(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1)
@@ -77,7 +77,17 @@ def parse():
     ap.add_argument("--verbose", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run plain 1 GiB device copies (for scaling rocprofv3 byte counters)")
-    return ap.parse_args()
+    return ap.parse_args(argv)
+
+
+def solver_opts(args):
+    """The solver options of the timed steps (also used by the full-size parity test)."""
+    from paper_2009_06725_amd import scvs
+    return scvs.default_opts(rtol=args.rtol, restart=args.restart, cheb_vel=args.cheb_vel,
+                             cheb_pres=args.cheb_pres, cheb_ratio=args.cheb_ratio,
+                             cheb_ratio_pres=args.cheb_ratio_pres, verbose=1 if args.verbose else 0,
+                             precision={"fp64": 0, "mixed": 1, "mixed32": 2}[args.precision], orth=args.orth,
+                             inner_rtol=args.inner_rtol, penalty=args.penalty)
 
 
 def log(msg):
@@ -251,11 +261,7 @@ def main():
     times = np.arange(args.ntimes) * case["period"] / args.ntimes
     ut = torch.empty((args.ntimes, info.n2 * 3), dtype=torch.float64, device="cuda")
     pt = torch.empty((args.ntimes, info.nv), dtype=torch.float64, device="cuda")
-    opts = scvs.default_opts(rtol=args.rtol, restart=args.restart, cheb_vel=args.cheb_vel,
-                             cheb_pres=args.cheb_pres, cheb_ratio=args.cheb_ratio,
-                             cheb_ratio_pres=args.cheb_ratio_pres, verbose=1 if args.verbose else 0,
-                             precision={"fp64": 0, "mixed": 1, "mixed32": 2}[args.precision], orth=args.orth,
-                             inner_rtol=args.inner_rtol, penalty=args.penalty)
+    opts = solver_opts(args)
     log(f"n2={info.n2} ndof={info.ndof} nnz_s2={info.nnz_s2} ingest+assembly {t_ingest:.2f}s")
     tuned = None
     if args.autotune:

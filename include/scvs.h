@@ -105,8 +105,12 @@ int scvs_mesh_info(scvs_mesh mesh, scvs_mesh_info_t* info);
 
 /* Curved boundary (section 3.1: inserted boundary nodes are projected onto the
  * curved surface). `n` edges given by their two vertex indices (any order)
- * and the position of their midside node (host, double[n][dim]). Must be
- * called before scvs_assemble. Errors: SCVS_E_INVALID if a pair is not an edge. */
+ * and the position of their midside node (host, double[n][dim]). Call order:
+ * scvs_mesh_set_midside, then scvs_mesh_set_bc, then scvs_assemble. Moving
+ * midside nodes after scvs_mesh_set_bc clears the boundary conditions (their
+ * traction loads and lumped outlets were integrated on the old facets) and the
+ * assembly, so both must be done again.
+ * Errors: SCVS_E_INVALID if a pair is not an edge. */
 int scvs_mesh_set_midside(scvs_mesh mesh, int64_t n, const int32_t* edge_vertices,
                           const double* xyz);
 
@@ -116,7 +120,7 @@ int scvs_mesh_set_midside(scvs_mesh mesh, int64_t n, const int32_t* edge_vertice
 int scvs_mesh_set_bc(scvs_mesh mesh, int n, const int32_t* tags, const int32_t* kinds);
 
 /* Lumped (Windkessel) outlets, as on the outflow faces of the Glenn case
- * (section 3.6, which names the model without its form). Each listed tag must
+ * (section 3.5, which names the model without its form). Each listed tag must
  * already be a TRACTION tag; its pressure becomes P = Z(w) Q + P0, where
  * Q = int u.n over the tag (outward flow), P0 is the tag's traction coefficient
  * of the system, and Z(w) = rp + rd / (1 + j w rd c) is the three-element model

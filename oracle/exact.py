@@ -35,6 +35,16 @@ def channel_pressure(x, P, L):
     return P * (1.0 - np.asarray(x) / L) + 0j
 
 
+def channel_velocity_dy(y, omega, P, mu, rho, L, H):
+    """d u_x / d y of channel_velocity (the only nonzero velocity gradient)."""
+    y = np.asarray(y, np.float64)
+    if omega == 0.0:
+        return -P / (mu * L) * y + 0j
+    nu = mu / rho
+    lam = np.sqrt(1j * omega * H * H / nu)
+    return 1j * P / (rho * L * omega) * (lam / H) * np.sinh(lam * y / H) / np.cosh(lam)
+
+
 def pipe_velocity(r, omega, Q, mu, rho, R):
     r = np.asarray(r, np.float64)
     if omega == 0.0:
@@ -83,6 +93,45 @@ def l2_error(mesh, asm, u, exact_fn, pressure=None, exact_p=None):
     return num / den, ep
 
 
+def h1_error(mesh, asm, u, grad_fn):
+    """Relative H1-seminorm error of one complex velocity mode against a
+    closed-form gradient grad_fn(x [m,d]) -> [m,d(component),d(direction)],
+    by the same degree-5 rule as l2_error (Eq. int_error bounds the L2 part;
+    the gradient error of quadratic elements is one order lower)."""
+    d = mesh.dim
+    lam, wq = gm_rule(d, 2)
+    absdet, grad, phi = cell_geometry(mesh, asm["edges"], asm["c2n"], lam)
+    X = asm["node_xyz"][asm["c2n"]]
+    xq = np.einsum("qa,ead->eqd", phi, X)
+    gh = np.einsum("eqak,eac->eqck", grad, u[asm["c2n"]])  # d u_c / d x_k
+    ge = grad_fn(xq.reshape(-1, d)).reshape(gh.shape)
+    w = (absdet * wq[None, :])[..., None, None]
+    return np.sqrt(np.sum(w * np.abs(ge - gh) ** 2)) / np.sqrt(np.sum(w * np.abs(ge) ** 2))
+
+
+def divergence_l2(mesh, asm, u):
+    """||div u_h||_{L2(Omega)} of one complex velocity mode (the continuity
+    equation of section 2.1 holds only weakly, against the linear pressure
+    space, so the pointwise divergence of the quadratic field is a
+    discretization error)."""
+    d = mesh.dim
+    lam, wq = gm_rule(d, 2)
+    absdet, grad, _ = cell_geometry(mesh, asm["edges"], asm["c2n"], lam)
+    div = np.einsum("eqac,eac->eq", grad, u[asm["c2n"]])
+    return float(np.sqrt(np.sum(absdet * wq[None, :] * np.abs(div) ** 2)))
+
+
+def weak_divergence(asm, u):
+    """G^T u per vertex: the discrete continuity residual of a velocity mode
+    (with the Dirichlet values included), which the method makes zero."""
+    rp, col = asm["C21"]
+    rows = np.repeat(np.arange(asm["n2"]), np.diff(rp))
+    out = np.zeros(asm["nv"], np.complex128)
+    for c in range(asm["dim"]):
+        np.add.at(out, col, asm["G"][c] * u[rows, c])
+    return out
+
+
 def time_l2_error(mesh, asm, umodes, omegas, exact_modes, t):
     """Eq. total_error at time t: relative L2 error of the reconstructed field.
 
@@ -104,5 +153,5 @@ def time_l2_error(mesh, asm, umodes, omegas, exact_modes, t):
     return np.sqrt(np.sum(ww * (ue - uh) ** 2)) / np.sqrt(np.sum(ww * ue**2))
 
 
-__all__ = ["channel_velocity", "channel_pressure", "pipe_velocity", "pipe_pressure",
-           "l2_error", "time_l2_error", "p2_basis"]
+__all__ = ["channel_velocity", "channel_velocity_dy", "channel_pressure", "pipe_velocity", "pipe_pressure",
+           "l2_error", "h1_error", "divergence_l2", "weak_divergence", "time_l2_error", "p2_basis"]

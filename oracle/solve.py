@@ -18,7 +18,7 @@ Section 2.3, Eqs. linear_sys_def / LS_construction, with these readings:
   ease the saddle point): with epsilon > 0 the continuity block becomes
   -(epsilon / mu) Mp, Mp the lumped P1 pressure mass, i.e. the discrete
   constraint G^T u = (epsilon / mu) Mp p; epsilon = 0 is the method itself;
-* lumped (Windkessel) outlets (section 3.6 puts one on each outflow face of
+* lumped (Windkessel) outlets (section 3.5 puts one on each outflow face of
   the Glenn case without giving its form): a traction tag may carry a
   three-element model, proximal resistance Rp in series with a capacitance C
   parallel to a distal resistance Rd. Its pressure is P = Z(w) Q + P0 with the

@@ -7,6 +7,8 @@
 #include <thread>
 #include <vector>
 
+#include <atomic>
+
 #include "internal.hpp"
 
 using scvs::DBuf;
@@ -58,6 +60,14 @@ scvs_solve_opts checked_opts(const scvs_solve_opts* opts) {
                    std::isfinite(o.penalty),
                SCVS_E_INVALID, "bad solve options");
   return o;
+}
+
+// Every option the autotuner does not choose (and that changes the solve), as a key.
+std::string untuned_key(const scvs_solve_opts& o) {
+  char buf[512];
+  snprintf(buf, sizeof buf, "%.17g|%d|%.17g|%d|%d|%d|%d|%.17g|%.17g|%.17g", o.rtol, o.max_iters, o.cheb_ratio,
+           o.max_batch, o.use_graph, o.precision, o.orth, o.cheb_ratio_pres, o.penalty, o.inner_rtol);
+  return buf;
 }
 
 }  // namespace
@@ -130,6 +140,8 @@ int scvs_mesh_create(scvs_ctx ctx, int dim, int64_t nv, const double* xyz, int64
     hipStream_t s = ctx->stream;
     auto m = std::make_unique<scvs_mesh_s>();
     m->ctx = ctx;
+    static std::atomic<uint64_t> next_uid{1};
+    m->uid = next_uid++;
     m->dim = dim;
     m->nvl = nvl;
     m->nn = nvl * (nvl + 1) / 2;
@@ -151,6 +163,8 @@ int scvs_mesh_destroy(scvs_mesh mesh) {
     if (mesh) {
       use_device(mesh->ctx);
       SCVS_HIP(hipStreamSynchronize(mesh->ctx->stream));
+      auto& t = mesh->ctx->tuned;
+      for (auto it = t.begin(); it != t.end();) it = std::get<0>(it->first) == mesh->uid ? t.erase(it) : std::next(it);
     }
     delete mesh;
   });
@@ -186,6 +200,11 @@ int scvs_mesh_set_midside(scvs_mesh m, int64_t n, const int32_t* ev, const doubl
     use_device(m->ctx);
     scvs::mesh_set_midside(m, n, ev, xyz, m->ctx->stream);
     m->assembled = false;
+    // the traction loads and lumped-outlet vectors were integrated on the old facets:
+    // boundary conditions must be set again
+    if (m->bc_set) scvs::mesh_windkessel(m, 0, nullptr, nullptr, nullptr, nullptr, m->ctx->stream);
+    m->bc_set = false;
+    m->generation++;
   });
 }
 
@@ -395,15 +414,14 @@ int scvs_autotune(scvs_mesh m, int64_t nsys, const double* omega, const double* 
     const scvs_solve_opts b = checked_opts(base);
     for (int64_t k = 0; k < nsys; ++k) SCVS_REQUIRE(std::isfinite(omega[k]), SCVS_E_INVALID, "non-finite omega");
     use_device(m->ctx);
-    const auto key = std::make_tuple((const void*)m, m->generation, nsys, (int)b.precision, b.rtol);
+    const auto key = std::make_tuple(m->uid, m->generation, nsys, untuned_key(b));
     auto hit = m->ctx->tuned.find(key);
     if (hit == m->ctx->tuned.end()) {
       scvs::DBuf<double2> u, p;
       u.alloc((size_t)nsys * m->n2 * m->dim);
       p.alloc((size_t)nsys * m->nv);
       std::vector<scvs_report> rep(nsys);
-      scvs_solve_opts pick = b;
-      double pick_ms = -1.0;
+      scvs_ctx_s::Tuned pick{b.restart, b.cheb_vel, b.cheb_pres, -1.0};
       const int ms_[] = {160, 220};
       const int kp_[] = {30, 50};
       const int kv_[] = {10, 12};
@@ -423,15 +441,16 @@ int scvs_autotune(scvs_mesh m, int64_t nsys, const double* omega, const double* 
             if (b.verbose)
               fprintf(stderr, "[scvs] autotune m %d Chebyshev %d/%d: %.1f ms%s\n", c.restart, kv, kp, ms,
                       ok ? "" : " (not converged)");
-            if (ok && (pick_ms < 0.0 || ms < pick_ms)) {
-              pick = c;
-              pick_ms = ms;
-            }
+            if (ok && (pick.ms < 0.0 || ms < pick.ms)) pick = {c.restart, kv, kp, ms};
           }
-      SCVS_REQUIRE(pick_ms >= 0.0, SCVS_E_STATE, "no candidate configuration converged");
-      hit = m->ctx->tuned.emplace(key, scvs_ctx_s::Tuned{pick, pick_ms}).first;
+      SCVS_REQUIRE(pick.ms >= 0.0, SCVS_E_STATE, "no candidate configuration converged");
+      hit = m->ctx->tuned.emplace(key, pick).first;
     }
-    *best = hit->second.opts;
+    // the tuned fields over the caller's own options
+    *best = b;
+    best->restart = hit->second.restart;
+    best->cheb_vel = hit->second.cheb_vel;
+    best->cheb_pres = hit->second.cheb_pres;
     if (best_ms) *best_ms = hit->second.ms;
   });
 }

@@ -133,18 +133,20 @@ struct scvs_ctx_s {
   hipStream_t stream = nullptr;   // caller's stream: all work runs here
   hipStream_t capture = nullptr;  // private stream used only to record graphs
   scvs::Profiler prof;
-  // autotuner results: (mesh, assembly generation, systems, precision, rtol) -> options, ms
+  // autotuner results, keyed by (mesh id, operator generation, systems, every caller option
+  // that the tuner does not choose); only the tuned fields are kept
   struct Tuned {
-    scvs_solve_opts opts;
+    int restart, cheb_vel, cheb_pres;
     double ms;
   };
-  std::map<std::tuple<const void*, uint64_t, int64_t, int, double>, Tuned> tuned;
+  std::map<std::tuple<uint64_t, uint64_t, int64_t, std::string>, Tuned> tuned;
 };
 
 constexpr int SCVS_MMAX = 256;  // largest Krylov dimension per cycle
 
 struct scvs_mesh_s {
   scvs_ctx ctx = nullptr;
+  uint64_t uid = 0;  // unique per mesh object in this process (never reused, unlike addresses)
   int dim = 0, nvl = 0, nn = 0;  // dim, vertices per cell, quadratic nodes per cell
   int64_t nv = 0, nc = 0, nf = 0, ne = 0, n2 = 0;
   int64_t nnz = 0, nnz21 = 0, nnzv = 0;  // S2 slots, vertex-column slots, slots of vertex rows

@@ -1211,7 +1211,9 @@ int solve_systems(scvs_mesh m, int64_t nsys, const double* omega, const double* 
       }
     }
     std::vector<int> iters(nb, 0), cycles(nb, 0), done(nb, 0);
-    std::map<int, std::pair<hipGraph_t, hipGraphExec_t>> graphs;
+    // captured graphs keyed by (kind: 0 steps of all active systems, 1 steps of the
+    // still-running subset, 2 cycle end; systems in the launch; chunk index)
+    std::map<std::tuple<int, int, int>, std::pair<hipGraph_t, hipGraphExec_t>> graphs;
     const int chunk = std::min(mk, 30);
     std::vector<int> act_prev;
     for (;;) {
@@ -1245,7 +1247,7 @@ int solve_systems(scvs_mesh m, int64_t nsys, const double* omega, const double* 
       // the cycle runs in chunks of steps; between chunks the host drops the systems that
       // stopped, and the cycle ends as soon as none is running
       const bool use_graph = o->use_graph && !m->ctx->prof.on;
-      auto launch = [&](int key, const std::function<void(hipStream_t)>& body) {
+      auto launch = [&](std::tuple<int, int, int> key, const std::function<void(hipStream_t)>& body) {
         if (!use_graph) {
           body(s);
           return;
@@ -1280,8 +1282,8 @@ int solve_systems(scvs_mesh m, int64_t nsys, const double* omega, const double* 
         Batch br = bc;
         br.nact = (int)run.size();
         br.act = all ? P.act.p : P.act_run.p;
-        const int key = ((all ? 0 : 1) * 4096 + br.nact) * 1024 + j0 / chunk;
-        launch(key, [&](hipStream_t st) { cycle_steps(m, P, br, pa, ndof, j0, j1, lagged, st); });
+        launch(std::make_tuple(all ? 0 : 1, br.nact, j0 / chunk),
+               [&](hipStream_t st) { cycle_steps(m, P, br, pa, ndof, j0, j1, lagged, st); });
         const bool prof_on = m->ctx->prof.on;
         if (j1 == mk && !prof_on) break;
         k_stops<<<(br.nact + 63) / 64, 64, 0, s>>>(P.st, br.act, br.nact, P.stops);
@@ -1320,7 +1322,8 @@ int solve_systems(scvs_mesh m, int64_t nsys, const double* omega, const double* 
         m->ctx->prof.correct("k_combine", -vb * (mk - jend[k]));
         if (lagged && jend[k] < mk) m->ctx->prof.correct("k_lag_dots", -vb * (mk + 1));
       }
-      launch(-1 - na, [&](hipStream_t st) { cycle_end(m, P, bc, pa, ndof, o->rtol, o->inner_rtol, lagged, st); });
+      launch(std::make_tuple(2, na, 0),
+             [&](hipStream_t st) { cycle_end(m, P, bc, pa, ndof, o->rtol, o->inner_rtol, lagged, st); });
       for (int k : act) cycles[k]++;
     }
     for (auto& kv : graphs) {

@@ -134,13 +134,34 @@ def _host(a, dtype):
     return a, a.ctypes.data_as(C.c_void_p)
 
 
-def _dev(t, dtype_name: str):
-    """Device pointer of a contiguous torch tensor of the expected dtype."""
+E_INVALID = -1
+
+
+def _dev(t, dtype_name: str, numel: int | None = None, device: int | None = None, what: str = "tensor"):
+    """Device pointer of a contiguous torch tensor of the expected dtype, holding
+    exactly `numel` elements (when given) on HIP device `device` (when given).
+    The C ABI carries no buffer sizes, so these checks are what keeps a kernel
+    from reading or writing past a caller's buffer."""
     import torch
-    assert isinstance(t, torch.Tensor) and t.is_cuda, "expected a device tensor"
-    assert t.is_contiguous(), "expected a contiguous tensor"
-    assert str(t.dtype) == dtype_name, f"expected {dtype_name}, got {t.dtype}"
+    if not (isinstance(t, torch.Tensor) and t.is_cuda):
+        raise ScvsError(E_INVALID, f"{what}: expected a device tensor")
+    if not t.is_contiguous():
+        raise ScvsError(E_INVALID, f"{what}: expected a contiguous tensor")
+    if str(t.dtype) != dtype_name:
+        raise ScvsError(E_INVALID, f"{what}: expected {dtype_name}, got {t.dtype}")
+    if numel is not None and t.numel() != numel:
+        raise ScvsError(E_INVALID, f"{what}: expected {numel} elements, got {t.numel()}")
+    if device is not None and t.device.index != device:
+        raise ScvsError(E_INVALID, f"{what}: tensor is on device {t.device.index}, the context on {device}")
     return C.c_void_p(t.data_ptr())
+
+
+def _traction(i, ns: int, traction):
+    """Host c128 [ns][ntraction] traction coefficients of ns systems."""
+    tr = np.asarray(traction, np.complex128)
+    if tr.size != ns * i.ntraction:
+        raise ScvsError(E_INVALID, f"traction: expected {ns}x{i.ntraction} values, got {tr.size}")
+    return _host(tr.reshape(ns, i.ntraction).view(np.float64) if tr.size else np.zeros(1), np.float64)
 
 
 def default_opts(**kw) -> SolveOpts:
@@ -260,15 +281,22 @@ class Mesh:
         _check(lib().scvs_mesh_export(self.h, which, out.ctypes.data_as(C.c_void_p)))
         return out[: int(np.prod(shape))].reshape(shape)
 
+    def _g(self, i, ns, g):
+        return _dev(g, "torch.complex128", ns * i.ndir * i.dim, self.ctx.device, "g") if g is not None else None
+
     def spmv(self, omega, x, y):
+        i = self.info
         om, po = _host(omega, np.float64)
-        _check(lib().scvs_spmv(self.h, om.size, po, _dev(x, "torch.complex128"), _dev(y, "torch.complex128")))
+        n = om.size * i.ndof
+        _check(lib().scvs_spmv(self.h, om.size, po, _dev(x, "torch.complex128", n, self.ctx.device, "x"),
+                               _dev(y, "torch.complex128", n, self.ctx.device, "y")))
 
     def rhs(self, omega, traction, g, f):
+        i = self.info
         om, po = _host(omega, np.float64)
-        tr, pt = _host(np.asarray(traction, np.complex128).view(np.float64), np.float64)
-        pg = _dev(g, "torch.complex128") if g is not None else None
-        _check(lib().scvs_rhs(self.h, om.size, po, pt, pg, _dev(f, "torch.complex128")))
+        tr, pt = _traction(i, om.size, traction)
+        _check(lib().scvs_rhs(self.h, om.size, po, pt, self._g(i, om.size, g),
+                              _dev(f, "torch.complex128", om.size * i.ndof, self.ctx.device, "f")))
 
     def solve(self, omega, traction, g=None, x0=None, u=None, p=None, opts: SolveOpts | None = None):
         """Solve all systems; returns (u [nsys,n2,d], p [nsys,nv], list of Report)."""
@@ -276,43 +304,41 @@ class Mesh:
         i = self.info
         om, po = _host(omega, np.float64)
         ns = om.size
-        tr = np.asarray(traction, np.complex128)
-        if i.ntraction and tr.size == ns * i.ntraction:
-            tr = tr.reshape(ns, i.ntraction)
-        tr, pt = _host(tr.view(np.float64), np.float64)
+        tr, pt = _traction(i, ns, traction)
         dev = torch.device("cuda", self.ctx.device)
         if u is None:
             u = torch.empty((ns, i.n2, i.dim), dtype=torch.complex128, device=dev)
         if p is None:
             p = torch.empty((ns, i.nv), dtype=torch.complex128, device=dev)
-        pg = _dev(g, "torch.complex128") if g is not None else None
-        px = _dev(x0, "torch.complex128") if x0 is not None else None
+        d = self.ctx.device
+        pg = self._g(i, ns, g)
+        px = _dev(x0, "torch.complex128", ns * i.ndof, d, "x0") if x0 is not None else None
         reps = (Report * ns)()
         o = opts if opts is not None else default_opts()
-        _check(lib().scvs_solve(self.h, ns, po, pt, pg, px, _dev(u, "torch.complex128"),
-                                _dev(p, "torch.complex128"), C.byref(o), reps))
+        _check(lib().scvs_solve(self.h, ns, po, pt, pg, px, _dev(u, "torch.complex128", ns * i.n2 * i.dim, d, "u"),
+                                _dev(p, "torch.complex128", ns * i.nv, d, "p"), C.byref(o), reps))
         return u, p, list(reps)
 
     def boundary_norms(self, omega, traction, g=None):
         """Per system (traction L2(Gamma) norm^2, Dirichlet-data L2(Gamma) norm^2)."""
         i = self.info
         ns = np.asarray(omega).size
-        tr = np.asarray(traction, np.complex128)
-        if i.ntraction and tr.size == ns * i.ntraction:
-            tr = tr.reshape(ns, i.ntraction)
-        tr, pt = _host(tr.view(np.float64), np.float64)
+        tr, pt = _traction(i, ns, traction)
         hn2 = np.zeros(ns)
         gn2 = np.zeros(ns)
-        _check(lib().scvs_boundary_norms(self.h, ns, pt, _dev(g, "torch.complex128") if g is not None else None,
+        _check(lib().scvs_boundary_norms(self.h, ns, pt, self._g(i, ns, g),
                                          hn2.ctypes.data_as(C.c_void_p), gn2.ctypes.data_as(C.c_void_p)))
         return hn2, gn2
 
     def mode_norms(self, u, p):
         """Per solved mode (u^H (I x M) u, p^H Mp p)."""
+        i = self.info
         ns = u.shape[0]
         un2 = np.zeros(ns)
         pn2 = np.zeros(ns)
-        _check(lib().scvs_mode_norms(self.h, ns, _dev(u, "torch.complex128"), _dev(p, "torch.complex128"),
+        d = self.ctx.device
+        _check(lib().scvs_mode_norms(self.h, ns, _dev(u, "torch.complex128", ns * i.n2 * i.dim, d, "u"),
+                                     _dev(p, "torch.complex128", ns * i.nv, d, "p"),
                                      un2.ctypes.data_as(C.c_void_p), pn2.ctypes.data_as(C.c_void_p)))
         return un2, pn2
 
@@ -321,11 +347,8 @@ class Mesh:
         i = self.info
         om, po = _host(omega, np.float64)
         ns = om.size
-        tr = np.asarray(traction, np.complex128)
-        if i.ntraction and tr.size == ns * i.ntraction:
-            tr = tr.reshape(ns, i.ntraction)
-        tr, pt = _host(tr.view(np.float64), np.float64)
-        pg = _dev(g, "torch.complex128") if g is not None else None
+        tr, pt = _traction(i, ns, traction)
+        pg = self._g(i, ns, g)
         best = SolveOpts()
         ms = C.c_double()
         b = base if base is not None else default_opts()
@@ -367,11 +390,9 @@ def solve_groups(groups):
         i = m.info
         om, po = _host(gr["omega"], np.float64)
         ns = om.size
-        tr = np.asarray(gr["traction"], np.complex128)
-        if i.ntraction and tr.size == ns * i.ntraction:
-            tr = tr.reshape(ns, i.ntraction)
-        tr, pt = _host(tr.view(np.float64), np.float64)
+        tr, pt = _traction(i, ns, gr["traction"])
         dev = torch.device("cuda", m.ctx.device)
+        d = m.ctx.device
         u = gr.get("u")
         p = gr.get("p")
         if u is None:
@@ -383,9 +404,10 @@ def solve_groups(groups):
         g = gr.get("g")
         x0 = gr.get("x0")
         arr[k] = SolveGroup(m.h.value if hasattr(m.h, "value") else m.h, ns, po, pt,
-                            _dev(g, "torch.complex128") if g is not None else None,
-                            _dev(x0, "torch.complex128") if x0 is not None else None,
-                            _dev(u, "torch.complex128"), _dev(p, "torch.complex128"),
+                            m._g(i, ns, g),
+                            _dev(x0, "torch.complex128", ns * i.ndof, d, "x0") if x0 is not None else None,
+                            _dev(u, "torch.complex128", ns * i.n2 * i.dim, d, "u"),
+                            _dev(p, "torch.complex128", ns * i.nv, d, "p"),
                             C.cast(C.pointer(o), C.c_void_p), C.cast(reps, C.c_void_p))
         keep += [om, tr, o, reps]
         out.append((u, p, reps))
@@ -401,11 +423,13 @@ def synthesize(ctx: Context, omega, modes, times, out=None):
     om, po = _host(omega, np.float64)
     tm, pt = _host(times, np.float64)
     nk = om.size
+    if nk == 0 or modes.numel() % nk:
+        raise ScvsError(E_INVALID, f"modes: {modes.numel()} values do not split into {nk} modes")
     nvals = modes.numel() // nk
     if out is None:
         out = torch.empty((tm.size, nvals), dtype=torch.float64, device=modes.device)
-    _check(lib().scvs_synthesize(ctx.h, nk, po, _dev(modes, "torch.complex128"), nvals, tm.size, pt,
-                                 _dev(out, "torch.float64")))
+    _check(lib().scvs_synthesize(ctx.h, nk, po, _dev(modes, "torch.complex128", nk * nvals, ctx.device, "modes"),
+                                 nvals, tm.size, pt, _dev(out, "torch.float64", tm.size * nvals, ctx.device, "out")))
     return out
 
 
@@ -425,8 +449,8 @@ class WarmStart:
         self.mesh = mesh
         om, po = _host(omega, np.float64)
         h = C.c_void_p()
-        _check(lib().scvs_ws_create(mesh.h, om.size, po, _dev(snaps, "torch.complex128"), rank, width, layers,
-                                    seed, C.byref(h)))
+        snp = _dev(snaps, "torch.complex128", om.size * mesh.info.ndof, mesh.ctx.device, "snaps")
+        _check(lib().scvs_ws_create(mesh.h, om.size, po, snp, rank, width, layers, seed, C.byref(h)))
         self.h, self.rank, self.nsnap = h, rank, om.size
 
     def train(self, epochs: int, lr: float = 1e-3) -> float:
@@ -441,15 +465,20 @@ class WarmStart:
         if out is None:
             out = torch.empty((om.size, self.mesh.info.ndof), dtype=torch.complex128,
                               device=torch.device("cuda", self.mesh.ctx.device))
-        _check(lib().scvs_ws_predict(self.h, om.size, po, pa, _dev(out, "torch.complex128")))
+        if a.size != 2 * om.size:
+            raise ScvsError(E_INVALID, f"amp: expected {om.size} values, got {a.size // 2}")
+        _check(lib().scvs_ws_predict(self.h, om.size, po, pa, _dev(out, "torch.complex128",
+                                                                    om.size * self.mesh.info.ndof,
+                                                                    self.mesh.ctx.device, "out")))
         return out
 
     def refine(self, omega, traction, g, x0):
         """In-place minimal-residual correction of x0 over x0 + span(POD basis)."""
         om, po = _host(omega, np.float64)
-        tr, ptr = _host(np.asarray(traction, np.complex128).reshape(om.size, -1).view(np.float64), np.float64)
-        _check(lib().scvs_ws_refine(self.h, om.size, po, ptr if tr.size else None,
-                                    None if g is None else _dev(g, "torch.complex128"), _dev(x0, "torch.complex128")))
+        i = self.mesh.info
+        tr, ptr = _traction(i, om.size, traction)
+        _check(lib().scvs_ws_refine(self.h, om.size, po, ptr if i.ntraction else None, self.mesh._g(i, om.size, g),
+                                    _dev(x0, "torch.complex128", om.size * i.ndof, self.mesh.ctx.device, "x0")))
         return x0
 
     def nparam(self) -> int:
@@ -468,7 +497,7 @@ class WarmStart:
             import torch
             out = torch.empty((self.rank, self.mesh.info.ndof), dtype=torch.complex128,
                               device=torch.device("cuda", self.mesh.ctx.device))
-            _check(lib().scvs_ws_export(self.h, which, _dev(out, "torch.complex128")))
+            _check(lib().scvs_ws_export(self.h, which, _dev(out, "torch.complex128", out.numel())))
             return out
         else:
             raise ValueError(which)

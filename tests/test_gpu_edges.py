@@ -137,3 +137,50 @@ def test_empty_and_oversized_calls_are_rejected(ctx):
     x = torch.zeros((n, m.info.ndof), dtype=torch.complex128, device="cuda")
     with pytest.raises(scvs.ScvsError):
         m.spmv(np.zeros(n), x, torch.zeros_like(x))
+
+
+def test_wrong_buffer_sizes_are_rejected(ctx):
+    """The C ABI carries no buffer sizes: the binding checks every device buffer
+    against the mesh before the call (a short output would be written past)."""
+    from paper_2009_06725_amd import scvs
+    c = cases.pipe_case(h=0.6, length=1.5, n_harm=1)
+    m = gpu_mesh(ctx, c)
+    g = gpu_dirichlet(m, c, torch)
+    i = m.info
+    ns = len(c["omega"])
+    short_u = torch.zeros((ns, i.n2 - 1, 3), dtype=torch.complex128, device="cuda")
+    with pytest.raises(scvs.ScvsError):
+        m.solve(c["omega"], c["traction"], g, u=short_u)
+    with pytest.raises(scvs.ScvsError):
+        m.solve(c["omega"], c["traction"], g[:, :-1].contiguous())
+    with pytest.raises(scvs.ScvsError):
+        m.solve(c["omega"], c["traction"], g, x0=torch.zeros((ns, i.ndof - 1), dtype=torch.complex128,
+                                                               device="cuda"))
+    with pytest.raises(scvs.ScvsError):
+        m.solve(c["omega"], np.zeros((ns, i.ntraction + 1), np.complex128), g)
+    with pytest.raises(scvs.ScvsError):
+        m.spmv(c["omega"], torch.zeros((ns, i.ndof), dtype=torch.complex64, device="cuda"),
+               torch.zeros((ns, i.ndof), dtype=torch.complex128, device="cuda"))
+
+
+def test_midside_after_bc_needs_new_bc(ctx):
+    """Moving midside nodes after the boundary conditions clears them (their loads
+    were integrated on the old facets): a solve is refused until they are set again,
+    and then matches a mesh set up in the documented order."""
+    from paper_2009_06725_amd import scvs
+    c = cases.pipe_case(h=0.6, length=1.5, n_harm=1)
+    mesh = c["mesh"]
+    m = scvs.Mesh(ctx, mesh.dim, mesh.xyz, mesh.cells, mesh.bfaces, mesh.btags)
+    m.set_bc(c["bc"])
+    m.set_midside(mesh.curved_edges, mesh.curved_xyz)
+    with pytest.raises(scvs.ScvsError):
+        m.assemble(c["rho"], c["mu"])
+        m.solve(c["omega"], c["traction"], None)
+    m.set_bc(c["bc"])
+    m.assemble(c["rho"], c["mu"])
+    ref = gpu_mesh(ctx, c)
+    g = gpu_dirichlet(ref, c, torch)
+    o = scvs.default_opts(rtol=1e-12)
+    u1, p1, _ = m.solve(c["omega"], c["traction"], g, opts=o)
+    u2, p2, _ = ref.solve(c["omega"], c["traction"], g, opts=o)
+    assert torch.equal(u1, u2) and torch.equal(p1, p2)

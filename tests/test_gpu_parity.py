@@ -287,6 +287,24 @@ def test_autotune_caches_and_solves(ctx):
     assert time.perf_counter() - t3 > 5 * (t2 - t1)
 
 
+def test_autotune_keeps_caller_options(ctx):
+    """Only the tuned fields (restart, degrees) come from the cache: a call whose
+    options differ elsewhere (here the penalty) is tuned as a separate entry and
+    gets its own options back, and a repeated call returns them unchanged."""
+    from paper_2009_06725_amd import scvs
+    c = cases.channel_case(n_harm=1)
+    m = gpu_mesh(ctx, c)
+    g = gpu_dirichlet(m, c, torch)
+    b0 = scvs.default_opts(rtol=1e-10)
+    b1 = scvs.default_opts(rtol=1e-10, penalty=1e-3, inner_rtol=1e-4)
+    best0, _ = m.autotune(c["omega"], c["traction"], g, base=b0)
+    best1, _ = m.autotune(c["omega"], c["traction"], g, base=b1)
+    best0b, _ = m.autotune(c["omega"], c["traction"], g, base=b0)
+    assert best0.penalty == 0.0 and best1.penalty == 1e-3 and best1.inner_rtol == 1e-4
+    assert best0b.penalty == 0.0 and best0b.inner_rtol == b0.inner_rtol
+    assert (best0b.restart, best0b.cheb_vel, best0b.cheb_pres) == (best0.restart, best0.cheb_vel, best0.cheb_pres)
+
+
 def test_solve_groups_equal_single_solves():
     """Several meshes solved concurrently (one context and stream each) give the
     same modes, bit for bit, as their separate solves."""

@@ -77,6 +77,31 @@ def test_adam_reduces_loss():
     assert mse_loss_grad(P, x, t)[0] < 0.2 * l0
 
 
+def test_adam_hand_values():
+    """Two Adam steps on one scalar weight and one scalar bias, worked out by
+    hand (Kingma and Ba 2015, with the bias corrections 1 - b1^t, 1 - b2^t and
+    eps added to the square root of the corrected second moment):
+      step 1, g = 0.5:   m = 0.05, v = 0.00025, m^ = 0.5, v^ = 0.25,
+                         w -= 0.1 * 0.5 / (0.5 + 1e-8)           -> -0.0999999980
+      step 2, g = -0.25: m = 0.045 - 0.025 = 0.02, m^ = 0.02 / 0.19,
+                         v = 0.00024975 + 0.0000625 = 0.00031225, v^ = v / 0.001999,
+                         w -= 0.1 * 0.1052632 / (0.3952246 + 1e-8) = 0.0266335
+    The bias of a tiny gradient g = 1e-9 moves by lr * g / (|g| + eps) =
+    lr / 11 on step 1, which fixes where eps enters."""
+    W = np.zeros((1, 1), np.float32)
+    b = np.zeros(1, np.float32)
+    st = [[(np.zeros((1, 1)), np.zeros((1, 1))), (np.zeros(1), np.zeros(1))]]
+    P = [(W, b)]
+    P = adam_step(P, [(np.full((1, 1), 0.5), np.full(1, 1e-9))], st, 0.1, 1)
+    assert abs(P[0][0][0, 0] - (-0.1 * 0.5 / (0.5 + 1e-8))) < 1e-8
+    assert abs(P[0][1][0] - (-0.1 / 11.0)) < 1e-8
+    w1 = float(P[0][0][0, 0])
+    P = adam_step(P, [(np.full((1, 1), -0.25), np.full(1, 0.0))], st, 0.1, 2)
+    step2 = 0.1 * (0.02 / 0.19) / (np.sqrt(0.00031225 / 0.001999) + 1e-8)
+    assert abs(step2 - 0.0266335) < 1e-6
+    assert abs(P[0][0][0, 0] - (w1 - step2)) < 1e-7
+
+
 def test_pod_matches_svd():
     rng = np.random.default_rng(3)
     X = rng.standard_normal((200, 12)) + 1j * rng.standard_normal((200, 12))
