@@ -106,49 +106,120 @@ __global__ void k_facet_l2(const int32_t* __restrict__ fnodes, int64_t nf, const
   out_area[f] = area;
 }
 
-// Block partial sums of u^H (I_d (x) M) u and p^H Mp p for system blockIdx.y.
+// Block partial sums of u^H (I_d (x) M) u and p^H Mp p for every system. A wavefront
+// walks one row of the quadratic pattern at a time, loading each (col, M) slot once for
+// all systems: its lanes are (system, component) pairs p = s*D + c (UL = 64/D*D pairs per
+// pass, further passes when the batch has more). Pair lane p accumulates
+// Re(conj(u_s[A][c]) (M u_s^c)_A) over its rows; each block then sums its waves and the
+// components of a system in a fixed order into part_u[s][block]. The pressure part is a
+// plain per-vertex sum per system. Block partials are reduced in block order by
+// k_sum_parts, so the norms are bit-reproducible.
+constexpr int NB_L2 = 256;  // blocks (partials per system)
 template <int D>
 __global__ void __launch_bounds__(256) k_mode_l2(const int64_t* __restrict__ rowptr, const int32_t* __restrict__ col,
                                                  const double* __restrict__ M, const double* __restrict__ Mp,
                                                  int64_t n2, int64_t nv, const double2* __restrict__ u, int64_t ust,
-                                                 const double2* __restrict__ p, int64_t pst,
+                                                 const double2* __restrict__ p, int64_t pst, int nsys,
                                                  double* __restrict__ part_u, double* __restrict__ part_p) {
-  __shared__ double shu[256], shp[256];
-  const int s = blockIdx.y;
-  const double2* us = u + (int64_t)s * ust;
-  const double2* ps = p + (int64_t)s * pst;
-  double au = 0.0, ap = 0.0;
-  for (int64_t A = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; A < n2; A += (int64_t)gridDim.x * blockDim.x) {
-#pragma unroll
-    for (int c = 0; c < D; ++c) {
+  __shared__ double sh[256];
+  constexpr int UL = (64 / D) * D;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t nw = (int64_t)gridDim.x * 4, w0 = (int64_t)blockIdx.x * 4 + wave;
+  const int npair = nsys * D;
+  for (int base = 0; base < npair; base += UL) {
+    const int pr = base + lane;
+    const bool ok = lane < UL && pr < npair;
+    const int si = ok ? pr / D : 0, c = ok ? pr % D : 0;
+    const double2* __restrict__ us = u + (int64_t)si * ust;
+    double acc = 0.0;
+    for (int64_t A = w0; A < n2; A += nw) {
+      const int64_t j0 = rowptr[A], j1 = rowptr[A + 1];
       double2 mu = make_double2(0.0, 0.0);
-      for (int64_t j = rowptr[A]; j < rowptr[A + 1]; ++j) {
-        const double2 v = us[(int64_t)col[j] * D + c];
-        mu.x += M[j] * v.x;
-        mu.y += M[j] * v.y;
+      for (int64_t jb = j0; jb < j1; jb += 64) {
+        const int n = (int)min((int64_t)64, j1 - jb);
+        int32_t mc = 0;
+        double mv = 0.0;
+        if (lane < n) {
+          mc = col[jb + lane];
+          mv = M[jb + lane];
+        }
+        for (int t = 0; t < n; ++t) {
+          const int32_t B = __shfl(mc, t, 64);
+          const double w = __shfl(mv, t, 64);
+          if (ok) {
+            const double2 v = us[(int64_t)B * D + c];
+            mu.x += w * v.x;
+            mu.y += w * v.y;
+          }
+        }
       }
-      const double2 ua = us[A * D + c];
-      au += ua.x * mu.x + ua.y * mu.y;  // Re(conj(u_A) (M u)_A)
+      if (ok) {
+        const double2 ua = us[A * D + c];
+        acc += ua.x * mu.x + ua.y * mu.y;
+      }
     }
-    if (A < nv) {
-      const double2 pa = ps[A];
-      ap += Mp[A] * (pa.x * pa.x + pa.y * pa.y);
-    }
-  }
-  shu[threadIdx.x] = au;
-  shp[threadIdx.x] = ap;
-  __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
-    if (threadIdx.x < o) {
-      shu[threadIdx.x] += shu[threadIdx.x + o];
-      shp[threadIdx.x] += shp[threadIdx.x + o];
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    const int nsp = min(UL, npair - base) / D;  // systems in this pass
+    if (threadIdx.x < nsp) {
+      double t = 0.0;
+      for (int w = 0; w < 4; ++w)
+        for (int cc = 0; cc < D; ++cc) t += sh[w * 64 + threadIdx.x * D + cc];
+      part_u[(int64_t)(base / D + threadIdx.x) * gridDim.x + blockIdx.x] = t;
     }
     __syncthreads();
   }
-  if (threadIdx.x == 0) {
-    part_u[(int64_t)s * gridDim.x + blockIdx.x] = shu[0];
-    part_p[(int64_t)s * gridDim.x + blockIdx.x] = shp[0];
+  for (int si = 0; si < nsys; ++si) {
+    const double2* __restrict__ ps = p + (int64_t)si * pst;
+    double ap = 0.0;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < nv; v += (int64_t)gridDim.x * blockDim.x) {
+      const double2 pa = ps[v];
+      ap += Mp[v] * (pa.x * pa.x + pa.y * pa.y);
+    }
+    sh[threadIdx.x] = ap;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+      if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) part_p[(int64_t)si * gridDim.x + blockIdx.x] = sh[0];
+    __syncthreads();
   }
+}
+
+// out[s] = sum of part[s][0..nb) in block order, for s < n.
+__global__ void k_sum_parts(const double* __restrict__ part, int nb, int n, double* __restrict__ out) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n) return;
+  double t = 0.0;
+  for (int b = 0; b < nb; ++b) t += part[(int64_t)s * nb + b];
+  out[s] = t;
+}
+
+// The norms of nsys systems with all partials and sums in `work` (2*nsys*NB_L2 + 2*nsys
+// doubles on the device); un2/pn2 are host outputs.
+void mode_norms_into(scvs_mesh m, int64_t nsys, const void* u, const void* p, double* work, double* un2,
+                     double* pn2) {
+  hipStream_t s = m->ctx->stream;
+  const int D = m->dim;
+  double* pu = work;
+  double* pp = work + nsys * NB_L2;
+  double* su = work + 2 * nsys * NB_L2;
+  double* sp = su + nsys;
+  const unsigned nb = NB_L2;
+  if (D == 2)
+    k_mode_l2<2><<<nb, 256, 0, s>>>(m->rowptr, m->col, m->M, m->Mp, m->n2, m->nv, (const double2*)u, m->n2 * D,
+                                    (const double2*)p, m->nv, (int)nsys, pu, pp);
+  else
+    k_mode_l2<3><<<nb, 256, 0, s>>>(m->rowptr, m->col, m->M, m->Mp, m->n2, m->nv, (const double2*)u, m->n2 * D,
+                                    (const double2*)p, m->nv, (int)nsys, pu, pp);
+  const unsigned ns = (unsigned)((nsys + 63) / 64);
+  k_sum_parts<<<ns, 64, 0, s>>>(pu, NB_L2, (int)nsys, su);
+  k_sum_parts<<<ns, 64, 0, s>>>(pp, NB_L2, (int)nsys, sp);
+  launch_check(s);
+  SCVS_HIP(hipMemcpyAsync(un2, su, sizeof(double) * nsys, hipMemcpyDeviceToHost, s));
+  SCVS_HIP(hipMemcpyAsync(pn2, sp, sizeof(double) * nsys, hipMemcpyDeviceToHost, s));
+  SCVS_HIP(hipStreamSynchronize(s));
 }
 
 }  // namespace
@@ -212,32 +283,9 @@ void boundary_norms(scvs_mesh m, int64_t nsys, const double* traction, const voi
 }
 
 void mode_norms(scvs_mesh m, int64_t nsys, const void* u, const void* p, double* un2, double* pn2) {
-  hipStream_t s = m->ctx->stream;
-  const int D = m->dim;
-  const unsigned nb = 256;
-  DBuf<double> pu, pp;
-  pu.alloc((size_t)nsys * nb);
-  pp.alloc((size_t)nsys * nb);
-  const dim3 gr(nb, (unsigned)nsys);
-  if (D == 2)
-    k_mode_l2<2><<<gr, 256, 0, s>>>(m->rowptr, m->col, m->M, m->Mp, m->n2, m->nv, (const double2*)u, m->n2 * D,
-                                    (const double2*)p, m->nv, pu, pp);
-  else
-    k_mode_l2<3><<<gr, 256, 0, s>>>(m->rowptr, m->col, m->M, m->Mp, m->n2, m->nv, (const double2*)u, m->n2 * D,
-                                    (const double2*)p, m->nv, pu, pp);
-  launch_check(s);
-  std::vector<double> hu((size_t)nsys * nb), hp((size_t)nsys * nb);
-  download(hu.data(), pu.p, hu.size(), s);
-  download(hp.data(), pp.p, hp.size(), s);
-  for (int64_t k = 0; k < nsys; ++k) {
-    double a = 0.0, b = 0.0;
-    for (unsigned i = 0; i < nb; ++i) {
-      a += hu[(size_t)k * nb + i];
-      b += hp[(size_t)k * nb + i];
-    }
-    un2[k] = a;
-    pn2[k] = b;
-  }
+  DBuf<double> work;
+  work.alloc((size_t)nsys * (2 * NB_L2 + 2));
+  mode_norms_into(m, nsys, u, p, work.p, un2, pn2);
 }
 
 }  // namespace scvs
