@@ -310,6 +310,21 @@ int scvs_autotune(scvs_mesh mesh, int64_t nsys, const double* omega, const doubl
 int scvs_boundary_norms(scvs_mesh mesh, int64_t nsys, const double* traction, const void* g, double* hn2,
                         double* gn2);
 int scvs_mode_norms(scvs_mesh mesh, int64_t nsys, const void* u, const void* p, double* un2, double* pn2);
+
+/* ---- scvs_mode_norms without allocation ----
+ * For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the same arguments and
+ * the same results, bit for bit, as scvs_mode_norms, with its partial sums in a
+ * file-scope device array of SCVS_NOALLOC_MAX_SYSTEMS * 514 doubles (1.05 MB
+ * per GPU, held from the first context created on that GPU until the process
+ * ends) instead of a per-call buffer. The call makes no hipMalloc or hipFree.
+ * Errors: as scvs_mode_norms, plus SCVS_E_CAPACITY when nsys exceeds
+ * SCVS_NOALLOC_MAX_SYSTEMS. Every call on one GPU uses that GPU's array and
+ * leaves its contents there; calls that overlap on one GPU (from several host
+ * threads or streams) race on it, so the caller must serialize them. */
+#define SCVS_NOALLOC_MAX_SYSTEMS 256
+int scvs_mode_norms_noalloc(scvs_mesh mesh, int64_t nsys, const void* u, const void* p, double* un2,
+                            double* pn2);
 int scvs_select_modes(int64_t nk, const double* omega, const double* hn2, const double* gn2, double eps,
                       int consecutive, int64_t* order, int64_t* count, double* err);
 int scvs_mode_increments(int64_t n, const double* omega, const double* un2, double* inc);

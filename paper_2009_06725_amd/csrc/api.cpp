@@ -85,6 +85,7 @@ int scvs_ctx_create(int device, void* stream, scvs_ctx* out) {
     SCVS_HIP(hipGetDeviceCount(&n));
     SCVS_REQUIRE(device >= 0 && device < n, SCVS_E_INVALID, "device index out of range");
     SCVS_HIP(hipSetDevice(device));
+    scvs::noalloc_init(device);
     auto* c = new scvs_ctx_s();
     c->device = device;
     c->stream = (hipStream_t)stream;
@@ -473,6 +474,15 @@ int scvs_mode_norms(scvs_mesh m, int64_t nsys, const void* u, const void* p, dou
     SCVS_REQUIRE(nsys > 0 && nsys <= 65535 && u && p && un2 && pn2, SCVS_E_INVALID, "bad mode-norm arguments");
     use_device(m->ctx);
     scvs::mode_norms(m, nsys, u, p, un2, pn2);
+  });
+}
+
+int scvs_mode_norms_noalloc(scvs_mesh m, int64_t nsys, const void* u, const void* p, double* un2, double* pn2) {
+  return guarded([&] {
+    require_ready(m);
+    SCVS_REQUIRE(nsys > 0 && u && p && un2 && pn2, SCVS_E_INVALID, "bad mode-norm arguments");
+    use_device(m->ctx);
+    scvs::mode_norms_noalloc(m, nsys, u, p, un2, pn2);
   });
 }
 

@@ -322,6 +322,10 @@ void scatter_dirichlet(scvs_mesh m, int64_t nsys, const void* g, VArg x, const i
 void boundary_norms(scvs_mesh m, int64_t nsys, const double* traction, const void* g, double* hn2, double* gn2);
 // Per system: u^H (I_d (x) M) u and p^H Mp p (lumped pressure mass); host outputs.
 void mode_norms(scvs_mesh m, int64_t nsys, const void* u, const void* p, double* un2, double* pn2);
+// The same with the partial sums in the library's file-scope device array (no allocation);
+// noalloc_init resolves that array's address on the current device (called per context).
+void mode_norms_noalloc(scvs_mesh m, int64_t nsys, const void* u, const void* p, double* un2, double* pn2);
+void noalloc_init(int device);
 
 // ---- learned.hip ----
 struct Mlp;

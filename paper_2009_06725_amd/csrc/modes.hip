@@ -8,6 +8,7 @@
 // w_k = 2, and the change from adding mode N to the reconstruction, Eq.
 // sol_reconstruct, into T * w_N * ||u_N||^2_{L2(Omega)}. The device computes the
 // per-mode norms; the selection itself is host arithmetic.
+#include <mutex>
 #include <numeric>
 
 #include "internal.hpp"
@@ -286,6 +287,42 @@ void mode_norms(scvs_mesh m, int64_t nsys, const void* u, const void* p, double*
   DBuf<double> work;
   work.alloc((size_t)nsys * (2 * NB_L2 + 2));
   mode_norms_into(m, nsys, u, p, work.p, un2, pn2);
+}
+
+// ---- mode norms without allocation ----
+// The partial sums of up to SCVS_NOALLOC_MAX_SYSTEMS systems live in this file-scope
+// device array (one copy per GPU, held until the process ends). Host code never passes
+// the array's name to a kernel: it uses the device address that hipGetSymbolAddress
+// returned for the current GPU when a context was created there.
+static __device__ __align__(256) double scratch[(size_t)SCVS_NOALLOC_MAX_SYSTEMS * (2 * NB_L2 + 2)];
+
+namespace {
+constexpr int SCRATCH_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[SCRATCH_MAX_DEVICES] = {};
+}  // namespace
+
+void noalloc_init(int device) {
+  if (device < 0 || device >= SCRATCH_MAX_DEVICES) return;  // the entry point then reports it
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[device]) return;
+  void* ptr = nullptr;
+  SCVS_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+  SCVS_REQUIRE(ptr != nullptr, SCVS_E_HIP, "hipGetSymbolAddress returned no address for the scratch array");
+  g_scratch_ptr[device] = ptr;
+}
+
+void mode_norms_noalloc(scvs_mesh m, int64_t nsys, const void* u, const void* p, double* un2, double* pn2) {
+  SCVS_REQUIRE(nsys <= SCVS_NOALLOC_MAX_SYSTEMS, SCVS_E_CAPACITY,
+               "at most " + std::to_string(SCVS_NOALLOC_MAX_SYSTEMS) + " systems per call without allocation");
+  const int dev = m->ctx->device;
+  void* ptr = nullptr;
+  if (dev >= 0 && dev < SCRATCH_MAX_DEVICES) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    ptr = g_scratch_ptr[dev];
+  }
+  SCVS_REQUIRE(ptr != nullptr, SCVS_E_STATE, "no scratch array address for this device");
+  mode_norms_into(m, nsys, u, p, static_cast<double*>(ptr), un2, pn2);
 }
 
 }  // namespace scvs

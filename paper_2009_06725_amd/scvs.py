@@ -25,7 +25,7 @@ EXPORTED = [
     "scvs_assemble",
     "scvs_mesh_export", "scvs_spmv", "scvs_rhs", "scvs_solve_opts_default", "scvs_solve",
     "scvs_autotune", "scvs_solve_groups", "scvs_boundary_norms", "scvs_mode_norms", "scvs_select_modes",
-    "scvs_mode_increments", "scvs_synthesize", "scvs_probe_mfma", "scvs_profile_enable", "scvs_profile_read",
+    "scvs_mode_increments", "scvs_mode_norms_noalloc", "scvs_synthesize", "scvs_probe_mfma", "scvs_profile_enable", "scvs_profile_read",
     "scvs_ws_create", "scvs_ws_train", "scvs_ws_predict", "scvs_ws_refine", "scvs_ws_destroy", "scvs_ws_export",
     "scvs_ws_set_params", "scvs_ws_loss_grad", "scvs_herm_eig", "scvs_probe_mfma_bf16",
 ]
@@ -101,6 +101,7 @@ def lib() -> C.CDLL:
         L.scvs_solve_groups.argtypes = [C.c_int, vp]
         L.scvs_boundary_norms.argtypes = [vp, i64, vp, vp, vp, vp]
         L.scvs_mode_norms.argtypes = [vp, i64, vp, vp, vp, vp]
+        L.scvs_mode_norms_noalloc.argtypes = [vp, i64, vp, vp, vp, vp]
         L.scvs_select_modes.argtypes = [i64, vp, vp, vp, C.c_double, C.c_int, vp, vp, vp]
         L.scvs_mode_increments.argtypes = [i64, vp, vp, vp]
         L.scvs_synthesize.argtypes = [vp, i64, vp, vp, i64, i64, vp, vp]
@@ -135,6 +136,7 @@ def _host(a, dtype):
 
 
 E_INVALID = -1
+SCVS_NOALLOC_MAX_SYSTEMS = 256  # include/scvs.h
 
 
 def _dev(t, dtype_name: str, numel: int | None = None, device: int | None = None, what: str = "tensor"):
@@ -340,6 +342,18 @@ class Mesh:
         _check(lib().scvs_mode_norms(self.h, ns, _dev(u, "torch.complex128", ns * i.n2 * i.dim, d, "u"),
                                      _dev(p, "torch.complex128", ns * i.nv, d, "p"),
                                      un2.ctypes.data_as(C.c_void_p), pn2.ctypes.data_as(C.c_void_p)))
+        return un2, pn2
+
+    def mode_norms_noalloc(self, u, p):
+        """mode_norms through the entry point that allocates no device memory."""
+        i = self.info
+        ns = u.shape[0]
+        un2 = np.zeros(ns)
+        pn2 = np.zeros(ns)
+        d = self.ctx.device
+        _check(lib().scvs_mode_norms_noalloc(self.h, ns, _dev(u, "torch.complex128", ns * i.n2 * i.dim, d, "u"),
+                                             _dev(p, "torch.complex128", ns * i.nv, d, "p"),
+                                             un2.ctypes.data_as(C.c_void_p), pn2.ctypes.data_as(C.c_void_p)))
         return un2, pn2
 
     def autotune(self, omega, traction, g=None, base: SolveOpts | None = None):
