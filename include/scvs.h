@@ -223,11 +223,31 @@ typedef struct {
   double inner_rtol;  /* mixed precision only: a restart cycle also ends once its own residual
                          estimate has fallen by this factor (the FP32 operator cannot take the
                          true residual much further within one cycle); 0 = only at rtol or m */
+  int32_t vel_block;  /* velocity block of the preconditioner. 0: Chebyshev polynomial of degree
+                         cheb_vel in the Jacobi-scaled real shift mu Ks + |w| rho M. 1: one
+                         V-cycle of aggregation multigrid on the complex block mu Ks + j w rho M
+                         (levels: the quadratic nodes, the linear space of the same mesh, then
+                         smoothed aggregates down to at most 256 rows, whose operator is
+                         inverted densely per system; built once per assembly and boundary
+                         conditions) */
+  int32_t pres_block; /* pressure Laplacian inverse in the Schur block (when cheb_pres > 0).
+                         0: Chebyshev polynomial of degree cheb_pres. 1: one multigrid V-cycle */
+  int32_t mg_smooth;  /* multigrid: Chebyshev smoothing steps before and after each coarse
+                         correction, >= 1 */
+  double mg_ratio;    /* multigrid: smoothers target [lambda / mg_ratio, lambda] of the level
+                         operator scaled by its complex diagonal, > 1 */
+  double steady_schur_omega; /* >= 0: for steady systems (w = 0) the Schur block uses this
+                         w in its Laplacian term, mu Mp^-1 + j w_s rho L^-1, instead of the
+                         pressure mass alone. The preconditioner acts from the right, so the
+                         solution is unchanged; pressure modes that the velocity controls only
+                         weakly (corners whose velocity nodes are all prescribed) then no
+                         longer stall the steady solve. 0 = off */
 } scvs_solve_opts;
 
 /* Fill `o` with the defaults (rtol 1e-10, m 200, 20000 iterations, degrees 12/50,
  * ratios 300 (velocity) / 1000 (pressure), batch 0, graphs on, FP64, lagged
- * orthogonalization, inner_rtol 3e-5). */
+ * orthogonalization, inner_rtol 3e-5, polynomial blocks (vel_block = pres_block = 0),
+ * multigrid smoothing 2 steps, ratio 10, steady_schur_omega 0). */
 void scvs_solve_opts_default(scvs_solve_opts* o);
 
 typedef struct {
@@ -250,6 +270,18 @@ typedef struct {
 int scvs_solve(scvs_mesh mesh, int64_t nsys, const double* omega, const double* traction,
                const void* g, const void* x0, void* u_out, void* p_out,
                const scvs_solve_opts* opts, scvs_report* rep);
+
+/* ---- a5: the multigrid hierarchies of the preconditioner ----
+ * Builds them if needed (as the first solve with vel_block or pres_block = 1
+ * does: once per assembly and boundary-condition set) and reports, for
+ * hierarchy `which` (0: velocity block, whose level 0 is the quadratic pattern;
+ * 1: pressure Laplacian), the rows and nonzeros of each level and the nonzeros
+ * of its transfer to the next coarser level (0 on the coarsest, which is
+ * inverted densely), for up to `maxlev` levels (host int64_t[maxlev] each);
+ * *nlev = the number of levels. Errors: SCVS_E_STATE before assembly,
+ * SCVS_E_CAPACITY if coarsening stalls. */
+int scvs_mesh_mg_info(scvs_mesh mesh, int which, int maxlev, int64_t* rows, int64_t* nnz, int64_t* pnnz,
+                      int* nlev);
 
 /* ---- a8: several meshes at once ----
  * Solves n groups of systems, each on its own mesh, concurrently: every group

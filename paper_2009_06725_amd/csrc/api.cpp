@@ -57,7 +57,10 @@ scvs_solve_opts checked_opts(const scvs_solve_opts* opts) {
                    (o.precision >= 0 && o.precision <= 2) && (o.orth == 0 || o.orth == 1) &&
                    (o.precision != 2 || o.orth == 1) && o.inner_rtol >= 0.0 && o.inner_rtol < 1.0 &&
                    (o.cheb_ratio_pres == 0.0 || o.cheb_ratio_pres > 1.0) && o.penalty >= 0.0 &&
-                   std::isfinite(o.penalty),
+                   std::isfinite(o.penalty) && (o.vel_block == 0 || o.vel_block == 1) &&
+                   (o.pres_block == 0 || o.pres_block == 1) && o.mg_smooth >= 1 && o.mg_smooth <= 16 &&
+                   o.mg_ratio > 1.0 && std::isfinite(o.mg_ratio) && o.steady_schur_omega >= 0.0 &&
+                   std::isfinite(o.steady_schur_omega),
                SCVS_E_INVALID, "bad solve options");
   return o;
 }
@@ -65,8 +68,9 @@ scvs_solve_opts checked_opts(const scvs_solve_opts* opts) {
 // Every option the autotuner does not choose (and that changes the solve), as a key.
 std::string untuned_key(const scvs_solve_opts& o) {
   char buf[512];
-  snprintf(buf, sizeof buf, "%.17g|%d|%.17g|%d|%d|%d|%d|%.17g|%.17g|%.17g", o.rtol, o.max_iters, o.cheb_ratio,
-           o.max_batch, o.use_graph, o.precision, o.orth, o.cheb_ratio_pres, o.penalty, o.inner_rtol);
+  snprintf(buf, sizeof buf, "%.17g|%d|%.17g|%d|%d|%d|%d|%.17g|%.17g|%.17g|%d|%d|%d|%.17g|%.17g", o.rtol, o.max_iters,
+           o.cheb_ratio, o.max_batch, o.use_graph, o.precision, o.orth, o.cheb_ratio_pres, o.penalty, o.inner_rtol,
+           o.vel_block, o.pres_block, o.mg_smooth, o.mg_ratio, o.steady_schur_omega);
   return buf;
 }
 
@@ -353,6 +357,11 @@ void scvs_solve_opts_default(scvs_solve_opts* o) {
   o->cheb_ratio_pres = 1000.0;
   o->penalty = 0.0;
   o->inner_rtol = 3e-5;
+  o->vel_block = 0;
+  o->pres_block = 0;
+  o->mg_smooth = 2;
+  o->mg_ratio = 10.0;
+  o->steady_schur_omega = 0.0;
 }
 
 int scvs_solve(scvs_mesh m, int64_t nsys, const double* omega, const double* traction, const void* g,
@@ -483,6 +492,17 @@ int scvs_mode_norms_noalloc(scvs_mesh m, int64_t nsys, const void* u, const void
     SCVS_REQUIRE(nsys > 0 && u && p && un2 && pn2, SCVS_E_INVALID, "bad mode-norm arguments");
     use_device(m->ctx);
     scvs::mode_norms_noalloc(m, nsys, u, p, un2, pn2);
+  });
+}
+
+int scvs_mesh_mg_info(scvs_mesh m, int which, int maxlev, int64_t* rows, int64_t* nnz, int64_t* pnnz,
+                      int* nlev) {
+  return guarded([&] {
+    require_ready(m);
+    SCVS_REQUIRE((which == 0 || which == 1) && maxlev >= 0 && (maxlev == 0 || (rows && nnz && pnnz)) && nlev,
+                 SCVS_E_INVALID, "bad multigrid-info arguments");
+    use_device(m->ctx);
+    *nlev = scvs::mg_info(m, which, maxlev, rows, nnz, pnnz);
   });
 }
 

@@ -12,6 +12,7 @@
 #include <cstring>
 #include <string>
 #include <map>
+#include <memory>
 #include <tuple>
 #include <vector>
 
@@ -144,6 +145,45 @@ struct scvs_ctx_s {
 
 constexpr int SCVS_MMAX = 256;  // largest Krylov dimension per cycle
 
+namespace scvs {
+// One level of an aggregation multigrid hierarchy (device): its operator pair (K, M;
+// M empty for a single-matrix hierarchy) with diagonals, FP32 copies, and the
+// transfer to the next coarser level, P (n x nc) and R = P^T (nc x n).
+struct MgLevel {
+  int64_t n = 0, nnz = 0, nc = 0;
+  DBuf<int64_t> ptr;
+  DBuf<int32_t> col;
+  DBuf<double> K, M, Kd, Md;
+  DBuf<float> K32, M32, Kd32, Md32;
+  DBuf<int64_t> pptr, rptr;
+  DBuf<int32_t> pcol, rcol;
+  DBuf<double> pval, rval;
+  DBuf<float> pval32, rval32;
+  double lam = 0.0;  // Gershgorin bound of D^-1 K (single-matrix hierarchies)
+};
+struct MgHier {
+  std::vector<MgLevel> lv;
+  bool mass = false;
+  DBuf<double2> cinv;  // single-matrix hierarchies: dense inverse of the coarsest level
+  DBuf<float2> cinv32;
+};
+constexpr int MG_COARSE_MAX = 256;  // rows of the coarsest level (inverted densely)
+struct MgData {
+  uint64_t gen = ~0ull;  // operator generation it was built for
+  MgHier vel;            // lv[0]: the quadratic pattern (transfer only), then P1 and aggregates
+  MgHier pres;           // lv[0]: the assembled pressure Laplacian
+};
+constexpr int MG_MAXLEV = 12;
+// Temporaries of one preconditioner application: per level 5 interleaved arrays.
+struct MgBufs {
+  void* v[MG_MAXLEV] = {};
+  void* p[MG_MAXLEV] = {};
+  const double* vlam = nullptr;  // [level][slots] per-system velocity bounds
+  const void* vinv = nullptr;    // [slots][nc][nc] coarsest velocity inverses (FP32 in mixed mode)
+  int slots = 0;
+};
+}  // namespace scvs
+
 struct scvs_mesh_s {
   scvs_ctx ctx = nullptr;
   uint64_t uid = 0;  // unique per mesh object in this process (never reused, unlike addresses)
@@ -191,6 +231,8 @@ struct scvs_mesh_s {
   scvs::DBuf<int64_t> wk_roff;         // [wk_nrow+1] -> (outlet, b) pairs of each row
   scvs::DBuf<int32_t> wk_rdof, wk_rout;
   scvs::DBuf<double> wk_rb;
+  // aggregation multigrid of the velocity block and the pressure Laplacian
+  std::unique_ptr<scvs::MgData> mg;
 };
 
 namespace scvs {
@@ -259,6 +301,8 @@ __host__ __device__ inline float2 cvt2<float2>(double2 v) { return make_float2((
 __host__ __device__ inline double2 to_d2(double2 v) { return v; }
 __host__ __device__ inline double2 to_d2(float2 v) { return make_double2((double)v.x, (double)v.y); }
 // The active systems of one launch.
+struct Batch;
+__host__ __device__ inline double schur_w(const Batch& b, int slot);
 struct Batch {
   int nact = 0;
   const int* act = nullptr;       // device [nact] slot indices
@@ -267,8 +311,14 @@ struct Batch {
   const double* insc = nullptr;   // device [slots * insc_st] input scale (nullptr = 1)
   int insc_st = 0, insc_idx = 0;
   double pen = 0.0;  // penalty: continuity block -pen * Mp (lumped), pen = epsilon / mu
+  double wsteady = 0.0;  // w of the Schur block's Laplacian term for steady (w = 0) systems
   bool no_lumped = false;  // leave out the lumped-outlet terms
 };
+// w in the Schur block mu Mp^-1 + j w rho L^-1 of a system: its own, or wsteady when it is 0
+__host__ __device__ inline double schur_w(const Batch& b, int slot) {
+  const double w = b.omega[slot];
+  return w != 0.0 ? w : b.wsteady;
+}
 enum { SPMV_APPLY = 0, SPMV_RESID = 1, SPMV_RHS = 2 };
 // y = A x (APPLY), y = f - A x (RESID), y = [-sum P n - A x ; x on Dirichlet rows ; -G^T x] (RHS).
 void spmv_full(scvs_mesh m, const Batch& b, VArg x, VArg y, int mode, bool maskcol, VArg f,
@@ -282,7 +332,12 @@ struct PrecondArgs {
   VArg32 vt32;    // FP32 velocity temps: 4 * d*n2 per slot
   VArg32 z32;     // FP32 preconditioned vector (velocity part, plus a copy of the pressure part)
   VArg vt;  // velocity temps: 4 * d*n2 per slot (b, three rotating iterates)
-  VArg pt;  // pressure temps: 4*nv per slot (r, d0, d1, x)
+  VArg pt;  // pressure temps: 4*nv per slot (r, d0, d1, x); 5*nv with pressure multigrid
+  // multigrid blocks (vt/vt32 then hold 5*d*n2 per slot: level 0 of the velocity cycle)
+  int vmg = 0, pmg = 0;
+  int mg_nu = 2;
+  double mg_ratio = 10.0;
+  MgBufs mg;
 };
 // With zil (a buffer of nact*ndof values, FP32 in mixed mode) the result is written
 // interleaved for spmv_apply_il instead of into z (z still receives the FP64 pressure
@@ -306,6 +361,27 @@ void spmv_apply32(scvs_mesh m, const Batch& b, VArg32 x, VArg y, hipStream_t s);
 void make_fp32_copies(scvs_mesh m, hipStream_t s);
 // Gershgorin bound of diag^-1 (mu Ks + |w| rho M) on the free rows, per slot.
 void velocity_bounds(scvs_mesh m, const Batch& b, double* lv_out, hipStream_t s);
+
+// ---- mg.hip ----
+void mg_setup(scvs_mesh m, hipStream_t s);
+// Bytes of the temporaries below level 0 for `slots` systems (complex elements of esize bytes).
+size_t mg_buffer_bytes(scvs_mesh m, int slots, size_t esize, bool vel, bool pres);
+void mg_assign(scvs_mesh m, int slots, size_t esize, bool vel, bool pres, char* base, void* vel0, void* pres0,
+               double* vlam, MgBufs& out);
+int mg_levels(scvs_mesh m, bool vel);
+// Per system: smoother bounds of every velocity level and the coarsest level's dense inverse.
+void mg_prepare(scvs_mesh m, const Batch& b, double* lam, int slots, double2* inv, float2* inv32, hipStream_t s);
+int64_t mg_coarse_rows(scvs_mesh m);
+// Levels of a hierarchy (0 velocity, 1 pressure; built if needed): rows, nonzeros and the
+// nonzeros of the transfer to the next level, for up to maxlev levels; returns the count.
+int mg_info(scvs_mesh m, int which, int maxlev, int64_t* rows, int64_t* nnz, int64_t* pnnz);
+// Velocity V-cycle from the level-0 right-hand side and first iterate (k_vinit); the
+// result goes to zil (interleaved) or, without it, to z (FP32 z32 in mixed mode).
+void mg_velocity(scvs_mesh m, const Batch& b, const PrecondArgs& pa, void* zil, VArg z, hipStream_t s);
+// Pressure-Laplacian V-cycle from the level-0 right-hand side and first iterate
+// (k_pinit) and the FP64 Schur combination into z for the systems with w != 0.
+void mg_pressure(scvs_mesh m, const Batch& b, const PrecondArgs& pa, VArg v, VArg z, hipStream_t s);
+void mg_pressure(scvs_mesh m, const Batch& b, const PrecondArgs& pa, VArg32 v, VArg z, hipStream_t s);
 
 // ---- krylov.hip ----
 int solve_systems(scvs_mesh m, int64_t nsys, const double* omega, const double* traction,

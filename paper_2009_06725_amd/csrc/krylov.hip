@@ -863,6 +863,10 @@ struct Pool {
   DBuf<double> omega, lv, info;
   DBuf<int> act, act_all, act_run, stops;
   DBuf<double2> zil;  // interleaved preconditioner output inside a cycle (FP32 pairs in mixed mode)
+  DBuf<char> mgbuf;   // multigrid temporaries below level 0
+  DBuf<double> mglam; // [velocity level][slot] smoother bounds
+  DBuf<double2> mginv; // [slot] dense inverse of the coarsest velocity level
+  DBuf<float2> mginv32;
   VArg Z() const { return VArg{W.p, 4 * ld}; }
   VArg X() const { return VArg{W.p + ld, 4 * ld}; }
   VArg F() const { return VArg{W.p + 2 * ld, 4 * ld}; }
@@ -1085,14 +1089,26 @@ int solve_systems(scvs_mesh m, int64_t nsys, const double* omega, const double* 
   const bool lagged = o->orth == 1;
   P.v32 = o->precision == 2;  // FP32 basis storage (lagged orthogonalization only; checked by the caller)
   if (mixed) make_fp32_copies(m, s);
+  // multigrid blocks: the hierarchy (once per assembly and boundary conditions) and, per
+  // slot, a fifth level-0 temporary, the coarse-level temporaries and the smoother bounds
+  const bool vmg = o->vel_block == 1, pmg = o->pres_block == 1 && o->cheb_pres > 0;
+  const size_t esz = mixed ? sizeof(float2) : sizeof(double2);
+  size_t mg_extra = 0;
+  if (vmg || pmg) {
+    mg_setup(m, s);
+    const size_t nc2 = (size_t)mg_coarse_rows(m) * mg_coarse_rows(m);
+    mg_extra = (vmg ? (size_t)DN * esz + nc2 * (sizeof(double2) + (mixed ? sizeof(float2) : 0)) : 0) +
+               (pmg ? (size_t)m->nv * sizeof(double2) : 0) + mg_buffer_bytes(m, 1, esz, vmg, pmg) +
+               sizeof(double) * mg_levels(m, true);
+  }
   int mk = o->restart;
   const int64_t want = std::min<int64_t>(nsys, 8);
-  while (mk > 30 &&
-         (int64_t)((double)fr * 0.9 / (double)slot_bytes(P.ld, mk, DN, m->nv, nch_max, mixed, P.v32)) < want)
+  while (mk > 30 && (int64_t)((double)fr * 0.9 /
+                              (double)(slot_bytes(P.ld, mk, DN, m->nv, nch_max, mixed, P.v32) + mg_extra)) < want)
     mk = std::max(30, mk * 3 / 4);
   if (o->verbose && mk != o->restart) fprintf(stderr, "[scvs] restart shortened to %d to fit memory\n", mk);
   P.m = mk;
-  const size_t per = slot_bytes(P.ld, mk, DN, m->nv, nch_max, mixed, P.v32);
+  const size_t per = slot_bytes(P.ld, mk, DN, m->nv, nch_max, mixed, P.v32) + mg_extra;
   int64_t fit = (int64_t)((double)fr * 0.9 / (double)per);
   SCVS_REQUIRE(fit >= 1, SCVS_E_NOMEM, "not enough device memory for one system's Krylov workspace");
   int B = (int)std::min<int64_t>(nsys, fit);
@@ -1100,13 +1116,23 @@ int solve_systems(scvs_mesh m, int64_t nsys, const double* omega, const double* 
   P.slots = B;
   P.V.alloc(P.v32 ? ((size_t)B * (mk + 1) * P.ld + 1) / 2 : (size_t)B * (mk + 1) * P.ld);
   P.W.alloc((size_t)B * 4 * P.ld);
+  const int nvt = vmg ? 5 : 4, npt = pmg ? 5 : 4;
   if (mixed) {
-    P.vt32.alloc((size_t)B * 4 * DN);
+    P.vt32.alloc((size_t)B * nvt * DN);
     P.z32.alloc((size_t)B * P.ld);
   } else {
-    P.vt.alloc((size_t)B * 4 * DN);
+    P.vt.alloc((size_t)B * nvt * DN);
   }
-  P.pt.alloc((size_t)B * 4 * m->nv);
+  P.pt.alloc((size_t)B * npt * m->nv);
+  if (vmg || pmg) {
+    P.mgbuf.alloc(mg_buffer_bytes(m, B, esz, vmg, pmg) + 256);
+    P.mglam.alloc((size_t)B * mg_levels(m, true));
+    if (vmg) {
+      const size_t nc2 = (size_t)mg_coarse_rows(m) * mg_coarse_rows(m);
+      P.mginv.alloc((size_t)B * nc2);
+      if (mixed) P.mginv32.alloc((size_t)B * nc2);
+    }
+  }
   P.part.alloc((size_t)B * nch_max * PSTRIDE);
   P.st.alloc(B);
   P.omega.alloc(B);
@@ -1127,7 +1153,15 @@ int solve_systems(scvs_mesh m, int64_t nsys, const double* omega, const double* 
   pa.mixed = mixed ? 1 : 0;
   pa.vt32 = VArg32{P.vt32.p, 4 * DN};
   pa.z32 = VArg32{P.z32.p, P.ld};
-  pa.pt = VArg{P.pt.p, 4 * m->nv};
+  pa.pt = VArg{P.pt.p, npt * m->nv};
+  pa.vmg = vmg ? 1 : 0;
+  pa.pmg = pmg ? 1 : 0;
+  pa.mg_nu = o->mg_smooth;
+  pa.mg_ratio = o->mg_ratio;
+  if (vmg || pmg)
+    mg_assign(m, B, esz, vmg, pmg, P.mgbuf.p, mixed ? (void*)P.vt32.p : (void*)P.vt.p, (void*)P.pt.p, P.mglam.p,
+              pa.mg);
+  pa.mg.vinv = mixed ? (const void*)P.mginv32.p : (const void*)P.mginv.p;
   std::vector<int> all(B);
   for (int k = 0; k < B; ++k) all[k] = k;
   SCVS_HIP(hipMemcpyAsync(P.act_all.p, all.data(), sizeof(int) * B, hipMemcpyHostToDevice, s));
@@ -1145,6 +1179,7 @@ int solve_systems(scvs_mesh m, int64_t nsys, const double* omega, const double* 
     b.omega = P.omega;
     b.lv = P.lv;
     b.pen = o->penalty / m->mu;
+    b.wsteady = o->steady_schur_omega;
     k_init_state<<<(nb + 63) / 64, 64, 0, s>>>(P.st, P.act_all, nb);
     const int nch0 = choose_nch(nb, ndof);
     KArgs a0 = kargs(P, ndof, nch0);
@@ -1168,7 +1203,10 @@ int solve_systems(scvs_mesh m, int64_t nsys, const double* omega, const double* 
     launch_check(s);
     spmv_full(m, b, P.T(), P.F(), SPMV_RHS, false, VArg{}, P.trac, s);
     k_norm<0><<<g0, RBS, 0, s>>>(a0, P.F(), o->rtol);
-    velocity_bounds(m, b, P.lv, s);
+    if (vmg)
+      mg_prepare(m, b, P.mglam.p, B, P.mginv.p, mixed ? P.mginv32.p : nullptr, s);
+    else
+      velocity_bounds(m, b, P.lv, s);
     // initial residual into V_0 of every slot, and its norm
     auto residual0 = [&](const Batch& bb, const KArgs& ka, dim3 gn) {
       const int64_t vst = (int64_t)(mk + 1) * P.ld;

@@ -10,30 +10,10 @@
 // Per system the momentum block is mu Ks + j w rho M; the preconditioner uses
 // the real shift mu Ks + |w| rho M and the pressure Laplacian G^T diag(M)^-1 G.
 #include "internal.hpp"
+#include "rowmap.hpp"
 
 namespace scvs {
 namespace {
-
-struct LaneMap {
-  int G;     // (system, component) pairs per row
-  int W;     // lanes per row group (a power of two, <= 64)
-  int UL;    // pair lanes used per pass (a multiple of D, <= W)
-  int R;     // rows per wavefront (64 / W)
-  int iters; // passes over the pairs
-};
-
-// Rows are handled by groups of W lanes (a power of two, so shuffles can stay
-// inside a group); the group's lanes cover the (system, component) pairs.
-LaneMap lane_map(int nact, int D) {
-  const int G = nact * D;
-  if (G <= 32) {
-    int W = 1;
-    while (W < G) W <<= 1;
-    return {G, W, G, 64 / W, 1};
-  }
-  const int UL = (64 / D) * D;
-  return {G, 64, UL, 1, (G + UL - 1) / UL};
-}
 
 struct MeshArgs {
   int64_t n2, nv, nnz21, nnzv, nnz, nnzl;
@@ -119,37 +99,6 @@ __device__ __forceinline__ C czero() {
   z.x = 0;
   z.y = 0;
   return z;
-}
-
-struct Lane {
-  int64_t row;
-  int li;     // lane within the row group
-  int p0;     // first pair of this lane
-  bool rowok;
-  bool pairok0;
-};
-
-// Workgroups are dealt to the 8 XCDs in turn. Within every group of 8 * XRUN
-// consecutive workgroups, XCD x takes the XRUN consecutive row blocks starting at
-// x * XRUN, so that neighbouring rows (whose gathers overlap) share one XCD's L2 while
-// all XCDs stay in the same stretch of rows; a ragged last group keeps its order.
-constexpr int64_t XRUN = 16;
-__device__ __forceinline__ int64_t row_block() {
-  const int64_t b = blockIdx.x, S = 8 * XRUN, g = b / S;
-  if ((g + 1) * S > (int64_t)gridDim.x) return b;
-  const int64_t off = b - g * S;
-  return g * S + (off % 8) * XRUN + off / 8;
-}
-
-__device__ __forceinline__ Lane lane_of(const LaneMap& lm, int64_t nrows) {
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  Lane L;
-  L.li = lane & (lm.W - 1);
-  L.p0 = L.li;
-  L.row = (row_block() * 4 + wave) * lm.R + lane / lm.W;
-  L.rowok = L.row < nrows;
-  L.pairok0 = L.li < lm.UL;
-  return L;
 }
 
 __device__ __forceinline__ double in_scale(const Batch& b, int slot) {
@@ -422,22 +371,6 @@ void wk_launch(scvs_mesh m, const Batch& b, int mode, SV<XC> x, const XC* xil, S
   launch_check(s);
 }
 
-// Chebyshev recurrence scalars for step i >= 1 on [lmax/ratio, lmax]:
-// rho_0 = 1/sigma, rho_k = 1/(2 sigma - rho_{k-1}) with sigma = theta/delta =
-// (1 + 1/ratio)/(1 - 1/ratio), which does not depend on lmax; returns rho_{i-1}, rho_i.
-// (Computed once per step on the host; the kernels form theta and delta from lmax.)
-struct ChebStep {
-  double rprev, rcur;
-};
-inline ChebStep cheb_step(double ratio, int i) {
-  const double sigma = (1.0 + 1.0 / ratio) / (1.0 - 1.0 / ratio);
-  double r = 1.0 / sigma, rp = r;
-  for (int k = 1; k <= i; ++k) {
-    rp = r;
-    r = 1.0 / (2.0 * sigma - r);
-  }
-  return {rp, r};
-}
 
 // Velocity block, Chebyshev polynomial in diag^-1 A_r with A_r = mu Ks + |w| rho M
 // (same for every component), in three-term form
@@ -463,7 +396,9 @@ struct ITemps {
 // here, pressure part copied from the FP64 Schur-block result zp).
 // With zil the result goes to the interleaved vector read by the next operator product
 // (layout of k_full's IL input); the pressure part is copied there too.
-template <int D, class R, class VI>
+// With CX (multigrid velocity block) x_1 = D^-1 b / theta uses the complex diagonal
+// D = mu Ks_AA + j w rho M_AA of level 0 and the level's bound b.lv.
+template <int D, class R, class VI, bool CX = false>
 __global__ void __launch_bounds__(256) k_vinit(MeshArgs ma, Batch b, LaneMap lm, SV<VI> v, VArg zp64,
                                                typename Prec<R>::V z, ITemps<typename Prec<R>::C> vt,
                                                double ratio, int kv, typename Prec<R>::C* __restrict__ zil) {
@@ -501,11 +436,18 @@ __global__ void __launch_bounds__(256) k_vinit(MeshArgs ma, Batch b, LaneMap lm,
     g_acc<D, R, double2>(ma, A, ma.rowptr[A], zp, 1, 0, c, (R)-1, t);
     const double lmax = b.lv[slot];
     const R theta = (R)(0.5 * lmax * (1.0 + 1.0 / ratio));
-    const R dinv = (R)1 / ((R)ma.mu * Prec<R>::Kd(ma)[A] + (R)(fabs(b.omega[slot]) * ma.rho) * Prec<R>::Md(ma)[A]);
     bb[ki] = t;
     C xv;
-    xv.x = t.x * (dinv / theta);
-    xv.y = t.y * (dinv / theta);
+    if (CX) {
+      const R dr = (R)ma.mu * Prec<R>::Kd(ma)[A], di = (R)(b.omega[slot] * ma.rho) * Prec<R>::Md(ma)[A];
+      const R sc2 = (R)1 / ((dr * dr + di * di) * theta);
+      xv.x = (t.x * dr + t.y * di) * sc2;
+      xv.y = (t.y * dr - t.x * di) * sc2;
+    } else {
+      const R dinv = (R)1 / ((R)ma.mu * Prec<R>::Kd(ma)[A] + (R)(fabs(b.omega[slot]) * ma.rho) * Prec<R>::Md(ma)[A]);
+      xv.x = t.x * (dinv / theta);
+      xv.y = t.y * (dinv / theta);
+    }
     *x1 = xv;
   }
 }
@@ -568,12 +510,13 @@ __global__ void k_pinit(MeshArgs ma, int D, Batch b, SV<VI> v, VArg z, ITemps<ty
   const double2 dd = cscale(vp, ma.lpdinv[vv] / theta);
   pt.arr(0)[ki] = cvt2<C>(vp);
   pt.iter(1)[ki] = cvt2<C>(dd);
-  // at w = 0 the Laplacian term j w rho L^-1 v_p vanishes: the block is final here and
-  // the Chebyshev steps skip this system
-  if (kp <= 1 || b.omega[slot] == 0.0) {
+  // without a Laplacian term (w = 0 and no steady pseudo-frequency) the block is final
+  // here and the Chebyshev steps skip this system
+  const double ws = schur_w(b, slot);
+  if (kp <= 1 || ws == 0.0) {
     // kp == 0: the Schur block is the pressure mass alone, zhat_p = -mu Mp^-1 v_p
     const double2 xl = kp == 0 ? make_double2(0.0, 0.0) : dd;
-    const double wr = b.omega[slot] * ma.rho, im = ma.mu / ma.Mp[vv];
+    const double wr = ws * ma.rho, im = ma.mu / ma.Mp[vv];
     z.at(slot)[DN + vv] = make_double2(-(im * vp.x - wr * xl.y), -(im * vp.y + wr * xl.x));
   }
 }
@@ -595,7 +538,7 @@ __global__ void __launch_bounds__(256) k_pstep(MeshArgs ma, int D, Batch b, SV<V
   const int64_t A = idx / G;
   const int p = (int)(idx - A * G);
   const int slot = b.act[p];
-  if (b.omega[slot] == 0.0) return;  // Schur block already final (k_pinit)
+  if (schur_w(b, slot) == 0.0) return;  // Schur block already final (k_pinit)
   const int64_t ki = idx;  // = A * G + p
   const C* __restrict__ xk = pt.iter(step);
   C q = czero<C>();
@@ -638,7 +581,7 @@ __global__ void __launch_bounds__(256) k_pstep(MeshArgs ma, int D, Batch b, SV<V
     const int64_t DN = D * ma.n2;
     const double sc = in_scale(b, slot);
     const double2 vp = cscale(to_d2(v.at(slot)[DN + A]), sc);
-    const double wr = b.omega[slot] * ma.rho, im = ma.mu / ma.Mp[A];
+    const double wr = schur_w(b, slot) * ma.rho, im = ma.mu / ma.Mp[A];
     const double2 xd = to_d2(xn);
     z.at(slot)[DN + A] = make_double2(-(im * vp.x - wr * xd.y), -(im * vp.y + wr * xd.x));
   }
@@ -667,10 +610,6 @@ __global__ void k_vbound(MeshArgs ma, Batch b, unsigned long long* __restrict__ 
   if (threadIdx.x == 0) atomicMax(&out[slot], (unsigned long long)__double_as_longlong(sh[0]));
 }
 
-inline unsigned row_blocks(int64_t nrows, const LaneMap& lm) {
-  const int64_t per = 4 * (int64_t)lm.R;
-  return (unsigned)((nrows + per - 1) / per);
-}
 
 // Algorithmic bytes of one full-operator launch: every matrix array once
 // (S2 col/Ks/M, G on the vertex-column prefix, Gt on vertex rows, row
@@ -732,8 +671,8 @@ void full_launch_il(Profiler* prof, const MeshArgs& ma, const Batch& b, const ty
 }
 
 template <int D, class VI>
-void precond_launch(Profiler* prof, const MeshArgs& ma, const Batch& b, const PrecondArgs& pa, SV<VI> v, VArg z,
-                    void* zil, hipStream_t s) {
+void precond_launch(scvs_mesh m, Profiler* prof, const MeshArgs& ma, const Batch& b, const PrecondArgs& pa, SV<VI> v,
+                    VArg z, void* zil, hipStream_t s) {
   const LaneMap lm = lane_map(b.nact, D);
   const unsigned nbu = row_blocks(ma.n2, lm);
   const unsigned nbp = (unsigned)((ma.nv * b.nact + 255) / 256);  // k_pstep: one thread per (vertex, system)
@@ -747,15 +686,19 @@ void precond_launch(Profiler* prof, const MeshArgs& ma, const Batch& b, const Pr
   {
     // per system: v_p read, r/d0/x written (and z_p when one step); lpdinv, Mp read
     ProfScope ps(prof, s, pa.mixed ? "k_pinit32" : "k_pinit", nv * 16.0 + na * nv * (16.0 + 2.0 * pes));
+    // (multigrid: the first smoothing iterate of the Laplacian's level 0, smoother interval)
+    const double rp = pa.pmg ? pa.mg_ratio : pa.ratio_p;
+    const int kp = pa.pmg ? 2 : pa.kp;
     if (pa.mixed)
-      k_pinit<VI, float><<<gp, 256, 0, s>>>(ma, D, b, v, z, ptl32, pa.ratio_p, pa.kp);
+      k_pinit<VI, float><<<gp, 256, 0, s>>>(ma, D, b, v, z, ptl32, rp, kp);
     else
-      k_pinit<VI, double><<<gp, 256, 0, s>>>(ma, D, b, v, z, ptl, pa.ratio_p, pa.kp);
+      k_pinit<VI, double><<<gp, 256, 0, s>>>(ma, D, b, v, z, ptl, rp, kp);
   }
+  if (pa.pmg) mg_pressure(m, b, pa, v, z, s);
   // L values and columns, row pointers, diag, Mp; per system x_i gathered (read once),
   // b and x_{i-1} read, x_{i+1} written (last step: v_p read and z_p written instead)
   const double pbytes = (double)ma.nnzl * (4.0 + pvs) + nv * 24.0 + na * nv * pes * 4.0;
-  if (pa.kp > 1) {
+  if (!pa.pmg && pa.kp > 1) {
     // the steps run back to back: one timed span for all of them
     ProfScope ps(prof, s, pa.mixed ? "k_pstep32" : "k_pstep", pbytes * (pa.kp - 1) + na * nv * (32.0 - pes),
                  pa.kp - 1);
@@ -778,10 +721,24 @@ void precond_launch(Profiler* prof, const MeshArgs& ma, const Batch& b, const Pr
     ProfScope ps(prof, s, pa.mixed ? "k_vinit32" : "k_vinit",
                  (double)ma.nnz21 * (4.0 + vs * D) + n2 * (24.0 + 2.0 * vs) +
                      na * (DN * 16.0 + nv * 16.0 + 2.0 * DN * es + (pa.mixed ? nv * es : 0.0)));
-    if (pa.mixed)
+    if (pa.vmg) {
+      // multigrid: b and the first smoothing iterate of level 0 (complex diagonal)
+      Batch bv = b;
+      bv.lv = pa.mg.vlam;
+      if (pa.mixed)
+        k_vinit<D, float, VI, true><<<nbu, 256, 0, s>>>(ma, bv, lm, v, z, pa.z32, it32, pa.mg_ratio, 2, (float2*)zil);
+      else
+        k_vinit<D, double, VI, true><<<nbu, 256, 0, s>>>(ma, bv, lm, v, z, z, it64, pa.mg_ratio, 2, (double2*)zil);
+    } else if (pa.mixed) {
       k_vinit<D, float, VI><<<nbu, 256, 0, s>>>(ma, b, lm, v, z, pa.z32, it32, pa.ratio, pa.kv, (float2*)zil);
-    else
+    } else {
       k_vinit<D, double, VI><<<nbu, 256, 0, s>>>(ma, b, lm, v, z, z, it64, pa.ratio, pa.kv, (double2*)zil);
+    }
+  }
+  if (pa.vmg) {
+    launch_check(s);
+    mg_velocity(m, b, pa, zil, z, s);
+    return;
   }
   // S2 col/Ks/M, rowptr/dmask/Kd/Md; per system x_k (gathered, read once), b, x_{k-1} read, x_{k+1} written
   const double vbytes = (double)ma.nnz * (4.0 + 2.0 * vs) + n2 * (12.0 + 2.0 * vs) + na * 4.0 * DN * es;
@@ -831,9 +788,9 @@ static void precond_any(scvs_mesh m, const Batch& b, const PrecondArgs& pa, SV<V
                         void* zil) {
   const MeshArgs ma = mesh_args(m);
   if (m->dim == 2)
-    precond_launch<2, VI>(&m->ctx->prof, ma, b, pa, v, z, zil, s);
+    precond_launch<2, VI>(m, &m->ctx->prof, ma, b, pa, v, z, zil, s);
   else
-    precond_launch<3, VI>(&m->ctx->prof, ma, b, pa, v, z, zil, s);
+    precond_launch<3, VI>(m, &m->ctx->prof, ma, b, pa, v, z, zil, s);
 }
 
 void precond_apply(scvs_mesh m, const Batch& b, const PrecondArgs& pa, VArg v, VArg z, hipStream_t s, void* zil) {

@@ -25,7 +25,7 @@ EXPORTED = [
     "scvs_assemble",
     "scvs_mesh_export", "scvs_spmv", "scvs_rhs", "scvs_solve_opts_default", "scvs_solve",
     "scvs_autotune", "scvs_solve_groups", "scvs_boundary_norms", "scvs_mode_norms", "scvs_select_modes",
-    "scvs_mode_increments", "scvs_mode_norms_noalloc", "scvs_synthesize", "scvs_probe_mfma", "scvs_profile_enable", "scvs_profile_read",
+    "scvs_mode_increments", "scvs_mode_norms_noalloc", "scvs_mesh_mg_info", "scvs_synthesize", "scvs_probe_mfma", "scvs_profile_enable", "scvs_profile_read",
     "scvs_ws_create", "scvs_ws_train", "scvs_ws_predict", "scvs_ws_refine", "scvs_ws_destroy", "scvs_ws_export",
     "scvs_ws_set_params", "scvs_ws_loss_grad", "scvs_herm_eig", "scvs_probe_mfma_bf16",
 ]
@@ -50,7 +50,8 @@ class SolveOpts(C.Structure):
                 ("cheb_vel", C.c_int32), ("cheb_pres", C.c_int32), ("cheb_ratio", C.c_double),
                 ("max_batch", C.c_int32), ("use_graph", C.c_int32), ("verbose", C.c_int32),
                 ("precision", C.c_int32), ("orth", C.c_int32), ("cheb_ratio_pres", C.c_double), ("penalty", C.c_double),
-                ("inner_rtol", C.c_double)]
+                ("inner_rtol", C.c_double), ("vel_block", C.c_int32), ("pres_block", C.c_int32),
+                ("mg_smooth", C.c_int32), ("mg_ratio", C.c_double), ("steady_schur_omega", C.c_double)]
 
 
 class SolveGroup(C.Structure):
@@ -102,6 +103,7 @@ def lib() -> C.CDLL:
         L.scvs_boundary_norms.argtypes = [vp, i64, vp, vp, vp, vp]
         L.scvs_mode_norms.argtypes = [vp, i64, vp, vp, vp, vp]
         L.scvs_mode_norms_noalloc.argtypes = [vp, i64, vp, vp, vp, vp]
+        L.scvs_mesh_mg_info.argtypes = [vp, C.c_int, C.c_int, vp, vp, vp, C.POINTER(C.c_int)]
         L.scvs_select_modes.argtypes = [i64, vp, vp, vp, C.c_double, C.c_int, vp, vp, vp]
         L.scvs_mode_increments.argtypes = [i64, vp, vp, vp]
         L.scvs_synthesize.argtypes = [vp, i64, vp, vp, i64, i64, vp, vp]
@@ -343,6 +345,16 @@ class Mesh:
                                      _dev(p, "torch.complex128", ns * i.nv, d, "p"),
                                      un2.ctypes.data_as(C.c_void_p), pn2.ctypes.data_as(C.c_void_p)))
         return un2, pn2
+
+    def mg_info(self, which: int = 0):
+        """Multigrid hierarchy (0 velocity, 1 pressure): [(rows, nnz, transfer nnz)] per level."""
+        n = C.c_int()
+        r = np.zeros(16, np.int64)
+        z = np.zeros(16, np.int64)
+        q = np.zeros(16, np.int64)
+        _check(lib().scvs_mesh_mg_info(self.h, which, 16, r.ctypes.data_as(C.c_void_p), z.ctypes.data_as(C.c_void_p),
+                                       q.ctypes.data_as(C.c_void_p), C.byref(n)))
+        return [(int(r[k]), int(z[k]), int(q[k])) for k in range(min(n.value, 16))]
 
     def mode_norms_noalloc(self, u, p):
         """mode_norms through the entry point that allocates no device memory."""

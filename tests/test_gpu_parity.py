@@ -238,6 +238,30 @@ def test_solve_mixed_matches_lu(setup, precision):
         assert eu <= 1e-8 and ep <= 1e-8, (s, eu, ep)
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_solve_multigrid_matches_lu(setup, precision):
+    """Multigrid blocks (one aggregation V-cycle on the complex velocity block, one on
+    the pressure Laplacian) at restart 40, with the steady systems' Schur block taking
+    the Laplacian term at the case's largest frequency: modes within 1e-10 (FP64) or
+    1e-8 (mixed) of the LU solution, like the polynomial blocks."""
+    from paper_2009_06725_amd import scvs
+    c, asm, m = setup["case"], setup["asm"], setup["m"]
+    u_o, p_o = _lu(setup)
+    g = gpu_dirichlet(m, c, torch)
+    wmax = float(np.abs(c["omega"]).max())
+    opts = scvs.default_opts(rtol=1e-13 if precision == 0 else 1e-12, precision=precision, vel_block=1,
+                             pres_block=1, restart=40, steady_schur_omega=wmax)
+    u, p, rep = m.solve(c["omega"], c["traction"], g, opts=opts)
+    u, p = u.cpu().numpy(), p.cpu().numpy()
+    print("[gpu]", setup["name"], f"multigrid precision {precision} iterations", [r.iterations for r in rep],
+          flush=True)
+    tol = 1e-10 if precision == 0 else 1e-8
+    for s in range(len(c["omega"])):
+        assert rep[s].status == 0, (s, rep[s].status, rep[s].rel_residual)
+        eu, ep = rel_l2(asm, u[s], u_o[s], p[s], p_o[s])
+        assert eu <= tol and ep <= tol, (s, eu, ep)
+
+
 def test_orthogonalization_variants_agree(setup):
     """Lagged (DCGS2) and classical two-pass Gram-Schmidt give the same modes."""
     from paper_2009_06725_amd import scvs

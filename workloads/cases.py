@@ -118,3 +118,31 @@ def vessel_tree_case(h: float = 0.25, generations: int = 3, n_harm: int = 2, see
     """Bifurcating tree (radii shrinking by sqrt 2 per generation, planes turned 90 degrees), T = 1."""
     from .meshes import vessel_tree_mesh
     return vessel_case(vessel_tree_mesh(h, generations), n_harm, seed_wave, 1.0)
+
+
+# ---- the vessel-network workloads at full size ----
+
+def tree_case(n_tets: int = 12_000_000, generations: int = 3, n_harm: int = 64, seed_wave: int = 5) -> dict:
+    """Precision-at-scale workload: a 3-generation tree (7 bifurcations, radii
+    shrinking by sqrt 2 per generation) of about n_tets tets, one seeded waveform
+    with n_harm harmonics plus the mean, T = 1."""
+    from .meshes import vessel_tree_mesh_for_tets
+    return vessel_case(vessel_tree_mesh_for_tets(n_tets, generations), n_harm, seed_wave, 1.0)
+
+
+def y_cases(n_tets: int, n_cases: int = 12, n_harm: int = 32, seed: int = 3) -> list:
+    """Batching workload on one Y-bifurcation of about n_tets tets: n_cases cases,
+    each with its own seeded waveform (n_harm harmonics plus the mean) and its own
+    period T ~ U[0.8, 1.2]. All cases share the mesh object."""
+    from .meshes import y_bifurcation_mesh_for_tets
+    from .waveforms import period_set
+    mesh = y_bifurcation_mesh_for_tets(n_tets)
+    periods = period_set(n_cases, seed)
+    coef = harmonic_coefficients(n_harm, seed, n_waves=n_cases)
+    out = []
+    for i in range(n_cases):
+        c = vessel_case(mesh, n_harm, seed, float(periods[i]))
+        c["inlet_amp"] = coef[i]
+        c["name"] = f"{mesh.name}_case{i}"
+        out.append(c)
+    return out

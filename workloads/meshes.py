@@ -242,6 +242,50 @@ for _p in ((0, 1, 2), (0, 2, 1), (1, 0, 2), (1, 2, 0), (2, 0, 1), (2, 1, 0)):
 _KUHN = np.array(_KUHN)
 
 
+def _inside_grid(segments, h: float):
+    """Boolean grid of the cubes (side h) whose centre lies inside the union of
+    capped cylinders and junction spheres; returns (inside, origin). Each
+    segment is evaluated only on the sub-grid of its own bounding box."""
+    lo = np.min([np.minimum(s["a"], s["b"]) - s["r"] for s in segments], 0) - h
+    hi = np.max([np.maximum(s["a"], s["b"]) + s["r"] for s in segments], 0) + h
+    lo[2] = 0.0  # the inlet starts on z = 0
+    n = np.ceil((hi - lo) / h).astype(int)
+    inside = np.zeros(n, bool)
+    for s in segments:
+        a, b, r = np.asarray(s["a"], float), np.asarray(s["b"], float), float(s["r"])
+        shapes = [("cyl", a, b)]
+        for end, pt in (("a", a), ("b", b)):
+            if s.get(end + "_role", "inner") == "inner":
+                shapes.append(("sph", pt, pt))
+        for kind, p0, p1 in shapes:
+            blo = np.maximum(np.floor((np.minimum(p0, p1) - r - lo) / h).astype(int) - 1, 0)
+            bhi = np.minimum(np.ceil((np.maximum(p0, p1) + r - lo) / h).astype(int) + 1, n)
+            if np.any(bhi <= blo):
+                continue
+            ax = [lo[d] + h * (np.arange(blo[d], bhi[d]) + 0.5) for d in range(3)]
+            X, Y, Z = np.meshgrid(*ax, indexing="ij")
+            P = np.stack([X.ravel(), Y.ravel(), Z.ravel()], 1)
+            if kind == "cyl":
+                f = _capped_cylinder_sdf(P, p0, p1, r)
+            else:
+                f = np.linalg.norm(P - p0, axis=1) - r
+            sub = inside[blo[0]:bhi[0], blo[1]:bhi[1], blo[2]:bhi[2]]
+            sub |= (f < 0.0).reshape(sub.shape)
+    return inside, lo
+
+
+# cube faces in corner bits (x=1, y=2, z=4): (axis, side, the four corners in the order
+# min, a, max, b around the face). With the Kuhn split every face is cut along its
+# min-max diagonal, so its two boundary triangles are (min, a, max) and (min, max, b).
+_CUBE_FACES = []
+for _ax in range(3):
+    _o = [d for d in range(3) if d != _ax]
+    for _side in (0, 1):
+        _base = _side << _ax
+        _c = [_base, _base | (1 << _o[0]), _base | (1 << _o[0]) | (1 << _o[1]), _base | (1 << _o[1])]
+        _CUBE_FACES.append((_ax, _side, _c))
+
+
 def vessel_mesh(segments, h: float, name: str):
     """Tet mesh of a union of cylinders. ``segments`` is a list of dicts with
     keys a, b (axis end points), r (radius) and role ('inlet', 'outlet' or
@@ -251,34 +295,25 @@ def vessel_mesh(segments, h: float, name: str):
     plane, so an inlet segment starting on it has a flat inlet); a cube is kept
     when its centre lies inside the union, only the largest face-connected set
     of cubes is kept, and each cube is split into six tets along one diagonal,
-    which makes the mesh conforming. Tags: 1 = inlet (facets on the inlet
-    segment's start plane), 2 + k = outlet of the k-th outlet segment (facets
-    within one cube of its end plane), 3 is never used for outlets; walls are
-    tag 3 and outlets are numbered from 4 when there are several."""
+    which makes the mesh conforming. The boundary facets are the cube faces
+    between a kept and a dropped cube, two triangles each, along the diagonal
+    the split uses. Tags: 1 = inlet (facets on the inlet segment's start
+    plane), 2 + k = outlet of the k-th outlet segment (facets within one cube
+    of its end plane), 3 is never used for outlets; walls are tag 3 and
+    outlets are numbered from 4 when there are several."""
     from scipy.ndimage import label
-    pts_lo = np.min([np.minimum(s["a"], s["b"]) - s["r"] for s in segments], 0) - h
-    pts_hi = np.max([np.maximum(s["a"], s["b"]) + s["r"] for s in segments], 0) + h
-    pts_lo[2] = 0.0  # the inlet starts on z = 0
-    n = np.ceil((pts_hi - pts_lo) / h).astype(int)
-    ii, jj, kk = np.meshgrid(np.arange(n[0]), np.arange(n[1]), np.arange(n[2]), indexing="ij")
-    centers = pts_lo + h * (np.stack([ii, jj, kk], -1).reshape(-1, 3) + 0.5)
-    sdf = np.full(centers.shape[0], np.inf)
-    for s in segments:
-        sdf = np.minimum(sdf, _capped_cylinder_sdf(centers, np.asarray(s["a"], float), np.asarray(s["b"], float),
-                                                   s["r"]))
-        for end in ("a", "b"):
-            if s.get(end + "_role", "inner") == "inner":
-                sdf = np.minimum(sdf, np.linalg.norm(centers - np.asarray(s[end], float), axis=1) - s["r"])
-    inside = (sdf < 0.0).reshape(n)
+    inside, pts_lo = _inside_grid(segments, h)
+    n = np.array(inside.shape)
     lab, nlab = label(inside)  # face connectivity (6-neighbourhood)
     sizes = np.bincount(lab.ravel())
     sizes[0] = 0
     keep = lab == np.argmax(sizes)
+    del lab
     hi, hj, hk = np.nonzero(keep)
     # corner vertex ids on the (n+1)^3 grid, compacted in lexicographic order
     nn = n + 1
     corners = np.stack([((hi + ((c >> 0) & 1)) * nn[1] + hj + ((c >> 1) & 1)) * nn[2] + hk + ((c >> 2) & 1)
-                        for c in range(8)], 1)
+                        for c in range(8)], 1).astype(np.int64)
     used, inv = np.unique(corners, return_inverse=True)
     corners = inv.reshape(corners.shape)
     gi = used // (nn[1] * nn[2])
@@ -286,7 +321,35 @@ def vessel_mesh(segments, h: float, name: str):
     gk = used % nn[2]
     xyz = pts_lo + h * np.stack([gi, gj, gk], 1).astype(float)
     cells = corners[:, _KUHN].reshape(-1, 4)
-    F = _boundary_faces_3d(cells, xyz)
+    # boundary facets: faces towards a dropped (or outside) cube, oriented outward
+    pad = np.zeros(n + 2, bool)
+    pad[1:-1, 1:-1, 1:-1] = keep
+    F = []
+    for ax, side, c in _CUBE_FACES:
+        off = [0, 0, 0]
+        off[ax] = 1 if side else -1
+        nb = pad[1 + off[0] + hi, 1 + off[1] + hj, 1 + off[2] + hk]
+        sel = ~nb
+        q = corners[sel][:, c]  # [m, 4]: min, a, max, b
+        t1 = q[:, [0, 1, 2]]
+        t2 = q[:, [0, 2, 3]]
+        F.append(np.concatenate([t1, t2], 0))
+    F = np.concatenate(F, 0)
+    # outward orientation from the geometry (the cube centre lies inside)
+    a, b, cc = xyz[F[:, 0]], xyz[F[:, 1]], xyz[F[:, 2]]
+    nrm = np.cross(b - a, cc - a)
+    mid = (a + b + cc) / 3.0
+    # the cube a facet came from: its centre is half a cube behind the facet
+    cen_all = []
+    for ax, side, c in _CUBE_FACES:
+        off = np.zeros(3)
+        off[ax] = 1 if side else -1
+        nb = pad[1 + int(off[0]) + hi, 1 + int(off[1]) + hj, 1 + int(off[2]) + hk]
+        m = int(np.count_nonzero(~nb))
+        cen_all.append(np.repeat(-off[None, :], 2 * m, 0))
+    back = np.concatenate(cen_all, 0)  # points from the facet into its cube
+    inward = np.einsum("ij,ij->i", nrm, back) > 0
+    F[inward] = F[inward][:, [0, 2, 1]]
     tags = np.full(F.shape[0], WALL, np.int32)
     fx = xyz[F]  # [nf, 3, 3]
     outs = [s for s in segments if s["role"] == "outlet"]
@@ -364,3 +427,26 @@ def y_bifurcation_mesh(h: float, radii=(1.0, 0.7, 0.7)) -> Mesh:
 
 def vessel_tree_mesh(h: float, generations: int = 3) -> Mesh:
     return vessel_mesh(vessel_tree_segments(generations), h, f"tree{generations}_h{h:g}")
+
+
+def _h_for_tets(make, n_tets: int, h0: float) -> float:
+    """Cube side h for about n_tets tets: one trial mesh at h0, then the count
+    scales as h^-3 (the domain volume is fixed)."""
+    trial = make(h0)
+    return h0 * (trial.nc / float(n_tets)) ** (1.0 / 3.0)
+
+
+def y_bifurcation_mesh_for_tets(n_tets: int) -> Mesh:
+    """Y-bifurcation (radii 1.0/0.7/0.7) with about n_tets tets."""
+    h = _h_for_tets(y_bifurcation_mesh, n_tets, 0.1)
+    m = y_bifurcation_mesh(h)
+    m.name = f"ybif_{m.nc}"
+    return m
+
+
+def vessel_tree_mesh_for_tets(n_tets: int, generations: int = 3) -> Mesh:
+    """Bifurcating tree with about n_tets tets."""
+    h = _h_for_tets(lambda hh: vessel_tree_mesh(hh, generations), n_tets, 0.08)
+    m = vessel_tree_mesh(h, generations)
+    m.name = f"tree{generations}_{m.nc}"
+    return m
