@@ -1,20 +1,27 @@
 """Benchmark of the spectral Stokes hot path on one MI355X.
 
-Workload (N=1): straight pipe R=1, L=10 with ~200k curved quadratic tets
-(~0.88M complex unknowns per mode), Womersley flow-rate inlet with 16 seeded
-harmonics plus the mean: 17 mode systems per step.
+Workloads (N=1):
+* tree (default): the 3-generation vessel tree (7 bifurcations, radii
+  shrinking by sqrt 2 per generation) with ~12M tets (~52M complex unknowns
+  per mode) and one seeded waveform of 64 harmonics plus the mean: 65 mode
+  systems. They are solved in waves of `--batch` systems (default 2; memory:
+  one FP64 Krylov basis of restart 40 is ~35 GB per system), and one step is
+  one wave: system k belongs to wave k mod n_waves, so every wave mixes low
+  and high modes, and the steps run through the waves in turn.
+* pipe: straight pipe R=1, L=10 with ~200k curved quadratic tets (~0.88M
+  complex unknowns per mode), 16 harmonics plus the mean; one step = all 17.
 
 Per-mesh setup (ingest, assembly of the mode-independent matrices, the
 preconditioner's multigrid hierarchies) runs once and is reported separately.
-One step = per-mode right-hand sides + batched block-preconditioned GMRES for
-all 17 modes to the relative residual `--rtol` + time synthesis of velocity
-and pressure at 64 instants. During the timed steps every library kernel launch
-is bracketed by HIP events on the stream it runs on; the dominant kernel's
-algorithmic bytes per launch divided by its mean launch time gives the
-roofline entry. The CPU baseline times the oracle (sparse LU of one mode) on
-a short pipe segment of the same mesh size h and scales it to the full
-problem linearly in unknowns (optimistic for the CPU: LU fill grows faster).
-Prints one JSON line.
+One step = per-mode right-hand sides + batched block-preconditioned GMRES to
+the relative residual `--rtol` + time synthesis of the step's modes. During
+the timed steps every library kernel launch is bracketed by HIP events on the
+stream it runs on; the dominant kernel's algorithmic bytes per launch divided
+by its mean launch time gives the roofline entry. The CPU baseline times the
+oracle (assembly + sparse LU per mode) in a process pool over the host's cores
+on small replicas of the workload and extrapolates to the full size with the
+LU cost exponent measured between the replicas (labelled as such). Prints one
+JSON line.
 """
 from __future__ import annotations
 
@@ -40,18 +47,21 @@ def parse(argv=None):
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--tets", type=int, default=200000)
-    ap.add_argument("--harmonics", type=int, default=16)
+    ap.add_argument("--workload", choices=["tree", "pipe"], default="tree")
+    ap.add_argument("--tets", type=int, default=None, help="default: 12,000,000 (tree), 200,000 (pipe)")
+    ap.add_argument("--harmonics", type=int, default=None, help="default: 64 (tree), 16 (pipe)")
+    ap.add_argument("--batch", type=int, default=None,
+                    help="systems per step (a wave); default: 6 (tree), all (pipe)")
     ap.add_argument("--rtol", type=float, default=4e-12,
                     help="relative residual; 4e-12 keeps the modes within 1e-8 of the reference here")
-    ap.add_argument("--restart", type=int, default=220)
+    ap.add_argument("--restart", type=int, default=40)
     ap.add_argument("--cheb-vel", type=int, default=12)
     ap.add_argument("--cheb-pres", type=int, default=50)
     ap.add_argument("--cheb-ratio", type=float, default=300.0,
                     help="the polynomials target [lambda_max/ratio, lambda_max] of the Jacobi-scaled blocks")
     ap.add_argument("--cheb-ratio-pres", type=float, default=1000.0,
                     help="interval ratio of the pressure polynomial (0: --cheb-ratio)")
-    ap.add_argument("--ntimes", type=int, default=64)
+    ap.add_argument("--ntimes", type=int, default=None, help="synthesis instants; default 16 (tree), 64 (pipe)")
     ap.add_argument("--precision", choices=["fp64", "mixed", "mixed32"], default="mixed",
                     help="mixed: FP32 operator and velocity block in FP64 refinement; mixed32: also an FP32 "
                          "Krylov basis (FP64 arithmetic)")
@@ -61,9 +71,9 @@ def parse(argv=None):
                     help="three-element lumped model on the outlet instead of a traction-free outlet")
     ap.add_argument("--inner-rtol", type=float, default=3e-5,
                     help="mixed precision: end a cycle once its own residual fell by this factor")
-    ap.add_argument("--vel-block", choices=["cheb", "mg"], default="cheb",
+    ap.add_argument("--vel-block", choices=["cheb", "mg"], default="mg",
                     help="velocity block: Chebyshev polynomial of the real shift, or a multigrid V-cycle")
-    ap.add_argument("--pres-block", choices=["cheb", "mg"], default="cheb",
+    ap.add_argument("--pres-block", choices=["cheb", "mg"], default="mg",
                     help="pressure-Laplacian inverse in the Schur block: Chebyshev polynomial or multigrid")
     ap.add_argument("--mg-smooth", type=int, default=2, help="multigrid smoothing steps per side")
     ap.add_argument("--mg-ratio", type=float, default=10.0, help="multigrid smoother interval ratio")
@@ -73,12 +83,14 @@ def parse(argv=None):
                     help="0: two-pass classical Gram-Schmidt, 1: lagged second pass (DCGS2)")
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the plain per-mode FP64 GMRES comparator step")
+    ap.add_argument("--compare-systems", type=int, default=None,
+                    help="systems of the first wave the comparator solves one at a time; default 2 (tree), all (pipe)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--autotune", action="store_true",
                     help="let the library time its candidate restart lengths and Chebyshev degrees first "
                          "(untimed setup); the defaults are what it picks on this workload")
     ap.add_argument("--no-warm-start", action="store_true",
-                    help="skip the learned-warm-start leg (reported beside the plain-method headline)")
+                    help="skip the learned-warm-start leg (pipe workload; reported beside the headline)")
     ap.add_argument("--ws-periods", type=int, default=4,
                     help="training periods for the warm start (each gives one solve per harmonic)")
     ap.add_argument("--no-error-check", action="store_true",
@@ -86,7 +98,19 @@ def parse(argv=None):
     ap.add_argument("--verbose", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run plain 1 GiB device copies (for scaling rocprofv3 byte counters)")
-    return ap.parse_args(argv)
+    a = ap.parse_args(argv)
+    tree = a.workload == "tree"
+    if a.tets is None:
+        a.tets = 12_000_000 if tree else 200_000
+    if a.harmonics is None:
+        a.harmonics = 64 if tree else 16
+    if a.ntimes is None:
+        a.ntimes = 16 if tree else 64
+    if a.batch is None:
+        a.batch = 2 if tree else 0
+    if a.compare_systems is None:
+        a.compare_systems = 2 if tree else 0
+    return a
 
 
 def solver_opts(args):
@@ -138,21 +162,63 @@ def copy_calibration(gib: float = 1.0, reps: int = 5):
           flush=True)
 
 
-def cpu_baseline(h: float, full_ndof: int):
-    """The oracle (assembly + SuperLU) on one mode of a pipe segment with the
-    same mesh size h and length 0.3; mode-solves/s scaled by unknowns."""
+def _oracle_mode(job):
+    """One worker of the CPU baseline: the oracle's assembly and sparse LU of one
+    mode of a replica case (runs in a fresh single-threaded process)."""
+    kind, size, k = job
+    from threadpoolctl import threadpool_limits
     from oracle.solve import case_setup, solve_modes
-    c = cases.pipe_case(h=h, length=0.3, n_harm=1)
+    threadpool_limits(1)  # one core per process (the parent's BLAS pool is inherited by fork)
     t0 = time.perf_counter()
+    if kind == "tree":
+        c = cases.vessel_tree_case(h=size, generations=3, n_harm=max(k, 1))
+    else:
+        c = cases.pipe_case(h=size, length=0.3, n_harm=max(k, 1))
     asm, loads, wall, dirn, g = case_setup(c)
-    _, _, res, _ = solve_modes(asm, loads, wall, dirn, c["omega"][1:2], c["rho"], c["mu"], c["traction"][1:2], g[1:2])
-    dt = time.perf_counter() - t0
-    ndof = 3 * asm["n2"] + asm["nv"]
-    return {"value": (1.0 / dt) * ndof / full_ndof, "unit": "mode-solves/s", "cores": 1, "kind": "oracle",
-            "sample": f"one mode (W=8pi) of a pipe segment L=0.3 with the same h ({c['mesh'].nc} tets, "
-                      f"{ndof} unknowns): assembly + SuperLU in {dt:.1f}s on one core; rate scaled by "
-                      f"{ndof}/{full_ndof} unknowns (linear, optimistic for LU)",
-            "sample_seconds": dt, "sample_rel_residual": float(res[0])}
+    _, _, res, _ = solve_modes(asm, loads, wall, dirn, c["omega"][k:k + 1], c["rho"], c["mu"],
+                               c["traction"][k:k + 1], g[k:k + 1])
+    return (time.perf_counter() - t0, 3 * asm["n2"] + asm["nv"], float(res[0]))
+
+
+def cpu_baseline(workload: str, h_pipe: float, full_ndof: int):
+    """The oracle timed on the host: a pool of single-threaded processes, one per
+    core (at most 16), each solving one mode of a small replica of the workload
+    by assembly and sparse LU; two replica sizes give the LU cost exponent, which
+    extrapolates the rate to the full problem. Runs before the GPU is touched."""
+    import multiprocessing as mp
+    cores = max(1, min(os.cpu_count() or 1, 16))
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), "")
+    except OSError:
+        pass
+    sizes = (0.5, 0.42) if workload == "tree" else (h_pipe * 1.6, h_pipe * 1.25)
+    os.environ["OMP_NUM_THREADS"] = "1"
+    out = {}
+    with mp.get_context("fork").Pool(cores) as pool:
+        for size in sizes:
+            jobs = [(workload, size, 1 + (i % 8)) for i in range(cores)]
+            t0 = time.perf_counter()
+            r = pool.map(_oracle_mode, jobs)
+            wall = time.perf_counter() - t0
+            out[size] = (wall, r)
+    (w1, r1), (w2, r2) = out[sizes[0]], out[sizes[1]]
+    n1, n2 = r1[0][1], r2[0][1]
+    t1 = float(np.mean([x[0] for x in r1]))
+    t2 = float(np.mean([x[0] for x in r2]))
+    expo = float(np.log(t2 / t1) / np.log(n2 / n1)) if n2 > n1 and t2 > t1 else 2.0
+    rate2 = cores / w2  # mode-solves/s of the larger replica on all cores
+    full = rate2 * (n2 / float(full_ndof)) ** expo
+    return {"value": full, "unit": "mode-solves/s", "cores": cores, "kind": "oracle",
+            "cpu_model": model, "nproc": os.cpu_count(),
+            "sample": f"{workload} replicas of {n1} and {n2} unknowns: one mode per process on {cores} "
+                      f"single-threaded processes, oracle assembly + SuperLU per mode ({t1:.1f}s and {t2:.1f}s "
+                      f"per mode); measured rate {rate2:.3g} mode-solves/s on the larger replica, "
+                      f"extrapolated to {full_ndof} unknowns with the measured LU time exponent {expo:.2f}",
+            "replica_mode_solves_per_s": rate2, "replica_unknowns": int(n2), "lu_time_exponent": expo,
+            "extrapolated": True, "sample_seconds": round(w1 + w2, 1),
+            "max_rel_residual": max(x[2] for x in r1 + r2)}
 
 
 def warm_start_leg(args, case, m, g, opts, ns, ur, pr):
@@ -231,6 +297,13 @@ def warm_start_leg(args, case, m, g, opts, ns, ur, pr):
     return res
 
 
+def rel_mass_l2(m, du, dp, ur, pr):
+    """Relative L2(Omega) errors per mode (mass-weighted: u^H (I x M) u, p^H Mp p)."""
+    dun, dpn = m.mode_norms(du, dp)
+    run, rpn = m.mode_norms(ur, pr)
+    return np.sqrt(dun / np.maximum(run, 1e-300)), np.sqrt(dpn / np.maximum(rpn, 1e-300))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -240,13 +313,27 @@ def main():
     if args.copy_calibration:
         copy_calibration()
         return
+    tree = args.workload == "tree"
+    t_start = time.perf_counter()
+    if tree:
+        case = cases.tree_case(n_tets=args.tets, n_harm=args.harmonics)
+        h_pipe = 0.0
+    else:
+        case = cases.pipe_case(n_tets=args.tets, n_harm=args.harmonics)
+        h_pipe = float(case["mesh"].name.split("_h")[1].split("_")[0])
+    mesh = case["mesh"]
+    t_mesh = time.perf_counter() - t_start
+    log(f"mesh {mesh.name}: {mesh.nc} tets, {mesh.nv} vertices ({t_mesh:.1f}s)")
+    cpu = None
+    if not args.no_cpu_baseline:
+        # the oracle on the host cores, before anything touches the GPU (the pool forks)
+        log("cpu baseline (oracle, process pool) ...")
+        est_ndof = int(3 * 7.8 * mesh.nv + mesh.nv) if tree else int(3 * 7.6 * mesh.nv + mesh.nv)
+        cpu = cpu_baseline(args.workload, h_pipe, est_ndof)
+        log(f"cpu baseline: {cpu['sample']}")
     import torch
     from paper_2009_06725_amd import scvs
 
-    case = cases.pipe_case(n_tets=args.tets, n_harm=args.harmonics)
-    mesh = case["mesh"]
-    h = float(mesh.name.split("_h")[1].split("_")[0])
-    log(f"mesh {mesh.name}: {mesh.nc} tets, {mesh.nv} vertices")
     ctx = scvs.Context(0)
     t0 = time.perf_counter()
     m = scvs.Mesh.from_workload(ctx, mesh)
@@ -263,31 +350,46 @@ def main():
     torch.cuda.synchronize()
     t_ingest = time.perf_counter() - t0
     info = m.info
+    if cpu is not None:
+        cpu["value"] *= 1.0  # (rate already for the estimated size; rescale to the exact one below)
+        ratio = (cpu["replica_unknowns"] / float(info.ndof)) ** cpu["lu_time_exponent"]
+        cpu["value"] = cpu["replica_mode_solves_per_s"] * ratio
+        cpu["sample"] = cpu["sample"].split(", extrapolated to")[0] + (
+            f", extrapolated to {info.ndof} unknowns with the measured LU time exponent {cpu['lu_time_exponent']:.2f}")
     ns = len(case["omega"])
     nodes = m.export(scvs.X_DIRNODES)
     xyz = m.export(scvs.X_NODEXYZ)[nodes]
     g = np.zeros((ns, nodes.size, 3), np.complex128)
-    for s, w in enumerate(case["omega"]):
-        g[s] = case["inlet_amp"][s] * case["inlet"](xyz, float(w))
+    for s_, w in enumerate(case["omega"]):
+        g[s_] = case["inlet_amp"][s_] * case["inlet"](xyz, float(w))
     g = torch.from_numpy(g).to("cuda")
-    u = torch.empty((ns, info.n2, 3), dtype=torch.complex128, device="cuda")
-    p = torch.empty((ns, info.nv), dtype=torch.complex128, device="cuda")
+    trac = np.asarray(case["traction"]).reshape(ns, -1)
+    # waves: system k goes to wave k mod n_waves (each wave mixes low and high modes)
+    B = ns if args.batch <= 0 or args.batch >= ns else args.batch
+    n_waves = (ns + B - 1) // B
+    waves = [np.arange(w, ns, n_waves) for w in range(n_waves)]
+    bmax = max(len(w) for w in waves)
+    u = torch.empty((bmax, info.n2, 3), dtype=torch.complex128, device="cuda")
+    p = torch.empty((bmax, info.nv), dtype=torch.complex128, device="cuda")
     times = np.arange(args.ntimes) * case["period"] / args.ntimes
     ut = torch.empty((args.ntimes, info.n2 * 3), dtype=torch.float64, device="cuda")
     pt = torch.empty((args.ntimes, info.nv), dtype=torch.float64, device="cuda")
     opts = solver_opts(args)
-    log(f"n2={info.n2} ndof={info.ndof} nnz_s2={info.nnz_s2} ingest+assembly {t_ingest:.2f}s")
+    if args.steady_schur_omega < 0:
+        opts.steady_schur_omega = float(np.abs(case["omega"]).max())
+    log(f"n2={info.n2} ndof={info.ndof} nnz_s2={info.nnz_s2} ingest+assembly {t_ingest:.2f}s; "
+        f"{ns} systems in {n_waves} waves of <= {bmax}")
     tuned = None
     if args.autotune:
         # untimed setup: the library times its candidate settings on these systems
         log("autotune ...")
         t0 = time.perf_counter()
-        best, best_ms = m.autotune(case["omega"], case["traction"], g, base=opts)
+        w0 = waves[0]
+        best, best_ms = m.autotune(case["omega"][w0], trac[w0], g[w0].contiguous(), base=opts)
         tuned = {"restart": best.restart, "cheb_vel": best.cheb_vel, "cheb_pres": best.cheb_pres,
                  "tuning_seconds": round(time.perf_counter() - t0, 1), "candidate_ms": round(best_ms, 1)}
         opts = best
         log(f"autotune: {tuned}")
-
     # per-mesh setup, timed once and reported (not part of a step): the multigrid
     # hierarchies of the preconditioner are built from the assembled matrices
     hier = None
@@ -298,33 +400,42 @@ def main():
         t_mg = time.perf_counter() - t0
         log(f"multigrid hierarchies in {t_mg:.2f}s: velocity {hier['velocity']} pressure {hier['pressure']}")
 
-    def step():
-        _, _, rep = m.solve(case["omega"], case["traction"], g, u=u, p=p, opts=opts)
-        scvs.synthesize(ctx, case["omega"], u, times, out=ut)
-        scvs.synthesize(ctx, case["omega"], p, times, out=pt)
-        return rep
+    def step(i):
+        sel = waves[i % n_waves]
+        k = len(sel)
+        gw = g[sel].contiguous() if k < ns else g
+        _, _, rep = m.solve(case["omega"][sel], trac[sel], gw, u=u[:k], p=p[:k], opts=opts)
+        scvs.synthesize(ctx, case["omega"][sel], u[:k], times, out=ut)
+        scvs.synthesize(ctx, case["omega"][sel], p[:k], times, out=pt)
+        return rep, sel
 
     for i in range(args.warmup):
         t0 = time.perf_counter()
-        rep = step()
+        rep, sel = step(i)
         torch.cuda.synchronize()
-        log(f"warmup {i}: {time.perf_counter() - t0:.2f}s iterations {[r.iterations for r in rep]}")
+        log(f"warmup {i}: {time.perf_counter() - t0:.2f}s systems {list(sel)} iterations {[r.iterations for r in rep]}")
     ctx.profile(True)
     ctx.profile_read()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     reps = []
+    solved = 0
     for i in range(args.steps):
-        reps.append(step())
+        rep, sel = step(i)
         torch.cuda.synchronize()
-        log(f"step {i} done at {time.perf_counter() - t0:.2f}s")
+        reps.append((rep, sel))
+        solved += len(sel)
+        log(f"step {i} done at {time.perf_counter() - t0:.2f}s systems {list(sel)} "
+            f"iterations {[r.iterations for r in rep]}")
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     stats = ctx.profile_read()
     ctx.profile(False)
-    rep = reps[-1]
-    iters = [r.iterations for r in rep]
-    conv = all(r.status == 0 for r in rep)
+    conv = all(r.status == 0 for rep, _ in reps for r in rep)
+    iters_by_system = {}
+    for rep, sel in reps:
+        for r, k in zip(rep, sel):
+            iters_by_system[int(k)] = r.iterations
 
     def roof(name):
         n, ms, by = stats[name]
@@ -340,9 +451,14 @@ def main():
     dominant = max(stats, key=lambda k: stats[k][1])
     kernels = {k: {"launches": v[0], "ms": round(v[1], 3), "GB/s": round(v[2] / (v[1] / 1e3) / 1e9, 1) if v[1] else None}
                for k, v in sorted(stats.items(), key=lambda kv: -kv[1][1])}
+    if tree:
+        wl = (f"3-generation vessel tree (7 bifurcations, radii / sqrt 2 per generation), {mesh.nc} P2/P1 tets, "
+              f"{ns} modes ({ns - 1} harmonics + mean) in waves of <= {bmax} systems (one wave per step)")
+    else:
+        wl = f"pipe R=1 L=10, {mesh.nc} curved P2/P1 tets, {ns} modes ({ns - 1} harmonics + mean)"
     out = {
         "metric": "mode-solves/s",
-        "value": ns * args.steps / dt,
+        "value": solved / dt,
         "unit": "mode-solves/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -351,105 +467,111 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"fp64": "c128", "mixed": "c64 operator and preconditioner polynomials / c128 Krylov basis, Schur scaling, refinement",
-                  "mixed32": "c64 operator, preconditioner polynomials and Krylov basis storage / c128 arithmetic, "
+        "dtype": {"fp64": "c128", "mixed": "c64 operator and preconditioner / c128 Krylov basis, Schur scaling, "
+                                           "refinement",
+                  "mixed32": "c64 operator, preconditioner and Krylov basis storage / c128 arithmetic, "
                              "Schur scaling, refinement"
                   }[args.precision],
         "data": "synthetic",
-        "config": {"workload": f"pipe R=1 L=10, {mesh.nc} curved P2/P1 tets, {ns} modes (16 harmonics + mean)",
-                   "ndof": int(info.ndof), "modes": ns, "rtol": args.rtol, "restart": opts.restart,
-                   "cheb_vel": opts.cheb_vel, "cheb_pres": opts.cheb_pres, "cheb_ratio": opts.cheb_ratio,
-                   "cheb_ratio_pres": opts.cheb_ratio_pres,
-                   "autotuned": tuned,
-                   "orth": args.orth, "inner_rtol": args.inner_rtol, "precision": args.precision,
-                   "penalty": args.penalty,
+        "config": {"workload": wl, "ndof": int(info.ndof), "modes": ns, "systems_per_step": bmax, "waves": n_waves,
+                   "rtol": args.rtol, "restart": opts.restart,
+                   "velocity_block": "multigrid V-cycle" if opts.vel_block else f"Chebyshev degree {opts.cheb_vel}",
+                   "pressure_block": "multigrid V-cycle" if opts.pres_block else f"Chebyshev degree {opts.cheb_pres}",
+                   "mg_smooth": opts.mg_smooth, "mg_ratio": opts.mg_ratio,
+                   "steady_schur_omega": opts.steady_schur_omega,
+                   "autotuned": tuned, "orth": args.orth, "inner_rtol": args.inner_rtol,
+                   "precision": args.precision, "penalty": args.penalty,
                    "outlet": "traction-free" if wk is None else
                    {"lumped": "three-element", "rp": wk[0], "c": wk[1], "rd": wk[2]},
                    "ntimes": args.ntimes},
-        "dof_modes_per_s": info.ndof * ns * args.steps / dt,
-        "setup_seconds": {"ingest_and_assembly": round(t_ingest, 3), "multigrid_hierarchies": round(t_mg, 3)},
+        "dof_modes_per_s": info.ndof * solved / dt,
+        "setup_seconds": {"mesh_generation": round(t_mesh, 2), "ingest_and_assembly": round(t_ingest, 3),
+                          "multigrid_hierarchies": round(t_mg, 3)},
         "multigrid_levels": hier,
         "roofline": roof(dominant),
         "spmv_roofline": roof("k_full_apply32" if "k_full_apply32" in stats else "k_full_apply"),
         "converged": conv,
-        "iterations": iters,
+        "iterations": [iters_by_system[k] for k in sorted(iters_by_system)],
+        "iterations_systems": sorted(iters_by_system),
         "kernels": kernels,
     }
     # mode selection on this workload: a-priori truncation error of the boundary data
-    # (Eq. mode_error) against the a-posteriori change of each added mode
-    hn2, gn2 = m.boundary_norms(case["omega"], case["traction"], g)
-    un2, _ = m.mode_norms(u, p)
-    wk = np.where(np.asarray(case["omega"]) == 0.0, 1.0, 2.0)  # Parseval weights, two-sided modes
+    # (Eq. mode_error); the a-posteriori increments need every mode (one-wave workloads)
+    hn2, gn2 = m.boundary_norms(case["omega"], trac, g)
+    wts = np.where(np.asarray(case["omega"]) == 0.0, 1.0, 2.0)  # Parseval weights, two-sided modes
 
     def e_first(n):  # e_M when the first n modes are kept (relative to all ns modes)
         e2 = 0.0
         for q in (np.asarray(hn2), np.asarray(gn2)):
-            tot = float(np.sum(wk * q))
+            tot = float(np.sum(wts * q))
             if tot > 0:
-                e2 += float(np.sum(wk[n:] * q[n:])) / tot
+                e2 += float(np.sum(wts[n:] * q[n:])) / tot
         return float(np.sqrt(e2))
 
-    full = [e_first(n + 1) for n in range(ns)]
-    inc = scvs.mode_increments(case["omega"], un2)
     picks = {}
     for eps in (1e-1, 1e-2, 1e-3):
         oc, nc, ec = scvs.select_modes(case["omega"], hn2, gn2, eps, True)
         oa, na, ea = scvs.select_modes(case["omega"], hn2, gn2, eps, False)
         picks[f"{eps:g}"] = {"consecutive": int(nc), "by_amplitude": int(na),
                              "by_amplitude_modes": [int(k) for k in oa[:na]]}
-    out["mode_selection"] = {
-        "a_priori_error_first_n_modes": full,
-        "a_posteriori_increment_of_mode_n": [float(x) for x in inc],
-        "modes_needed": picks}
+    out["mode_selection"] = {"a_priori_error_first_n_modes": [e_first(n + 1) for n in range(ns)],
+                             "modes_needed": picks}
+    if n_waves == 1:
+        un2, _ = m.mode_norms(u, p)
+        out["mode_selection"]["a_posteriori_increment_of_mode_n"] = [
+            float(x) for x in scvs.mode_increments(case["omega"], un2)]
+    # the first wave again, kept for the error check, the comparator and the warm start
+    w0 = waves[0]
+    k0 = len(w0)
+    g0 = g[w0].contiguous() if k0 < ns else g
+    u0 = torch.empty((k0, info.n2, 3), dtype=torch.complex128, device="cuda")
+    p0 = torch.empty((k0, info.nv), dtype=torch.complex128, device="cuda")
+    m.solve(case["omega"][w0], trac[w0], g0, u=u0, p=p0, opts=opts)
+    ur = pr = None
     if not args.no_error_check:
         # error of the timed solution: against an FP64 solve to a 100x tighter residual
-        # (not below 1e-13, about where FP64 restarts stop gaining)
+        # (not below 1e-13, about where FP64 restarts stop gaining), in L2(Omega)
         rref = max(args.rtol * 1e-2, 1e-13)
-        ref = scvs.default_opts(rtol=rref, restart=opts.restart, cheb_vel=opts.cheb_vel,
-                                cheb_pres=opts.cheb_pres, cheb_ratio=opts.cheb_ratio,
-                                cheb_ratio_pres=opts.cheb_ratio_pres, precision=0,
-                                verbose=1 if args.verbose else 0)
-        ur = torch.empty_like(u)
-        pr = torch.empty_like(p)
-        log("error check: FP64 reference solve ...")
-        _, _, rep3 = m.solve(case["omega"], case["traction"], g, u=ur, p=pr, opts=ref)
-        eu = (torch.linalg.vector_norm((u - ur).reshape(ns, -1), dim=1) /
-              torch.linalg.vector_norm(ur.reshape(ns, -1), dim=1)).cpu().numpy()
-        ep = (torch.linalg.vector_norm(p - pr, dim=1) / torch.linalg.vector_norm(pr, dim=1)).cpu().numpy()
+        ref = solver_opts(args)
+        ref.rtol, ref.precision, ref.steady_schur_omega = rref, 0, opts.steady_schur_omega
+        ur = torch.empty_like(u0)
+        pr = torch.empty_like(p0)
+        log("error check: FP64 reference solve of the first wave ...")
+        _, _, rep3 = m.solve(case["omega"][w0], trac[w0], g0, u=ur, p=pr, opts=ref)
+        eu, ep = rel_mass_l2(m, (u0 - ur).contiguous(), (p0 - pr).contiguous(), ur, pr)
         out["error_vs_tight_reference"] = {
-            "reference": f"FP64 path, rtol {rref:g}", "norm": "relative Euclidean per mode",
+            "reference": f"FP64 path, rtol {rref:g}", "norm": "relative L2(Omega) per mode (mass-weighted)",
+            "systems": [int(k) for k in w0],
             "max_u": float(eu.max()), "max_p": float(ep.max()),
             "per_mode_u": [float(x) for x in eu], "per_mode_p": [float(x) for x in ep],
             "reference_converged": all(r.status == 0 for r in rep3)}
-    if not args.no_warm_start:
-        out["warm_started"] = warm_start_leg(args, case, m, g, opts, ns, ur if not args.no_error_check else None,
-                                             pr if not args.no_error_check else None)
+    if not tree and not args.no_warm_start:
+        out["warm_started"] = warm_start_leg(args, case, m, g, opts, ns, ur, pr)
     if not args.no_compare:
         # comparator: plain per-mode FP64 GMRES (one system at a time, same
-        # preconditioner, restart and tolerance, two-pass Gram-Schmidt)
-        plain = scvs.default_opts(rtol=args.rtol, restart=opts.restart, cheb_vel=opts.cheb_vel,
-                                  cheb_pres=opts.cheb_pres, cheb_ratio=opts.cheb_ratio,
-                                cheb_ratio_pres=opts.cheb_ratio_pres, precision=0, max_batch=1,
-                                  orth=0,
-                                  verbose=1 if args.verbose else 0)
-        u2 = torch.empty_like(u)
-        p2 = torch.empty_like(p)
-        log("comparator: plain per-mode FP64 GMRES ...")
+        # preconditioner, restart and tolerance, two-pass Gram-Schmidt) on systems
+        # of the first wave
+        nc = k0 if args.compare_systems <= 0 else min(args.compare_systems, k0)
+        sel = np.array(w0[:nc])
+        plain = solver_opts(args)
+        plain.precision, plain.max_batch, plain.orth = 0, 1, 0
+        plain.steady_schur_omega = opts.steady_schur_omega
+        u2 = torch.empty((nc, info.n2, 3), dtype=torch.complex128, device="cuda")
+        p2 = torch.empty((nc, info.nv), dtype=torch.complex128, device="cuda")
+        log(f"comparator: plain per-mode FP64 GMRES on systems {list(sel)} ...")
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        _, _, rep2 = m.solve(case["omega"], case["traction"], g, u=u2, p=p2, opts=plain)
+        _, _, rep2 = m.solve(case["omega"][sel], trac[sel], g[sel].contiguous(), u=u2, p=p2, opts=plain)
         torch.cuda.synchronize()
         dtp = time.perf_counter() - t0
-        du = torch.linalg.vector_norm(u - u2) / torch.linalg.vector_norm(u2)
-        dp = torch.linalg.vector_norm(p - p2) / torch.linalg.vector_norm(p2)
-        out["plain_fp64_per_mode"] = {"mode_solves_per_s": ns / dtp, "seconds": dtp,
+        du, dpp = rel_mass_l2(m, (u0[:nc] - u2).contiguous(), (p0[:nc] - p2).contiguous(), u2, p2)
+        out["plain_fp64_per_mode"] = {"mode_solves_per_s": nc / dtp, "seconds": dtp, "systems": [int(k) for k in sel],
                                       "iterations": [r.iterations for r in rep2],
                                       "converged": all(r.status == 0 for r in rep2)}
-        out["speedup_vs_plain_fp64"] = (ns / dtp and out["value"] / (ns / dtp))
-        out["rel_diff_vs_plain_fp64"] = {"u": float(du), "p": float(dp)}
-    if not args.no_cpu_baseline:
-        log("cpu baseline (oracle) ...")
-        out["cpu_baseline"] = cpu_baseline(h, int(info.ndof))
+        out["speedup_vs_plain_fp64"] = out["value"] / (nc / dtp)
+        out["rel_diff_vs_plain_fp64"] = {"u": float(du.max()), "p": float(dpp.max())}
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
 
 

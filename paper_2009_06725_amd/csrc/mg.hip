@@ -157,18 +157,27 @@ double diag_of(const HCsr& A, int64_t i) {
   return 0.0;
 }
 
-// Greedy aggregation on the strong couplings |a_ij| >= theta sqrt(a_ii a_jj) (i != j):
-// a node whose strong neighbours are all free starts an aggregate with them; a leftover
-// node joins the aggregate of its first aggregated strong neighbour; what is still
-// left starts aggregates with its free strong neighbours. Returns the aggregate of
-// every node and the count.
+// Greedy aggregation on the strong couplings: a node whose strong neighbours are all
+// free starts an aggregate with them; a leftover node joins the aggregate of its first
+// aggregated strong neighbour; what is still left starts aggregates with its free
+// strong neighbours. Strength: with theta > 0, |a_ij| >= theta sqrt(a_ii a_jj) (the
+// first aggregation, on the sparse linear-element operators); with theta < 0,
+// |a_ij| >= |theta| max_k |a_ik| over the row's off-diagonals (the deeper, denser
+// levels, where every single coupling is small against the diagonal). Returns the
+// aggregate of every node and the count.
 std::vector<int32_t> aggregate(const HCsr& A, double theta, int32_t& na) {
   const int64_t n = A.n;
-  std::vector<double> d(n);
-  for (int64_t i = 0; i < n; ++i) d[i] = std::fabs(diag_of(A, i));
+  std::vector<double> d(n), mx(n, 0.0);
+  for (int64_t i = 0; i < n; ++i) {
+    d[i] = std::fabs(diag_of(A, i));
+    for (int64_t k = A.ptr[i]; k < A.ptr[i + 1]; ++k)
+      if (A.col[k] != i) mx[i] = std::max(mx[i], std::fabs(A.a[k]));
+  }
   auto strong = [&](int64_t i, int64_t k) {
     const int32_t j = A.col[k];
-    return j != i && std::fabs(A.a[k]) >= theta * std::sqrt(d[i] * d[j]);
+    if (j == i) return false;
+    if (theta < 0.0) return mx[i] > 0.0 && std::fabs(A.a[k]) >= -theta * mx[i];
+    return std::fabs(A.a[k]) >= theta * std::sqrt(d[i] * d[j]);
   };
   std::vector<int32_t> agg(n, -1);
   na = 0;
@@ -312,9 +321,11 @@ void upload_transfer(MgLevel& L, const HCsr& P, hipStream_t s) {
 }
 
 // Aggregation levels from A down: appends levels and the transfers between them until a
-// level has at most `coarse_max` rows (it is then inverted densely). When the strong
-// couplings stop coarsening, every coupling counts as strong for that level.
+// level has at most `coarse_max` rows (it is then inverted densely). The first
+// aggregation uses symmetric strength theta, the deeper ones row-relative strength 0.25
+// (0.1 when that leaves the level nearly uncoarsened).
 void build_below(MgHier& H, HCsr A, int coarse_max, double theta, hipStream_t s) {
+  const size_t first_level = H.lv.size();
   for (;;) {
     H.lv.emplace_back();
     MgLevel& L = H.lv.back();
@@ -324,8 +335,10 @@ void build_below(MgHier& H, HCsr A, int coarse_max, double theta, hipStream_t s)
     }
     SCVS_REQUIRE(H.lv.size() < (size_t)MG_MAXLEV, SCVS_E_CAPACITY, "multigrid hierarchy too deep");
     int32_t na = 0;
-    std::vector<int32_t> agg = aggregate(A, theta, na);
-    if (na >= A.n * 0.85) agg = aggregate(A, 0.0, na);
+    // first aggregation of this hierarchy: symmetric strength; deeper: row-relative
+    const bool first = H.lv.size() == first_level + 1;
+    std::vector<int32_t> agg = aggregate(A, first ? theta : -0.25, na);
+    if (na >= A.n * 0.85) agg = aggregate(A, -0.1, na);  // more couplings count as strong
     SCVS_REQUIRE(na < A.n * 0.85 && na >= 1, SCVS_E_CAPACITY, "multigrid coarsening stalled");
     const HCsr P = smoothed_prolongator(A, agg, na);
     HCsr AP = spgemm(A, P);
