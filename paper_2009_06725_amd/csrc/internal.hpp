@@ -161,8 +161,24 @@ struct MgLevel {
   DBuf<float> pval32, rval32;
   double lam = 0.0;  // Gershgorin bound of D^-1 K (single-matrix hierarchies)
 };
+// Sliced rows of a level-0 operator for the wide row kernels: rows are ordered by
+// length (longest first, ties by index) inside windows of SELL_WIN consecutive rows
+// and cut into slices of SELL_C rows; entry t of the r-th row of slice s sits at
+// off[s] + t * SELL_C + r, so that one wavefront load of entry t covers SELL_C rows
+// in one contiguous run. Rows shorter than their slice are padded with their own
+// index and zero values. Values are filled per precision on first use.
+constexpr int SELL_C = 32, SELL_WIN = 512;
+struct Sell {
+  int64_t nslot = 0;  // slices * SELL_C
+  DBuf<int64_t> off;  // [slices + 1]
+  DBuf<int32_t> row;  // [nslot] row of each slot, -1 past the last row
+  DBuf<int32_t> col;  // [off[slices]]
+  DBuf<float> K32, M32;
+  DBuf<double> K, M;
+};
 struct MgHier {
   std::vector<MgLevel> lv;
+  Sell sell0;  // level 0's operator in sliced rows
   bool mass = false;
   DBuf<double2> cinv;  // single-matrix hierarchies: dense inverse of the coarsest level
   DBuf<float2> cinv32;
@@ -369,6 +385,8 @@ size_t mg_buffer_bytes(scvs_mesh m, int slots, size_t esize, bool vel, bool pres
 void mg_assign(scvs_mesh m, int slots, size_t esize, bool vel, bool pres, char* base, void* vel0, void* pres0,
                double* vlam, MgBufs& out);
 int mg_levels(scvs_mesh m, bool vel);
+// Level-0 values in sliced rows for the cycle's precision (FP32 when f32).
+void mg_sell_values(scvs_mesh m, bool f32, bool vel, bool pres, hipStream_t s);
 // Per system: smoother bounds of every velocity level and the coarsest level's dense inverse.
 void mg_prepare(scvs_mesh m, const Batch& b, double* lam, int slots, double2* inv, float2* inv32, hipStream_t s);
 int64_t mg_coarse_rows(scvs_mesh m);

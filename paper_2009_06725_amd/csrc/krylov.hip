@@ -1096,6 +1096,7 @@ int solve_systems(scvs_mesh m, int64_t nsys, const double* omega, const double* 
   size_t mg_extra = 0;
   if (vmg || pmg) {
     mg_setup(m, s);
+    mg_sell_values(m, mixed, vmg, pmg, s);
     const size_t nc2 = (size_t)mg_coarse_rows(m) * mg_coarse_rows(m);
     mg_extra = (vmg ? (size_t)DN * esz + nc2 * (sizeof(double2) + (mixed ? sizeof(float2) : 0)) : 0) +
                (pmg ? (size_t)m->nv * sizeof(double2) : 0) + mg_buffer_bytes(m, 1, esz, vmg, pmg) +

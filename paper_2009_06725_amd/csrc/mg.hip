@@ -19,13 +19,16 @@
 //   * pressure: the same aggregation on the assembled Laplacian L (no mass).
 // Smoothing is a Chebyshev iteration in D^-1 A with D the complex diagonal of
 // the level operator, on [lambda/ratio, lambda], lambda a Gershgorin bound of
-// |D^-1 A| per system and level; the coarsest level runs a longer Chebyshev
-// iteration in one workgroup. The hierarchy is built on the host once per
-// assembly and boundary-condition set and lives on the device.
+// |D^-1 A| per system and level; the coarsest level (at most MG_COARSE_MAX rows)
+// is solved with its dense inverse. The hierarchy is built on the host once per
+// assembly and boundary-condition set and lives on the device. Level 0 of both
+// hierarchies is also kept in sliced rows (Sell), which its smoothing and residual
+// kernels read: one lane per (row, system) walks the row with coalesced loads.
 //
 // Vectors of one level are interleaved [n_l][G]: pair p = (system index in the
 // batch) * PD + component (PD = dim for the velocity, 1 for the pressure), so
 // one column index gathers the values of every system and component at once.
+#include <algorithm>
 #include <thread>
 
 #include "internal.hpp"
@@ -371,6 +374,91 @@ void dense_inverse(std::vector<double>& a, int64_t n) {
 }  // namespace
 
 // Builds both hierarchies of a mesh (after assembly and boundary conditions).
+namespace {
+
+// Column indices of the sliced rows: thread per slot, entries of its row in order,
+// padding with the row's own index (the last slice's rows past n: column 0).
+__global__ void k_sell_col(const int64_t* __restrict__ ptr, const int32_t* __restrict__ col,
+                           const int64_t* __restrict__ off, const int32_t* __restrict__ row, int64_t nslot,
+                           int32_t* __restrict__ out) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= nslot) return;
+  const int64_t sl = q / SELL_C, e0 = off[sl] + q % SELL_C;
+  const int len = (int)((off[sl + 1] - off[sl]) / SELL_C);
+  const int32_t i = row[q];
+  const int64_t j0 = i >= 0 ? ptr[i] : 0, rl = i >= 0 ? ptr[i + 1] - j0 : 0;
+  for (int t = 0; t < len; ++t) out[e0 + (int64_t)t * SELL_C] = t < rl ? col[j0 + t] : (i >= 0 ? i : 0);
+}
+
+// Values of the sliced rows (zero on padding) from CSR values in the same pattern.
+template <class R>
+__global__ void k_sell_val(const int64_t* __restrict__ ptr, const R* __restrict__ a,
+                           const int64_t* __restrict__ off, const int32_t* __restrict__ row, int64_t nslot,
+                           R* __restrict__ out) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= nslot) return;
+  const int64_t sl = q / SELL_C, e0 = off[sl] + q % SELL_C;
+  const int len = (int)((off[sl + 1] - off[sl]) / SELL_C);
+  const int32_t i = row[q];
+  const int64_t j0 = i >= 0 ? ptr[i] : 0, rl = i >= 0 ? ptr[i + 1] - j0 : 0;
+  for (int t = 0; t < len; ++t) out[e0 + (int64_t)t * SELL_C] = t < rl ? a[j0 + t] : (R)0;
+}
+
+// The sliced-row layout of an n-row CSR pattern (host row pointers `ptr`, device
+// pointers and columns `dptr`, `dcol`); values are filled later by sell_fill.
+void build_sell(Sell& S, const std::vector<int64_t>& ptr, int64_t n, const int64_t* dptr, const int32_t* dcol,
+                hipStream_t s) {
+  const int64_t nsl = (n + SELL_C - 1) / SELL_C;
+  S.nslot = nsl * SELL_C;
+  std::vector<int32_t> row(S.nslot, -1);
+  const int64_t nwin = (n + SELL_WIN - 1) / SELL_WIN;
+  const int nt = host_threads();
+  std::vector<std::thread> th;
+  for (int t = 0; t < nt; ++t)
+    th.emplace_back([&, t] {
+      for (int64_t w = t; w < nwin; w += nt) {
+        const int64_t a = w * SELL_WIN, b = std::min(n, a + SELL_WIN);
+        int32_t* r = row.data() + a;
+        for (int64_t i = a; i < b; ++i) r[i - a] = (int32_t)i;
+        std::stable_sort(r, r + (b - a), [&](int32_t x, int32_t y) {
+          return ptr[x + 1] - ptr[x] > ptr[y + 1] - ptr[y];
+        });
+      }
+    });
+  for (auto& x : th) x.join();
+  std::vector<int64_t> off(nsl + 1, 0);
+  for (int64_t sl = 0; sl < nsl; ++sl) {
+    int64_t len = 0;  // windows are whole slices, so the first row is the longest
+    const int32_t i = row[sl * SELL_C];
+    if (i >= 0) len = ptr[i + 1] - ptr[i];
+    off[sl + 1] = off[sl] + len * SELL_C;
+  }
+  S.off.upload(off.data(), off.size(), s);
+  S.row.upload(row.data(), row.size(), s);
+  S.col.alloc((size_t)off[nsl]);
+  k_sell_col<<<(unsigned)((S.nslot + 255) / 256), 256, 0, s>>>(dptr, dcol, S.off, S.row, S.nslot, S.col);
+  launch_check(s);
+  SCVS_HIP(hipStreamSynchronize(s));  // row and off are host temporaries
+}
+
+// Fills (once per precision) the sliced values from CSR values K, M (M may be null).
+template <class R>
+void sell_fill(Sell& S, const int64_t* dptr, const R* K, const R* M, DBuf<R>& sK, DBuf<R>& sM, hipStream_t s) {
+  if (sK.p) return;
+  const size_t ne = S.col.n;
+  const unsigned nb = (unsigned)((S.nslot + 255) / 256);
+  sK.alloc(ne);
+  k_sell_val<R><<<nb, 256, 0, s>>>(dptr, K, S.off, S.row, S.nslot, sK);
+  launch_check(s);
+  if (M) {
+    sM.alloc(ne);
+    k_sell_val<R><<<nb, 256, 0, s>>>(dptr, M, S.off, S.row, S.nslot, sM);
+    launch_check(s);
+  }
+}
+
+}  // namespace
+
 void mg_setup(scvs_mesh m, hipStream_t s) {
   if (m->mg && m->mg->gen == m->generation) return;
   auto mg = std::make_unique<MgData>();
@@ -414,6 +502,7 @@ void mg_setup(scvs_mesh m, hipStream_t s) {
   }
   // level-1 operators P0^T [Ks, M] P0 (Dirichlet rows of P0 are empty, so the
   // Dirichlet rows and columns of Ks and M drop out)
+  build_sell(mg->vel.sell0, rp, n2, m->rowptr.p, m->col.p, s);
   HCsr A0;
   A0.n = A0.m = n2;
   A0.ptr = std::move(rp);
@@ -438,6 +527,7 @@ void mg_setup(scvs_mesh m, hipStream_t s) {
   download(L.ptr.data(), m->lp_ptr.p, nv + 1, s);
   download(L.col.data(), m->lp_col.p, m->nnzl, s);
   download(L.a.data(), m->lp_val.p, m->nnzl, s);
+  build_sell(mg->pres.sell0, L.ptr, nv, m->lp_ptr.p, m->lp_col.p, s);
   build_below(mg->pres, std::move(L), MG_COARSE_MAX, 0.08, s);
   mg->pres.mass = false;
   {
@@ -853,6 +943,117 @@ __global__ void __launch_bounds__(256) k_mg_step_split(LevelArgs<R> la, Batch b,
   }
 }
 
+template <class R>
+struct SellArgs {
+  int64_t nslot;
+  const int64_t* off;
+  const int32_t* row;
+  const int32_t* col;
+  const R *K, *M;  // M null: no mass term
+};
+
+// Lanes of the sliced-row kernels: W lanes per row (a power of two >= the batch's
+// systems, at most 64), each lane one system's PD components; 64 / W rows per wavefront.
+struct SellMap {
+  int G, W, R;
+};
+inline SellMap sell_map(int nact, int PD) {
+  int W = 1;
+  while (W < nact && W < 64) W <<= 1;
+  return {nact * PD, W, 64 / W};
+}
+
+// k_mg_step on level 0 in sliced rows: same arithmetic, one lane per (row, system)
+// accumulating the row's PD components; entry t of the wavefront's rows is one
+// contiguous load of column indices and of each value array.
+template <class R, int PD, bool MASS, int MODE>
+__global__ void __launch_bounds__(256) k_mg_step_sell(LevelArgs<R> la, SellArgs<R> sa, Batch b, SellMap sm,
+                                                      const double* __restrict__ lam, double lamc, double ratio,
+                                                      ChebStep cs, int first,
+                                                      const typename CplxOf<R>::C* __restrict__ xk,
+                                                      const typename CplxOf<R>::C* __restrict__ xo,
+                                                      const typename CplxOf<R>::C* __restrict__ bb,
+                                                      typename CplxOf<R>::C* __restrict__ xn) {
+  using C = typename CplxOf<R>::C;
+  constexpr int U = 8;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t q = (row_block() * 4 + wave) * sm.R + lane / sm.W;
+  if (q >= sa.nslot) return;
+  const int32_t i = sa.row[q];
+  if (i < 0) return;
+  const int64_t sl = q / SELL_C, e0 = sa.off[sl] + q % SELL_C;
+  const int len = (int)((sa.off[sl + 1] - sa.off[sl]) / SELL_C);
+  const bool dir = la.dmask && la.dmask[i] != 0;
+  for (int si = lane & (sm.W - 1); si < b.nact; si += sm.W) {
+    const int slot = b.act[si];
+    const int64_t o = (int64_t)i * sm.G + si * PD;
+    if (dir) {
+#pragma unroll
+      for (int d = 0; d < PD; ++d) xn[o + d] = zero2<C>();
+      continue;
+    }
+    const R wr = MASS ? (R)(b.omega[slot] * (double)la.rho) : (R)0;
+    const C* __restrict__ xs = xk + si * PD;
+    C acc[PD];
+#pragma unroll
+    for (int d = 0; d < PD; ++d) acc[d] = zero2<C>();
+    for (int t = 0; t < len; t += U) {
+      int32_t c[U];
+      R k[U], m[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const bool v = t + u < len;
+        const int64_t e = e0 + (int64_t)(t + u) * SELL_C;
+        c[u] = v ? sa.col[e] : -1;
+        k[u] = v ? sa.K[e] : (R)0;
+        m[u] = (MASS && v) ? sa.M[e] : (R)0;
+      }
+      C xv[U][PD];
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int d = 0; d < PD; ++d) xv[u][d] = c[u] >= 0 ? xs[(int64_t)c[u] * sm.G + d] : zero2<C>();
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const R kr = la.mu * k[u], ki = wr * m[u];
+#pragma unroll
+        for (int d = 0; d < PD; ++d) {
+          acc[d].x += kr * xv[u][d].x - ki * xv[u][d].y;
+          acc[d].y += kr * xv[u][d].y + ki * xv[u][d].x;
+        }
+      }
+    }
+    const R dr = la.mu * la.Kd[i], di = MASS ? wr * la.Md[i] : (R)0;
+    const double lm_ = lam ? lam[slot] : lamc;
+    R a = 0, cc = 0;
+    if (MODE == MG_STEP) {
+      if (first) {
+        cc = (R)(1.0 / (0.5 * lm_ * (1.0 + 1.0 / ratio)));
+      } else {
+        a = (R)(cs.rcur * cs.rprev);
+        cc = (R)(2.0 * cs.rcur / (0.5 * lm_ * (1.0 - 1.0 / ratio)));
+      }
+    }
+#pragma unroll
+    for (int d = 0; d < PD; ++d) {
+      C r = bb[o + d];
+      r.x -= acc[d].x;
+      r.y -= acc[d].y;
+      if (MODE == MG_RESID) {
+        xn[o + d] = r;
+        continue;
+      }
+      const C dv = cdiv<R, C>(r, dr, di);
+      const C xv = xk[o + d];
+      const C xv0 = (xo && !first) ? xo[o + d] : zero2<C>();
+      C w;
+      w.x = xv.x + a * (xv.x - xv0.x) + cc * dv.x;
+      w.y = xv.y + a * (xv.y - xv0.y) + cc * dv.y;
+      xn[o + d] = w;
+    }
+  }
+}
+
 // k_mg_restrict for long restriction rows.
 template <class R, int PD, bool MASS>
 __global__ void __launch_bounds__(256) k_mg_restrict_split(XferArgs<R> rt, LevelArgs<R> lc, Batch b, SplitMap sm,
@@ -1014,9 +1215,9 @@ struct CoarseInv {
 };
 
 template <class R, int PD, bool MASS>
-int mg_cycle(const MgHier& H, const std::vector<LevelArgs<R>>& las, const std::vector<void*>& bufs,
-             const std::vector<const double*>& lams, int l, const Batch& b, int nu, double ratio, CoarseInv coarse,
-             typename CplxOf<R>::C* out, Profiler* prof, hipStream_t s) {
+int mg_cycle(const MgHier& H, const std::vector<LevelArgs<R>>& las, const SellArgs<R>& sell0,
+             const std::vector<void*>& bufs, const std::vector<const double*>& lams, int l, const Batch& b, int nu,
+             double ratio, CoarseInv coarse, typename CplxOf<R>::C* out, Profiler* prof, hipStream_t s) {
   using C = typename CplxOf<R>::C;
   const LaneMap lm = lane_map(b.nact, PD);
   const int nlev = (int)las.size();
@@ -1047,8 +1248,17 @@ int mg_cycle(const MgHier& H, const std::vector<LevelArgs<R>>& las, const std::v
   // one smoothing or residual launch on this level: split rows when they are long
   const SplitMap sm = split_map(lm, la.n ? (double)nnz / (double)la.n : 0.0);
   const unsigned nbs = (unsigned)((la.n + sm.RB - 1) / sm.RB);
+  const SellMap ssm = sell_map(b.nact, PD);
+  const unsigned nbsell = (unsigned)((sell0.nslot + 4 * ssm.R - 1) / (4 * ssm.R));
   auto step = [&](int mode, ChebStep cs, int first, const C* xk, const C* xo, C* xn) {
-    if (sm.S > 1) {
+    if (l == 0 && sell0.off) {
+      if (mode == MG_STEP)
+        k_mg_step_sell<R, PD, MASS, MG_STEP><<<nbsell, 256, 0, s>>>(la, sell0, b, ssm, lam, lamc, ratio, cs, first,
+                                                                     xk, xo, arr(0), xn);
+      else
+        k_mg_step_sell<R, PD, MASS, MG_RESID><<<nbsell, 256, 0, s>>>(la, sell0, b, ssm, lam, lamc, ratio, cs, first,
+                                                                      xk, xo, arr(0), xn);
+    } else if (sm.S > 1) {
       if (mode == MG_STEP)
         k_mg_step_split<R, PD, MASS, MG_STEP><<<nbs, 256, 0, s>>>(la, b, sm, lam, lamc, ratio, cs, first, xk, xo,
                                                                    arr(0), xn);
@@ -1090,7 +1300,7 @@ int mg_cycle(const MgHier& H, const std::vector<LevelArgs<R>>& las, const std::v
                                                                      ratio, arr(4), cb, cb + 2 * ncG);
   }
   launch_check(s);
-  const int kres = mg_cycle<R, PD, MASS>(H, las, bufs, lams, l + 1, b, nu, ratio, coarse, nullptr, prof, s);
+  const int kres = mg_cycle<R, PD, MASS>(H, las, sell0, bufs, lams, l + 1, b, nu, ratio, coarse, nullptr, prof, s);
   {
     const double tb = (double)H.lv[l].pval.n * (4.0 + vb) + (double)la.n * 8.0 + (double)la.n * lm.G * 4.0 * vb +
                       (double)lc.n * lm.G * 2.0 * vb;
@@ -1167,12 +1377,30 @@ std::vector<LevelArgs<R>> pres_levels(scvs_mesh m) {
   return las;
 }
 
+// Level 0 in sliced rows with values in precision R; all null (the CSR kernels run)
+// when those values were not filled.
+template <class R>
+SellArgs<R> sell_args(const Sell& S, bool mass) {
+  const R* K;
+  const R* M;
+  if constexpr (sizeof(R) == 4) {
+    K = S.K32.p;
+    M = S.M32.p;
+  } else {
+    K = S.K.p;
+    M = S.M.p;
+  }
+  if (!K || (mass && !M)) return {0, nullptr, nullptr, nullptr, nullptr, nullptr};
+  return {S.nslot, S.off, S.row, S.col, K, mass ? M : nullptr};
+}
+
 template <class R, int D>
 void vel_cycle(scvs_mesh m, const Batch& b, const PrecondArgs& pa, void* zil, SV<typename CplxOf<R>::C> z,
                hipStream_t s) {
   using C = typename CplxOf<R>::C;
   const MgHier& H = m->mg->vel;
   const auto las = vel_levels<R>(m);
+  const SellArgs<R> s0 = sell_args<R>(H.sell0, true);
   std::vector<void*> bufs(H.lv.size());
   std::vector<const double*> lams(H.lv.size());
   for (size_t l = 0; l < H.lv.size(); ++l) {
@@ -1182,7 +1410,7 @@ void vel_cycle(scvs_mesh m, const Batch& b, const PrecondArgs& pa, void* zil, SV
   Profiler* prof = &m->ctx->prof;
   const int64_t nc = H.lv.back().n;
   const CoarseInv ci{pa.mg.vinv, nc * nc};
-  const int k = mg_cycle<R, D, true>(H, las, bufs, lams, 0, b, pa.mg_nu, pa.mg_ratio, ci,
+  const int k = mg_cycle<R, D, true>(H, las, s0, bufs, lams, 0, b, pa.mg_nu, pa.mg_ratio, ci,
                                      reinterpret_cast<C*>(zil), prof, s);
   if (!zil) {
     const int64_t G = (int64_t)b.nact * D;
@@ -1198,12 +1426,13 @@ void pres_cycle(scvs_mesh m, const Batch& b, const PrecondArgs& pa, SV<VI> v, VA
   using C = typename CplxOf<R>::C;
   const MgHier& H = m->mg->pres;
   const auto las = pres_levels<R>(m);
+  const SellArgs<R> s0 = sell_args<R>(H.sell0, false);
   std::vector<void*> bufs(H.lv.size());
   std::vector<const double*> lams(H.lv.size(), nullptr);
   for (size_t l = 0; l < H.lv.size(); ++l) bufs[l] = pa.mg.p[l];
   Profiler* prof = &m->ctx->prof;
   const CoarseInv ci{sizeof(R) == 4 ? (const void*)H.cinv32.p : (const void*)H.cinv.p, 0};
-  const int k = mg_cycle<R, 1, false>(H, las, bufs, lams, 0, b, pa.mg_nu, pa.mg_ratio, ci, nullptr, prof, s);
+  const int k = mg_cycle<R, 1, false>(H, las, s0, bufs, lams, 0, b, pa.mg_nu, pa.mg_ratio, ci, nullptr, prof, s);
   const C* res = reinterpret_cast<C*>(pa.mg.p[0]) + (int64_t)k * m->nv * b.nact;
   ProfScope ps(prof, s, "k_p_combine", (double)m->nv * (8.0 + b.nact * (sizeof(C) + sizeof(VI) + 16.0)));
   k_p_combine<C, VI><<<1024, 256, 0, s>>>(res, m->nv, (int64_t)m->dim * m->n2, b, m->Mp, m->mu, m->rho, v, z);
@@ -1245,6 +1474,25 @@ void mg_assign(scvs_mesh m, int slots, size_t esize, bool vel, bool pres, char* 
     SCVS_REQUIRE(m->mg->pres.lv.size() <= (size_t)MG_MAXLEV, SCVS_E_CAPACITY, "too many multigrid levels");
     out.p[0] = pres0;
     for (size_t l = 1; l < m->mg->pres.lv.size(); ++l) out.p[l] = take(5 * (size_t)m->mg->pres.lv[l].n * slots * esize);
+  }
+}
+
+// Sliced-row values of level 0 in the cycle's precision (FP32 when f32), for the
+// hierarchies in use; once per hierarchy and precision, outside any graph capture.
+void mg_sell_values(scvs_mesh m, bool f32, bool vel, bool pres, hipStream_t s) {
+  MgData& g = *m->mg;
+  if (vel) {
+    if (f32)
+      sell_fill<float>(g.vel.sell0, m->rowptr, m->Ks32, m->M32, g.vel.sell0.K32, g.vel.sell0.M32, s);
+    else
+      sell_fill<double>(g.vel.sell0, m->rowptr, m->Ks, m->M, g.vel.sell0.K, g.vel.sell0.M, s);
+  }
+  if (pres) {
+    const MgLevel& L0 = g.pres.lv[0];
+    if (f32)
+      sell_fill<float>(g.pres.sell0, m->lp_ptr, L0.K32.p, nullptr, g.pres.sell0.K32, g.pres.sell0.M32, s);
+    else
+      sell_fill<double>(g.pres.sell0, m->lp_ptr, L0.K.p, nullptr, g.pres.sell0.K, g.pres.sell0.M, s);
   }
 }
 

@@ -49,6 +49,11 @@ def short_name(demangled: str) -> str:
         return base + ("32" if f32 else "")
     if base in ("k_pstep", "k_pinit"):  # <input type, recurrence real type>
         return base + ("32" if targs.split(",")[-1].strip() == "float" else "")
+    if base in ("k_mg_step", "k_mg_step_split", "k_mg_step_sell"):  # <real, PD, mass, mode>
+        ta = [t.strip() for t in targs.split(",")]
+        if len(ta) == 4:  # level 0 runs in sliced rows, the coarse levels in CSR
+            return (f"k_mg{'p' if ta[1] == '1' else 'v'}_{'smooth' if ta[3] == '0' else 'resid'}"
+                    + ("0" if base == "k_mg_step_sell" else ""))
     if base == "k_dots" and targs.strip() == "1":
         return "k_dots1"
     if base == "k_update" and targs.strip() == "2":
@@ -71,7 +76,8 @@ def kernels_table(db: str, top: int = 20) -> str:
 
 
 def counter_means(path: str, counter: str) -> dict:
-    """Mean value per dispatch of `counter` for every kernel in a --pmc CSV run."""
+    """Mean value per dispatch of `counter` for every (kernel, grid size) in a
+    --pmc CSV run (the multigrid kernels serve several levels of different sizes)."""
     vals = defaultdict(list)
     files = glob.glob(os.path.join(path, "**", "*counter_collection.csv"), recursive=True)
     if not files:
@@ -81,7 +87,7 @@ def counter_means(path: str, counter: str) -> dict:
             for row in csv.DictReader(fh):
                 if row.get("Counter_Name") != counter:
                     continue
-                vals[row["Kernel_Name"]].append(float(row["Counter_Value"]))
+                vals[(row["Kernel_Name"], int(float(row.get("Grid_Size") or 0)))].append(float(row["Counter_Value"]))
     return {k: (sum(v) / len(v), len(v)) for k, v in vals.items()}
 
 
@@ -91,12 +97,12 @@ def traffic(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, copy_bytes, ou
     cf = counter_means(copy_fetch_dir, "FETCH_SIZE")
     cw = counter_means(copy_write_dir, "WRITE_SIZE")
     # the calibration program runs one plain copy kernel many times; take the largest
-    ck = max(cf, key=lambda k: cf[k][0] * cf[k][1])
+    ck = max(cf, key=lambda k: cf[k][0] * cf[k][1])  # (name, grid)
     kf = cf[ck][0] * 1024.0 / copy_bytes  # counter KiB * 1024 per byte actually read
     kw = cw[ck][0] * 1024.0 / copy_bytes if ck in cw else 1.0
     per = {}
     for k, (fv, n) in fetch.items():
-        sk = short_name(k)
+        sk = short_name(k[0])
         wv = write.get(k, (0.0, 0))[0]
         b = fv * 1024.0 / kf + wv * 1024.0 / kw
         if sk in per:  # several instantiations with one profiler name: weight by dispatches
@@ -105,7 +111,7 @@ def traffic(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, copy_bytes, ou
         else:
             per[sk] = (b, n)
     res = {"source_hash": kernel_source_hash(),
-           "calibration": {"copy_kernel": ck, "copy_bytes": copy_bytes, "fetch_factor": kf, "write_factor": kw},
+           "calibration": {"copy_kernel": ck[0], "copy_bytes": copy_bytes, "fetch_factor": kf, "write_factor": kw},
            "bytes_per_launch": {k: v[0] for k, v in sorted(per.items())},
            "dispatches": {k: v[1] for k, v in sorted(per.items())}}
     with open(out, "w") as fh:

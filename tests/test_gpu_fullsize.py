@@ -4,9 +4,9 @@ complex unknowns, 17 modes) in the launch configuration bench.py times.
 LU is out of reach at this size, so the check uses what the oracle can still
 compute independently: its own FP64 assembly of every mode's constrained
 matrix and right-hand side, and from them the true residual of the GPU
-solution. The solves use exactly the options bench.py times (its defaults,
-read from bench.py itself): mixed precision, the bench's restart length,
-preconditioner degrees, interval ratios and inner tolerance. The oracle's
+solution. The solves use exactly the options bench.py times on its pipe
+workload (read from bench.py itself): mixed precision, the bench's restart
+length, multigrid blocks, smoother settings and inner tolerance. The oracle's
 FP64 residual must be below 5e-12; with the error/residual ratio of about
 1,400 measured on this pipe (the modes' error against a 100x tighter solve),
 that keeps the error under 1e-8. The error itself is also bounded against an
@@ -35,11 +35,12 @@ def test_pipe_200k_residual_and_error():
     m = gpu_mesh(ctx, c)
     g = gpu_dirichlet(m, c, torch)
     import bench
-    args = bench.parse([])
+    args = bench.parse(["--workload", "pipe"])
     opts = bench.solver_opts(args)
     assert opts.precision == 1 and args.tets == 200000 and args.harmonics == 16
-    print(f"[gpu] full size: bench options restart {opts.restart} cheb {opts.cheb_vel}/{opts.cheb_pres} "
-          f"ratios {opts.cheb_ratio}/{opts.cheb_ratio_pres} inner {opts.inner_rtol} rtol {opts.rtol}", flush=True)
+    print(f"[gpu] full size: bench options restart {opts.restart} blocks {opts.vel_block}/{opts.pres_block} "
+          f"smooth {opts.mg_smooth} ratio {opts.mg_ratio} steady {opts.steady_schur_omega:.1f} "
+          f"inner {opts.inner_rtol} rtol {opts.rtol}", flush=True)
     u, p, rep = m.solve(c["omega"], c["traction"], g, opts=opts)
     assert all(r.status == 0 for r in rep)
     ur, pr, rep_ref = m.solve(c["omega"], c["traction"], g, opts=scvs.default_opts(rtol=1e-13, precision=0))

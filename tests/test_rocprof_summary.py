@@ -21,6 +21,11 @@ from paper_2009_06725_amd.rocprof_summary import short_name, traffic
     ("void scvs::(anonymous namespace)::k_lag_dots<HIP_vector_type<double, 2u> >(scvs::KArgs, int, int)",
      "k_lag_dots"),
     ("void scvs::(anonymous namespace)::k_dots<1>(...)", "k_dots1"),
+    ("void scvs::(anonymous namespace)::k_mg_step_sell<float, 3, true, 0>(...)", "k_mgv_smooth0"),
+    ("void scvs::(anonymous namespace)::k_mg_step_sell<float, 3, true, 1>(...)", "k_mgv_resid0"),
+    ("void scvs::(anonymous namespace)::k_mg_step_sell<double, 1, false, 0>(...)", "k_mgp_smooth0"),
+    ("void scvs::(anonymous namespace)::k_mg_step<float, 3, true, 0>(...)", "k_mgv_smooth"),
+    ("void scvs::(anonymous namespace)::k_mg_step_split<float, 1, false, 1>(...)", "k_mgp_resid"),
     ("__amd_rocclr_copyBuffer", "__amd_rocclr_copyBuffer"),
 ])
 def test_short_names(demangled, name):
@@ -30,10 +35,10 @@ def test_short_names(demangled, name):
 def _write(dirpath, counter, rows):
     dirpath.mkdir(parents=True, exist_ok=True)
     with open(dirpath / "run_counter_collection.csv", "w", newline="") as fh:
-        w = csv.DictWriter(fh, fieldnames=["Kernel_Name", "Counter_Name", "Counter_Value"])
+        w = csv.DictWriter(fh, fieldnames=["Kernel_Name", "Grid_Size", "Counter_Name", "Counter_Value"])
         w.writeheader()
         for k, v in rows:
-            w.writerow({"Kernel_Name": k, "Counter_Name": counter, "Counter_Value": v})
+            w.writerow({"Kernel_Name": k, "Grid_Size": 256, "Counter_Name": counter, "Counter_Value": v})
 
 
 def test_traffic_scaling(tmp_path):

@@ -286,7 +286,17 @@ for _ax in range(3):
         _CUBE_FACES.append((_ax, _side, _c))
 
 
-def vessel_mesh(segments, h: float, name: str):
+def _morton3(i, j, k) -> np.ndarray:
+    """Z-order (Morton) keys of non-negative 3D grid indices below 2^21: the
+    bits of i, j and k interleaved, i's bit b going to bit 3b + 2."""
+    i, j, k = (np.asarray(a, np.int64) for a in (i, j, k))
+    key = np.zeros(i.shape, np.int64)
+    for b in range(21):
+        key |= (((i >> b) & 1) << (3 * b + 2)) | (((j >> b) & 1) << (3 * b + 1)) | (((k >> b) & 1) << (3 * b))
+    return key
+
+
+def vessel_mesh(segments, h: float, name: str, order: str = "morton"):
     """Tet mesh of a union of cylinders. ``segments`` is a list of dicts with
     keys a, b (axis end points), r (radius) and role ('inlet', 'outlet' or
     'inner'); inner end points get a junction sphere of the segment's radius.
@@ -300,7 +310,12 @@ def vessel_mesh(segments, h: float, name: str):
     the split uses. Tags: 1 = inlet (facets on the inlet segment's start
     plane), 2 + k = outlet of the k-th outlet segment (facets within one cube
     of its end plane), 3 is never used for outlets; walls are tag 3 and
-    outlets are numbered from 4 when there are several."""
+    outlets are numbered from 4 when there are several.
+
+    ``order`` numbers cubes (hence cells) and vertices: "morton" along the
+    Z-order curve of their grid indices, so that consecutive vertex (and edge)
+    numbers lie close together in space, as a mesh renumbering pass would
+    leave them; "lex" in lexicographic grid order."""
     from scipy.ndimage import label
     inside, pts_lo = _inside_grid(segments, h)
     n = np.array(inside.shape)
@@ -310,15 +325,24 @@ def vessel_mesh(segments, h: float, name: str):
     keep = lab == np.argmax(sizes)
     del lab
     hi, hj, hk = np.nonzero(keep)
-    # corner vertex ids on the (n+1)^3 grid, compacted in lexicographic order
+    if order == "morton":  # cubes along the Z-order curve of their grid index
+        o = np.argsort(_morton3(hi, hj, hk), kind="stable")
+        hi, hj, hk = hi[o], hj[o], hk[o]
+    # corner vertex ids on the (n+1)^3 grid, compacted
     nn = n + 1
     corners = np.stack([((hi + ((c >> 0) & 1)) * nn[1] + hj + ((c >> 1) & 1)) * nn[2] + hk + ((c >> 2) & 1)
                         for c in range(8)], 1).astype(np.int64)
     used, inv = np.unique(corners, return_inverse=True)
-    corners = inv.reshape(corners.shape)
     gi = used // (nn[1] * nn[2])
     gj = (used // nn[2]) % nn[1]
     gk = used % nn[2]
+    if order == "morton":  # renumber the vertices along the same curve
+        o = np.argsort(_morton3(gi, gj, gk), kind="stable")
+        rank = np.empty_like(o)
+        rank[o] = np.arange(o.size)
+        inv = rank[inv]
+        gi, gj, gk = gi[o], gj[o], gk[o]
+    corners = inv.reshape(corners.shape)
     xyz = pts_lo + h * np.stack([gi, gj, gk], 1).astype(float)
     cells = corners[:, _KUHN].reshape(-1, 4)
     # boundary facets: faces towards a dropped (or outside) cube, oriented outward
