@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libscvs.so")
 SOURCES = ["util.hip", "mesh.hip", "assemble.hip", "spmv.hip", "krylov.hip", "synth.hip", "learned.hip", "modes.hip",
-           "mg.hip", "api.cpp"]
+           "mg.hip", "sell.hip", "api.cpp"]
 FLAGS = ["-x", "hip", "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
          "-Wno-unused-function", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 

@@ -264,6 +264,7 @@ int scvs_assemble(scvs_mesh m, double rho, double mu) {
     m->mu = mu;
     m->assembled = true;
     m->fp32_ready = false;
+    scvs::s2sell_release_values(m);
     m->generation++;
     if (m->bc_set) scvs::mesh_precond_setup(m, m->ctx->stream);
   });

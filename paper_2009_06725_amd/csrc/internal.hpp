@@ -167,18 +167,22 @@ struct MgLevel {
 // off[s] + t * SELL_C + r, so that one wavefront load of entry t covers SELL_C rows
 // in one contiguous run. Rows shorter than their slice are padded with their own
 // index and zero values. Values are filled per precision on first use.
+// Rows below a split index (the vertex rows of S2) fill the first split_slots slots,
+// the others start on a fresh slice, so no slice mixes the two kinds.
 constexpr int SELL_C = 32, SELL_WIN = 512;
 struct Sell {
-  int64_t nslot = 0;  // slices * SELL_C
-  DBuf<int64_t> off;  // [slices + 1]
-  DBuf<int32_t> row;  // [nslot] row of each slot, -1 past the last row
-  DBuf<int32_t> col;  // [off[slices]]
+  int64_t nslot = 0;          // slices * SELL_C
+  int64_t split_slots = 0;    // slots of the rows below the split (a multiple of SELL_C)
+  int64_t split_entries = 0;  // their entries (off[split_slots / SELL_C])
+  DBuf<int64_t> off;          // [slices + 1]
+  DBuf<int32_t> row;          // [nslot] row of each slot, -1 for padding slots
+  DBuf<int32_t> col;          // [off[slices]]
   DBuf<float> K32, M32;
   DBuf<double> K, M;
 };
 struct MgHier {
   std::vector<MgLevel> lv;
-  Sell sell0;  // level 0's operator in sliced rows
+  Sell sell0;  // pressure: level 0 in sliced rows (the velocity's level 0 is the mesh's S2)
   bool mass = false;
   DBuf<double2> cinv;  // single-matrix hierarchies: dense inverse of the coarsest level
   DBuf<float2> cinv32;
@@ -219,6 +223,13 @@ struct scvs_mesh_s {
   // assembled values
   scvs::DBuf<double> Ks, M, G, Gt, Kd, Md, Mp;
   scvs::DBuf<float> Ks32, M32, G32, Gt32, Kd32, Md32;  // made on the first mixed-precision solve
+  // S2 in sliced rows (vertex rows first): the pattern once per mesh, values per
+  // assembly and precision on first use; G on each row's vertex-column prefix in
+  // slices of their own (s2_goff, D values per entry), G^T on the vertex slices' entries
+  scvs::Sell s2sell;
+  scvs::DBuf<int64_t> s2_goff;
+  int64_t s2_gn = 0;
+  scvs::DBuf<float> s2_G32, s2_Gt32;
   bool fp32_ready = false;
   uint64_t generation = 0;  // bumped whenever the operator changes (assembly, boundary conditions)
   // boundary conditions
@@ -387,6 +398,17 @@ void mg_assign(scvs_mesh m, int slots, size_t esize, bool vel, bool pres, char* 
 int mg_levels(scvs_mesh m, bool vel);
 // Level-0 values in sliced rows for the cycle's precision (FP32 when f32).
 void mg_sell_values(scvs_mesh m, bool f32, bool vel, bool pres, hipStream_t s);
+// Sliced rows of an n-row CSR pattern (host row pointers, device pointers and columns);
+// rows below `split` fill the first slices.
+void sell_build(Sell& S, const std::vector<int64_t>& ptr, int64_t n, int64_t split, const int64_t* dptr,
+                const int32_t* dcol, hipStream_t s);
+// Sliced values from CSR values of the pattern the layout was built from.
+template <class R>
+void sell_values(const Sell& S, const int64_t* dptr, const R* a, DBuf<R>& out, hipStream_t s);
+// The mesh's S2 in sliced rows with FP32 values (Ks, M, G, G^T; f32) and FP64 values
+// (Ks, M; f64), each made once per assembly; needs the FP32 copies for f32.
+void s2sell_setup(scvs_mesh m, bool f32, bool f64, hipStream_t s);
+void s2sell_release_values(scvs_mesh m);
 // Per system: smoother bounds of every velocity level and the coarsest level's dense inverse.
 void mg_prepare(scvs_mesh m, const Batch& b, double* lam, int slots, double2* inv, float2* inv32, hipStream_t s);
 int64_t mg_coarse_rows(scvs_mesh m);

@@ -1088,7 +1088,10 @@ int solve_systems(scvs_mesh m, int64_t nsys, const double* omega, const double* 
   const bool mixed = o->precision >= 1;
   const bool lagged = o->orth == 1;
   P.v32 = o->precision == 2;  // FP32 basis storage (lagged orthogonalization only; checked by the caller)
-  if (mixed) make_fp32_copies(m, s);
+  if (mixed) {
+    make_fp32_copies(m, s);
+    s2sell_setup(m, true, false, s);  // the operator product reads S2 in sliced rows
+  }
   // multigrid blocks: the hierarchy (once per assembly and boundary conditions) and, per
   // slot, a fifth level-0 temporary, the coarse-level temporaries and the smoother bounds
   const bool vmg = o->vel_block == 1, pmg = o->pres_block == 1 && o->cheb_pres > 0;

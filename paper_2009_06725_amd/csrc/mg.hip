@@ -374,91 +374,6 @@ void dense_inverse(std::vector<double>& a, int64_t n) {
 }  // namespace
 
 // Builds both hierarchies of a mesh (after assembly and boundary conditions).
-namespace {
-
-// Column indices of the sliced rows: thread per slot, entries of its row in order,
-// padding with the row's own index (the last slice's rows past n: column 0).
-__global__ void k_sell_col(const int64_t* __restrict__ ptr, const int32_t* __restrict__ col,
-                           const int64_t* __restrict__ off, const int32_t* __restrict__ row, int64_t nslot,
-                           int32_t* __restrict__ out) {
-  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= nslot) return;
-  const int64_t sl = q / SELL_C, e0 = off[sl] + q % SELL_C;
-  const int len = (int)((off[sl + 1] - off[sl]) / SELL_C);
-  const int32_t i = row[q];
-  const int64_t j0 = i >= 0 ? ptr[i] : 0, rl = i >= 0 ? ptr[i + 1] - j0 : 0;
-  for (int t = 0; t < len; ++t) out[e0 + (int64_t)t * SELL_C] = t < rl ? col[j0 + t] : (i >= 0 ? i : 0);
-}
-
-// Values of the sliced rows (zero on padding) from CSR values in the same pattern.
-template <class R>
-__global__ void k_sell_val(const int64_t* __restrict__ ptr, const R* __restrict__ a,
-                           const int64_t* __restrict__ off, const int32_t* __restrict__ row, int64_t nslot,
-                           R* __restrict__ out) {
-  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= nslot) return;
-  const int64_t sl = q / SELL_C, e0 = off[sl] + q % SELL_C;
-  const int len = (int)((off[sl + 1] - off[sl]) / SELL_C);
-  const int32_t i = row[q];
-  const int64_t j0 = i >= 0 ? ptr[i] : 0, rl = i >= 0 ? ptr[i + 1] - j0 : 0;
-  for (int t = 0; t < len; ++t) out[e0 + (int64_t)t * SELL_C] = t < rl ? a[j0 + t] : (R)0;
-}
-
-// The sliced-row layout of an n-row CSR pattern (host row pointers `ptr`, device
-// pointers and columns `dptr`, `dcol`); values are filled later by sell_fill.
-void build_sell(Sell& S, const std::vector<int64_t>& ptr, int64_t n, const int64_t* dptr, const int32_t* dcol,
-                hipStream_t s) {
-  const int64_t nsl = (n + SELL_C - 1) / SELL_C;
-  S.nslot = nsl * SELL_C;
-  std::vector<int32_t> row(S.nslot, -1);
-  const int64_t nwin = (n + SELL_WIN - 1) / SELL_WIN;
-  const int nt = host_threads();
-  std::vector<std::thread> th;
-  for (int t = 0; t < nt; ++t)
-    th.emplace_back([&, t] {
-      for (int64_t w = t; w < nwin; w += nt) {
-        const int64_t a = w * SELL_WIN, b = std::min(n, a + SELL_WIN);
-        int32_t* r = row.data() + a;
-        for (int64_t i = a; i < b; ++i) r[i - a] = (int32_t)i;
-        std::stable_sort(r, r + (b - a), [&](int32_t x, int32_t y) {
-          return ptr[x + 1] - ptr[x] > ptr[y + 1] - ptr[y];
-        });
-      }
-    });
-  for (auto& x : th) x.join();
-  std::vector<int64_t> off(nsl + 1, 0);
-  for (int64_t sl = 0; sl < nsl; ++sl) {
-    int64_t len = 0;  // windows are whole slices, so the first row is the longest
-    const int32_t i = row[sl * SELL_C];
-    if (i >= 0) len = ptr[i + 1] - ptr[i];
-    off[sl + 1] = off[sl] + len * SELL_C;
-  }
-  S.off.upload(off.data(), off.size(), s);
-  S.row.upload(row.data(), row.size(), s);
-  S.col.alloc((size_t)off[nsl]);
-  k_sell_col<<<(unsigned)((S.nslot + 255) / 256), 256, 0, s>>>(dptr, dcol, S.off, S.row, S.nslot, S.col);
-  launch_check(s);
-  SCVS_HIP(hipStreamSynchronize(s));  // row and off are host temporaries
-}
-
-// Fills (once per precision) the sliced values from CSR values K, M (M may be null).
-template <class R>
-void sell_fill(Sell& S, const int64_t* dptr, const R* K, const R* M, DBuf<R>& sK, DBuf<R>& sM, hipStream_t s) {
-  if (sK.p) return;
-  const size_t ne = S.col.n;
-  const unsigned nb = (unsigned)((S.nslot + 255) / 256);
-  sK.alloc(ne);
-  k_sell_val<R><<<nb, 256, 0, s>>>(dptr, K, S.off, S.row, S.nslot, sK);
-  launch_check(s);
-  if (M) {
-    sM.alloc(ne);
-    k_sell_val<R><<<nb, 256, 0, s>>>(dptr, M, S.off, S.row, S.nslot, sM);
-    launch_check(s);
-  }
-}
-
-}  // namespace
-
 void mg_setup(scvs_mesh m, hipStream_t s) {
   if (m->mg && m->mg->gen == m->generation) return;
   auto mg = std::make_unique<MgData>();
@@ -502,7 +417,6 @@ void mg_setup(scvs_mesh m, hipStream_t s) {
   }
   // level-1 operators P0^T [Ks, M] P0 (Dirichlet rows of P0 are empty, so the
   // Dirichlet rows and columns of Ks and M drop out)
-  build_sell(mg->vel.sell0, rp, n2, m->rowptr.p, m->col.p, s);
   HCsr A0;
   A0.n = A0.m = n2;
   A0.ptr = std::move(rp);
@@ -527,7 +441,7 @@ void mg_setup(scvs_mesh m, hipStream_t s) {
   download(L.ptr.data(), m->lp_ptr.p, nv + 1, s);
   download(L.col.data(), m->lp_col.p, m->nnzl, s);
   download(L.a.data(), m->lp_val.p, m->nnzl, s);
-  build_sell(mg->pres.sell0, L.ptr, nv, m->lp_ptr.p, m->lp_col.p, s);
+  sell_build(mg->pres.sell0, L.ptr, nv, nv, m->lp_ptr.p, m->lp_col.p, s);
   build_below(mg->pres, std::move(L), MG_COARSE_MAX, 0.08, s);
   mg->pres.mass = false;
   {
@@ -1054,6 +968,94 @@ __global__ void __launch_bounds__(256) k_mg_step_sell(LevelArgs<R> la, SellArgs<
   }
 }
 
+// k_mg_step on level 0 in sliced rows with two (system, component) pairs per lane
+// (FP32, an even number G of pairs per row): a row's group of W lanes gathers a
+// column's G values with one 16-byte load per lane, so a wavefront gathers 64 / W
+// rows' values in one instruction. Same arithmetic per pair as k_mg_step_sell.
+template <int PD, bool MASS, int MODE>
+__global__ void __launch_bounds__(256) k_mg_step_sell2(LevelArgs<float> la, SellArgs<float> sa, Batch b, SellMap sm,
+                                                       const double* __restrict__ lam, double lamc, double ratio,
+                                                       ChebStep cs, int first, const float2* __restrict__ xk,
+                                                       const float2* __restrict__ xo, const float2* __restrict__ bb,
+                                                       float2* __restrict__ xn) {
+  constexpr int U = 8;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t q = (row_block() * 4 + wave) * sm.R + lane / sm.W;
+  if (q >= sa.nslot) return;
+  const int32_t i = sa.row[q];
+  if (i < 0) return;
+  const int64_t sl = q / SELL_C, e0 = sa.off[sl] + q % SELL_C;
+  const int len = (int)((sa.off[sl + 1] - sa.off[sl]) / SELL_C);
+  const bool dir = la.dmask && la.dmask[i] != 0;
+  const int G = sm.G;
+  for (int p0 = 2 * (lane & (sm.W - 1)); p0 < G; p0 += 2 * sm.W) {
+    const int64_t o = (int64_t)i * G + p0;
+    if (dir) {
+      *reinterpret_cast<float4*>(xn + o) = make_float4(0.f, 0.f, 0.f, 0.f);
+      continue;
+    }
+    const int slot0 = b.act[p0 / PD], slot1 = b.act[(p0 + 1) / PD];
+    const float w0 = MASS ? (float)(b.omega[slot0] * (double)la.rho) : 0.f;
+    const float w1 = MASS ? (float)(b.omega[slot1] * (double)la.rho) : 0.f;
+    float2 a0 = make_float2(0.f, 0.f), a1 = make_float2(0.f, 0.f);
+    const float2* __restrict__ xs = xk + p0;
+    for (int t = 0; t < len; t += U) {
+      int32_t c[U];
+      float k[U], m[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const bool v = t + u < len;
+        const int64_t e = e0 + (int64_t)(t + u) * SELL_C;
+        c[u] = v ? sa.col[e] : -1;
+        k[u] = v ? sa.K[e] : 0.f;
+        m[u] = (MASS && v) ? sa.M[e] : 0.f;
+      }
+      float4 xv[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        xv[u] = c[u] >= 0 ? *reinterpret_cast<const float4*>(xs + (int64_t)c[u] * G) : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const float kr = la.mu * k[u], ki0 = w0 * m[u], ki1 = w1 * m[u];
+        a0.x += kr * xv[u].x - ki0 * xv[u].y;
+        a0.y += kr * xv[u].y + ki0 * xv[u].x;
+        a1.x += kr * xv[u].z - ki1 * xv[u].w;
+        a1.y += kr * xv[u].w + ki1 * xv[u].z;
+      }
+    }
+    const float4 bv = *reinterpret_cast<const float4*>(bb + o);
+    float2 r0 = make_float2(bv.x - a0.x, bv.y - a0.y), r1 = make_float2(bv.z - a1.x, bv.w - a1.y);
+    if (MODE == MG_RESID) {
+      *reinterpret_cast<float4*>(xn + o) = make_float4(r0.x, r0.y, r1.x, r1.y);
+      continue;
+    }
+    const float4 xv = *reinterpret_cast<const float4*>(xk + o);
+    const float4 x0 = (xo && !first) ? *reinterpret_cast<const float4*>(xo + o) : make_float4(0.f, 0.f, 0.f, 0.f);
+    float4 w;
+    {
+      const double lm_ = lam ? lam[slot0] : lamc;
+      const float dr = la.mu * la.Kd[i], di = MASS ? w0 * la.Md[i] : 0.f;
+      const float2 d = cdiv<float, float2>(r0, dr, di);
+      const float a = first ? 0.f : (float)(cs.rcur * cs.rprev);
+      const float cc = first ? (float)(1.0 / (0.5 * lm_ * (1.0 + 1.0 / ratio)))
+                             : (float)(2.0 * cs.rcur / (0.5 * lm_ * (1.0 - 1.0 / ratio)));
+      w.x = xv.x + a * (xv.x - x0.x) + cc * d.x;
+      w.y = xv.y + a * (xv.y - x0.y) + cc * d.y;
+    }
+    {
+      const double lm_ = lam ? lam[slot1] : lamc;
+      const float dr = la.mu * la.Kd[i], di = MASS ? w1 * la.Md[i] : 0.f;
+      const float2 d = cdiv<float, float2>(r1, dr, di);
+      const float a = first ? 0.f : (float)(cs.rcur * cs.rprev);
+      const float cc = first ? (float)(1.0 / (0.5 * lm_ * (1.0 + 1.0 / ratio)))
+                             : (float)(2.0 * cs.rcur / (0.5 * lm_ * (1.0 - 1.0 / ratio)));
+      w.z = xv.z + a * (xv.z - x0.z) + cc * d.x;
+      w.w = xv.w + a * (xv.w - x0.w) + cc * d.y;
+    }
+    *reinterpret_cast<float4*>(xn + o) = w;
+  }
+}
+
 // k_mg_restrict for long restriction rows.
 template <class R, int PD, bool MASS>
 __global__ void __launch_bounds__(256) k_mg_restrict_split(XferArgs<R> rt, LevelArgs<R> lc, Batch b, SplitMap sm,
@@ -1250,7 +1252,24 @@ int mg_cycle(const MgHier& H, const std::vector<LevelArgs<R>>& las, const SellAr
   const unsigned nbs = (unsigned)((la.n + sm.RB - 1) / sm.RB);
   const SellMap ssm = sell_map(b.nact, PD);
   const unsigned nbsell = (unsigned)((sell0.nslot + 4 * ssm.R - 1) / (4 * ssm.R));
+  // two pairs per lane (FP32, even G): W lanes per row cover the G pairs in 16-byte loads
+  const bool two = sizeof(R) == 4 && lm.G % 2 == 0;
+  SellMap sm2{lm.G, 1, 64};
+  while (sm2.W < lm.G / 2 && sm2.W < 64) sm2.W <<= 1;
+  sm2.R = 64 / sm2.W;
+  const unsigned nbsell2 = (unsigned)((sell0.nslot + 4 * sm2.R - 1) / (4 * sm2.R));
   auto step = [&](int mode, ChebStep cs, int first, const C* xk, const C* xo, C* xn) {
+    if constexpr (sizeof(R) == 4) {
+      if (l == 0 && sell0.off && two) {
+        if (mode == MG_STEP)
+          k_mg_step_sell2<PD, MASS, MG_STEP><<<nbsell2, 256, 0, s>>>(la, sell0, b, sm2, lam, lamc, ratio, cs, first,
+                                                                      xk, xo, arr(0), xn);
+        else
+          k_mg_step_sell2<PD, MASS, MG_RESID><<<nbsell2, 256, 0, s>>>(la, sell0, b, sm2, lam, lamc, ratio, cs, first,
+                                                                       xk, xo, arr(0), xn);
+        return;
+      }
+    }
     if (l == 0 && sell0.off) {
       if (mode == MG_STEP)
         k_mg_step_sell<R, PD, MASS, MG_STEP><<<nbsell, 256, 0, s>>>(la, sell0, b, ssm, lam, lamc, ratio, cs, first,
@@ -1400,7 +1419,7 @@ void vel_cycle(scvs_mesh m, const Batch& b, const PrecondArgs& pa, void* zil, SV
   using C = typename CplxOf<R>::C;
   const MgHier& H = m->mg->vel;
   const auto las = vel_levels<R>(m);
-  const SellArgs<R> s0 = sell_args<R>(H.sell0, true);
+  const SellArgs<R> s0 = sell_args<R>(m->s2sell, true);
   std::vector<void*> bufs(H.lv.size());
   std::vector<const double*> lams(H.lv.size());
   for (size_t l = 0; l < H.lv.size(); ++l) {
@@ -1478,21 +1497,14 @@ void mg_assign(scvs_mesh m, int slots, size_t esize, bool vel, bool pres, char* 
 }
 
 // Sliced-row values of level 0 in the cycle's precision (FP32 when f32), for the
-// hierarchies in use; once per hierarchy and precision, outside any graph capture.
+// hierarchies in use; once per assembly and precision, outside any graph capture.
 void mg_sell_values(scvs_mesh m, bool f32, bool vel, bool pres, hipStream_t s) {
-  MgData& g = *m->mg;
-  if (vel) {
-    if (f32)
-      sell_fill<float>(g.vel.sell0, m->rowptr, m->Ks32, m->M32, g.vel.sell0.K32, g.vel.sell0.M32, s);
-    else
-      sell_fill<double>(g.vel.sell0, m->rowptr, m->Ks, m->M, g.vel.sell0.K, g.vel.sell0.M, s);
-  }
+  if (vel) s2sell_setup(m, f32, !f32, s);
   if (pres) {
-    const MgLevel& L0 = g.pres.lv[0];
-    if (f32)
-      sell_fill<float>(g.pres.sell0, m->lp_ptr, L0.K32.p, nullptr, g.pres.sell0.K32, g.pres.sell0.M32, s);
-    else
-      sell_fill<double>(g.pres.sell0, m->lp_ptr, L0.K.p, nullptr, g.pres.sell0.K, g.pres.sell0.M, s);
+    Sell& S = m->mg->pres.sell0;
+    const MgLevel& L0 = m->mg->pres.lv[0];
+    if (f32 && !S.K32.p) sell_values<float>(S, m->lp_ptr, L0.K32.p, S.K32, s);
+    if (!f32 && !S.K.p) sell_values<double>(S, m->lp_ptr, L0.K.p, S.K, s);
   }
 }
 

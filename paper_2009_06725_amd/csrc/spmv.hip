@@ -286,6 +286,132 @@ __global__ void __launch_bounds__(256) k_full(MeshArgs ma, Batch b, LaneMap lm, 
   }
 }
 
+// S2 in sliced rows for the FP32 operator product (layout of struct Sell).
+struct S2SellArgs {
+  int64_t nslot, vslots;      // slots; slots of the vertex rows (the first slices)
+  const int64_t *off, *goff;  // entries per slice of S2 and of the vertex-column prefix
+  const int32_t* row;
+  const int32_t* col;
+  const float *K, *M;
+  const float* G;   // [goff[end]][D]: G^c on the vertex-column prefix of each row
+  const float* Gt;  // [off[vslots / SELL_C]][D]: G^T^c on the vertex rows' entries
+};
+
+// k_full (operator product y = A x, FP32 values, interleaved input xil) in sliced
+// rows: one lane per (row, system) holds that system's D momentum sums, and on a
+// vertex row also its divergence sum; entry t of the wavefront's rows is one
+// contiguous load of columns and of each value array. Same arithmetic and outputs as
+// k_full<D, SPMV_APPLY, false, float, true, YT>.
+template <int D, class YT>
+__global__ void __launch_bounds__(256) k_full_sell(MeshArgs ma, S2SellArgs sa, Batch b, int W, int RW,
+                                                   const float2* __restrict__ xil, SV<YT> y) {
+  constexpr int U = 4;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t q = (row_block() * 4 + wave) * RW + lane / W;
+  if (q >= sa.nslot) return;
+  const int32_t A = sa.row[q];
+  if (A < 0) return;
+  const int64_t sl = q / SELL_C, r = q % SELL_C;
+  const int64_t e0 = sa.off[sl] + r, g0 = sa.goff[sl] + r;
+  const int len = (int)((sa.off[sl + 1] - sa.off[sl]) / SELL_C);
+  const int glen = (int)((sa.goff[sl + 1] - sa.goff[sl]) / SELL_C);
+  const bool isv = q < sa.vslots;
+  const int32_t dm = ma.dmask[A];
+  const int nvr = ma.nvc[A];
+  const int G = b.nact * D;
+  const float2* __restrict__ pil = xil + ma.n2 * G;  // pressures: [nv][nact]
+  const float mu = (float)ma.mu;
+  for (int si = lane & (W - 1); si < b.nact; si += W) {
+    const int slot = b.act[si];
+    const double sc = in_scale(b, slot);
+    const float wr = (float)(b.omega[slot] * ma.rho);
+    const float2* __restrict__ xs = xil + si * D;
+    float2 au[D], ap = make_float2(0.f, 0.f);
+#pragma unroll
+    for (int d = 0; d < D; ++d) au[d] = make_float2(0.f, 0.f);
+    if (dm == 0 || isv) {
+      for (int t = 0; t < len; t += U) {
+        int32_t c[U];
+        float k[U], m[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const bool v = t + u < len;
+          const int64_t e = e0 + (int64_t)(t + u) * SELL_C;
+          c[u] = v ? sa.col[e] : -1;
+          k[u] = v ? sa.K[e] : 0.f;
+          m[u] = v ? sa.M[e] : 0.f;
+        }
+        float2 xv[U][D];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+          for (int d = 0; d < D; ++d) xv[u][d] = c[u] >= 0 ? xs[(int64_t)c[u] * G + d] : make_float2(0.f, 0.f);
+        if (dm == 0) {
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            const float kr = mu * k[u], ki = wr * m[u];
+#pragma unroll
+            for (int d = 0; d < D; ++d) {
+              au[d].x += kr * xv[u][d].x - ki * xv[u][d].y;
+              au[d].y += kr * xv[u][d].y + ki * xv[u][d].x;
+            }
+          }
+          if (t < glen) {  // G p over the vertex-column prefix
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+              if (t + u < nvr) {
+                const int64_t ge = (g0 + (int64_t)(t + u) * SELL_C) * D;
+                const float2 pv = pil[(int64_t)c[u] * b.nact + si];
+#pragma unroll
+                for (int d = 0; d < D; ++d) {
+                  const float g = sa.G[ge + d];
+                  au[d].x += g * pv.x;
+                  au[d].y += g * pv.y;
+                }
+              }
+            }
+          }
+        }
+        if (isv) {  // divergence row: sum_c G^T^c x_c
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            if (t + u < len) {
+              const int64_t e = (e0 + (int64_t)(t + u) * SELL_C) * D;
+#pragma unroll
+              for (int d = 0; d < D; ++d) {
+                const float g = sa.Gt[e + d];
+                ap.x += g * xv[u][d].x;
+                ap.y += g * xv[u][d].y;
+              }
+            }
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      double2 yu;
+      if (dm != 0) {
+        const float2 xv = xs[(int64_t)A * G + d];
+        yu = make_double2(sc * (double)xv.x, sc * (double)xv.y);
+      } else {
+        yu = make_double2(sc * (double)au[d].x, sc * (double)au[d].y);
+      }
+      y.at(slot)[(int64_t)A * D + d] = cvt2<YT>(yu);
+    }
+    if (isv) {
+      double2 yp = make_double2(sc * (double)ap.x, sc * (double)ap.y);
+      if (b.pen != 0.0) {  // penalized continuity block -pen Mp p
+        const float2 xp = pil[(int64_t)A * b.nact + si];
+        const double w = b.pen * ma.Mp[A] * sc;
+        yp.x -= w * (double)xp.x;
+        yp.y -= w * (double)xp.y;
+      }
+      y.at(slot)[(int64_t)D * ma.n2 + A] = cvt2<YT>(yp);
+    }
+  }
+}
+
 // Lumped outlets: after the operator kernel, y += s * sc * Z_o(w) (b_o^T x) b_o on the
 // free momentum rows of every outlet o, s = +1 for y = A x and -1 for y = f - A x and
 // for the right-hand side (where x is the Dirichlet lift and b_o^T x runs over the
@@ -449,6 +575,81 @@ __global__ void __launch_bounds__(256) k_vinit(MeshArgs ma, Batch b, LaneMap lm,
       xv.y = t.y * (dinv / theta);
     }
     *x1 = xv;
+  }
+}
+
+// k_vinit<D, float, VI, true> (multigrid velocity block, FP32 temporaries, interleaved
+// result) in sliced rows: one lane per (row, system) forms b = v_u - G z_p for its D
+// components from the G slices and the first smoothing iterate x_1 = D^-1 b / theta
+// of level 0, and copies z_p to the interleaved result on a vertex row.
+template <int D, class VI>
+__global__ void __launch_bounds__(256) k_vinit_sell(MeshArgs ma, S2SellArgs sa, Batch b, int W, int RW, SV<VI> v,
+                                                    VArg zp64, ITemps<float2> vt, double ratio,
+                                                    float2* __restrict__ zil) {
+  constexpr int U = 4;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t q = (row_block() * 4 + wave) * RW + lane / W;
+  if (q >= sa.nslot) return;
+  const int32_t A = sa.row[q];
+  if (A < 0) return;
+  const int64_t sl = q / SELL_C, r = q % SELL_C;
+  const int64_t e0 = sa.off[sl] + r, g0 = sa.goff[sl] + r;
+  const int glen = min((int)((sa.goff[sl + 1] - sa.goff[sl]) / SELL_C), ma.nvc[A]);
+  const int G = b.nact * D;
+  const int64_t DN = (int64_t)D * ma.n2;
+  const bool dir = ma.dmask[A] != 0;
+  for (int si = lane & (W - 1); si < b.nact; si += W) {
+    const int slot = b.act[si];
+    const double2* __restrict__ zp = zp64.at(slot) + DN;
+    if (A < ma.nv) {
+      const double2 pq = zp[A];
+      zil[ma.n2 * G + (int64_t)A * b.nact + si] = make_float2((float)pq.x, (float)pq.y);
+    }
+    const int64_t o = (int64_t)A * G + si * D;
+    float2* __restrict__ bb = vt.arr(0);
+    float2* __restrict__ x1 = vt.iter(1);
+    if (dir) {
+#pragma unroll
+      for (int d = 0; d < D; ++d) bb[o + d] = x1[o + d] = make_float2(0.f, 0.f);
+      continue;
+    }
+    const double sc = in_scale(b, slot);
+    float2 t[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      const double2 vv = to_d2(v.at(slot)[(int64_t)A * D + d]);
+      t[d] = make_float2((float)(sc * vv.x), (float)(sc * vv.y));
+    }
+    for (int jt = 0; jt < glen; jt += U) {
+      int32_t c[U];
+      float2 pv[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) c[u] = jt + u < glen ? sa.col[e0 + (int64_t)(jt + u) * SELL_C] : -1;
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const double2 pd = c[u] >= 0 ? zp[c[u]] : make_double2(0.0, 0.0);
+        pv[u] = make_float2((float)pd.x, (float)pd.y);
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if (c[u] < 0) continue;
+        const int64_t ge = (g0 + (int64_t)(jt + u) * SELL_C) * D;
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+          const float g = sa.G[ge + d];
+          t[d].x += -1.f * g * pv[u].x;
+          t[d].y += -1.f * g * pv[u].y;
+        }
+      }
+    }
+    const float theta = (float)(0.5 * b.lv[slot] * (1.0 + 1.0 / ratio));
+    const float dr = (float)ma.mu * ma.Kd32[A], di = (float)(b.omega[slot] * ma.rho) * ma.Md32[A];
+    const float sc2 = 1.f / ((dr * dr + di * di) * theta);
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      bb[o + d] = t[d];
+      x1[o + d] = make_float2((t[d].x * dr + t[d].y * di) * sc2, (t[d].y * dr - t[d].x * di) * sc2);
+    }
   }
 }
 
@@ -655,8 +856,8 @@ void full_launch32(Profiler* prof, const MeshArgs& ma, const Batch& b, VArg32 x,
 
 // y = A x for the interleaved preconditioner output (FP64 or FP32 values by R).
 template <int D, class R, class YT>
-void full_launch_il(Profiler* prof, const MeshArgs& ma, const Batch& b, const typename Prec<R>::C* xil, SV<YT> y,
-                    hipStream_t s) {
+void full_launch_il(Profiler* prof, const MeshArgs& ma, const S2SellArgs* sa, const Batch& b,
+                    const typename Prec<R>::C* xil, SV<YT> y, hipStream_t s) {
   const LaneMap lm = lane_map(b.nact, D);
   const unsigned nb = row_blocks(ma.n2, lm);
   const double vb = sizeof(R);  // bytes per real matrix value
@@ -665,6 +866,17 @@ void full_launch_il(Profiler* prof, const MeshArgs& ma, const Batch& b, const ty
   const double ndof = (double)D * ma.n2 + ma.nv;
   ProfScope ps(prof, s, sizeof(R) == 4 ? "k_full_apply32" : "k_full_apply",
                mat + b.nact * ndof * (2.0 * vb + (double)sizeof(YT)));
+  if constexpr (sizeof(R) == 4) {
+    if (sa) {  // sliced rows: W lanes per row (a power of two >= the systems, <= 64)
+      int W = 1;
+      while (W < b.nact && W < 64) W <<= 1;
+      const int RW = 64 / W;
+      const unsigned nbs = (unsigned)((sa->nslot + 4 * RW - 1) / (4 * RW));
+      k_full_sell<D, YT><<<nbs, 256, 0, s>>>(ma, *sa, b, W, RW, xil, y);
+      launch_check(s);
+      return;
+    }
+  }
   k_full<D, SPMV_APPLY, false, R, true, YT><<<nb, 256, 0, s>>>(ma, b, lm, typename Prec<R>::V{}, y, VArg{}, nullptr,
                                                                0, nullptr, xil);
   launch_check(s);
@@ -725,7 +937,16 @@ void precond_launch(scvs_mesh m, Profiler* prof, const MeshArgs& ma, const Batch
       // multigrid: b and the first smoothing iterate of level 0 (complex diagonal)
       Batch bv = b;
       bv.lv = pa.mg.vlam;
-      if (pa.mixed)
+      const Sell& S = m->s2sell;
+      if (pa.mixed && zil && S.K32.p && m->s2_G32.p) {
+        int W = 1;
+        while (W < b.nact && W < 64) W <<= 1;
+        const int RW = 64 / W;
+        const S2SellArgs sa{S.nslot, S.split_slots, S.off, m->s2_goff, S.row, S.col, S.K32, S.M32, m->s2_G32,
+                            m->s2_Gt32};
+        k_vinit_sell<D, VI><<<(unsigned)((S.nslot + 4 * RW - 1) / (4 * RW)), 256, 0, s>>>(
+            ma, sa, bv, W, RW, v, z, it32, pa.mg_ratio, (float2*)zil);
+      } else if (pa.mixed)
         k_vinit<D, float, VI, true><<<nbu, 256, 0, s>>>(ma, bv, lm, v, z, pa.z32, it32, pa.mg_ratio, 2, (float2*)zil);
       else
         k_vinit<D, double, VI, true><<<nbu, 256, 0, s>>>(ma, bv, lm, v, z, z, it64, pa.mg_ratio, 2, (double2*)zil);
@@ -804,16 +1025,19 @@ void precond_apply(scvs_mesh m, const Batch& b, const PrecondArgs& pa, VArg32 v,
 template <class YT>
 static void spmv_il_any(scvs_mesh m, const Batch& b, const void* xil, bool fp32, SV<YT> y, hipStream_t s) {
   const MeshArgs ma = mesh_args(m);
+  const Sell& S = m->s2sell;
+  S2SellArgs sa{S.nslot, S.split_slots, S.off, m->s2_goff, S.row, S.col, S.K32, S.M32, m->s2_G32, m->s2_Gt32};
+  const S2SellArgs* sp = (fp32 && S.K32.p && m->s2_G32.p) ? &sa : nullptr;
   if (m->dim == 2) {
     if (fp32)
-      full_launch_il<2, float, YT>(&m->ctx->prof, ma, b, (const float2*)xil, y, s);
+      full_launch_il<2, float, YT>(&m->ctx->prof, ma, sp, b, (const float2*)xil, y, s);
     else
-      full_launch_il<2, double, YT>(&m->ctx->prof, ma, b, (const double2*)xil, y, s);
+      full_launch_il<2, double, YT>(&m->ctx->prof, ma, nullptr, b, (const double2*)xil, y, s);
   } else {
     if (fp32)
-      full_launch_il<3, float, YT>(&m->ctx->prof, ma, b, (const float2*)xil, y, s);
+      full_launch_il<3, float, YT>(&m->ctx->prof, ma, sp, b, (const float2*)xil, y, s);
     else
-      full_launch_il<3, double, YT>(&m->ctx->prof, ma, b, (const double2*)xil, y, s);
+      full_launch_il<3, double, YT>(&m->ctx->prof, ma, nullptr, b, (const double2*)xil, y, s);
   }
   if (fp32)
     wk_launch<float2, true, YT>(m, b, SPMV_APPLY, SV<float2>{}, (const float2*)xil, y, s);
