@@ -39,7 +39,8 @@ sys.path.insert(0, ROOT)
 from workloads import cases  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_pipe200k.json")
+TRAFFIC_FILES = {"tree": os.path.join(ROOT, "profiles", "traffic_tree12m.json"),
+                 "pipe": os.path.join(ROOT, "profiles", "traffic_pipe200k.json")}
 
 
 def parse(argv=None):
@@ -51,7 +52,7 @@ def parse(argv=None):
     ap.add_argument("--tets", type=int, default=None, help="default: 12,000,000 (tree), 200,000 (pipe)")
     ap.add_argument("--harmonics", type=int, default=None, help="default: 64 (tree), 16 (pipe)")
     ap.add_argument("--batch", type=int, default=None,
-                    help="systems per step (a wave); default: 6 (tree), all (pipe)")
+                    help="systems per step (a wave); default: 2 (tree), all (pipe)")
     ap.add_argument("--rtol", type=float, default=None,
                     help="relative residual; default 2e-12 (tree), 4e-12 (pipe), which keep every mode "
                          "within 1e-8 of the reference (the tree's steady pressure has the largest "
@@ -136,12 +137,13 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def stored_traffic(kernel: str):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, or
-    None when absent or taken on different kernel sources."""
+def stored_traffic(kernel: str, workload: str):
+    """Bytes per launch beyond L2 (FETCH_SIZE + WRITE_SIZE, copy-calibrated) from the
+    committed rocprofv3 counter summary of this workload, or None when absent or
+    taken on different kernel sources."""
     from paper_2009_06725_amd.rocprof_summary import kernel_source_hash
     try:
-        with open(TRAFFIC_FILE) as fh:
+        with open(TRAFFIC_FILES[workload]) as fh:
             t = json.load(fh)
     except (OSError, ValueError):
         return None
@@ -446,7 +448,7 @@ def main():
         per = by / n
         avg_s = ms / n / 1e3
         gbs = per / avg_s / 1e9
-        tr = stored_traffic(name)
+        tr = stored_traffic(name, args.workload)
         return {"kernel": name, "bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": gbs / HBM_PEAK_GBS, "traffic": tr, "bytes_per_launch": per,
                 "avg_launch_us": avg_s * 1e6, "launches": n,

@@ -1056,6 +1056,124 @@ __global__ void __launch_bounds__(256) k_mg_step_sell2(LevelArgs<float> la, Sell
   }
 }
 
+// Value of lane U of each group of four lanes (DPP quad broadcast).
+template <int U>
+__device__ __forceinline__ int quad_bcast(int v) {
+  return __builtin_amdgcn_mov_dpp(v, U * 0x55, 0xF, 0xF, false);
+}
+template <int U>
+__device__ __forceinline__ float quad_bcast(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), U * 0x55, 0xF, 0xF, false));
+}
+
+// k_mg_step_sell2 for rows of 6 or 8 pairs (four lanes per row): the four lanes of a
+// row load four consecutive entries' (column, K, M) at once and share them by quad
+// broadcasts, so a wavefront issues one index and value load per four entries.
+template <int PD, bool MASS, int MODE>
+__global__ void __launch_bounds__(256) k_mg_step_sell4(LevelArgs<float> la, SellArgs<float> sa, Batch b, SellMap sm,
+                                                       const double* __restrict__ lam, double lamc, double ratio,
+                                                       ChebStep cs, int first, const float2* __restrict__ xk,
+                                                       const float2* __restrict__ xo, const float2* __restrict__ bb,
+                                                       float2* __restrict__ xn) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t q = (row_block() * 4 + wave) * 16 + lane / 4;  // sm.W == 4: 16 rows per wavefront
+  if (q >= sa.nslot) return;
+  const int32_t i = sa.row[q];
+  if (i < 0) return;  // uniform over the four lanes of the row
+  const int64_t sl = q / SELL_C, e0 = sa.off[sl] + q % SELL_C;
+  const int len = (int)((sa.off[sl + 1] - sa.off[sl]) / SELL_C);
+  const bool dir = la.dmask && la.dmask[i] != 0;
+  const int G = sm.G, li = lane & 3, p0 = 2 * li;
+  const bool act = p0 < G;
+  const int64_t o = (int64_t)i * G + p0;
+  if (dir) {
+    if (act) *reinterpret_cast<float4*>(xn + o) = make_float4(0.f, 0.f, 0.f, 0.f);
+    return;
+  }
+  const int slot0 = b.act[act ? p0 / PD : 0], slot1 = b.act[act ? (p0 + 1) / PD : 0];
+  const float w0 = MASS ? (float)(b.omega[slot0] * (double)la.rho) : 0.f;
+  const float w1 = MASS ? (float)(b.omega[slot1] * (double)la.rho) : 0.f;
+  float2 a0 = make_float2(0.f, 0.f), a1 = make_float2(0.f, 0.f);
+  const float2* __restrict__ xs = xk + p0;
+  for (int t = 0; t < len; t += 8) {
+    int32_t cl[2];
+    float kl[2], ml[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const bool v = t + 4 * h + li < len;
+      const int64_t e = e0 + (int64_t)(t + 4 * h + li) * SELL_C;
+      cl[h] = v ? sa.col[e] : -1;
+      kl[h] = v ? sa.K[e] : 0.f;
+      ml[h] = (MASS && v) ? sa.M[e] : 0.f;
+    }
+    int32_t c[8];
+    float k[8], m[8];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      c[4 * h + 0] = quad_bcast<0>(cl[h]);
+      c[4 * h + 1] = quad_bcast<1>(cl[h]);
+      c[4 * h + 2] = quad_bcast<2>(cl[h]);
+      c[4 * h + 3] = quad_bcast<3>(cl[h]);
+      k[4 * h + 0] = quad_bcast<0>(kl[h]);
+      k[4 * h + 1] = quad_bcast<1>(kl[h]);
+      k[4 * h + 2] = quad_bcast<2>(kl[h]);
+      k[4 * h + 3] = quad_bcast<3>(kl[h]);
+      if (MASS) {
+        m[4 * h + 0] = quad_bcast<0>(ml[h]);
+        m[4 * h + 1] = quad_bcast<1>(ml[h]);
+        m[4 * h + 2] = quad_bcast<2>(ml[h]);
+        m[4 * h + 3] = quad_bcast<3>(ml[h]);
+      } else {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) m[4 * h + u] = 0.f;
+      }
+    }
+    float4 xv[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      xv[u] = (act && c[u] >= 0) ? *reinterpret_cast<const float4*>(xs + (int64_t)c[u] * G)
+                                 : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const float kr = la.mu * k[u], ki0 = w0 * m[u], ki1 = w1 * m[u];
+      a0.x += kr * xv[u].x - ki0 * xv[u].y;
+      a0.y += kr * xv[u].y + ki0 * xv[u].x;
+      a1.x += kr * xv[u].z - ki1 * xv[u].w;
+      a1.y += kr * xv[u].w + ki1 * xv[u].z;
+    }
+  }
+  if (!act) return;
+  const float4 bv = *reinterpret_cast<const float4*>(bb + o);
+  float2 r0 = make_float2(bv.x - a0.x, bv.y - a0.y), r1 = make_float2(bv.z - a1.x, bv.w - a1.y);
+  if (MODE == MG_RESID) {
+    *reinterpret_cast<float4*>(xn + o) = make_float4(r0.x, r0.y, r1.x, r1.y);
+    return;
+  }
+  const float4 xv = *reinterpret_cast<const float4*>(xk + o);
+  const float4 x0 = (xo && !first) ? *reinterpret_cast<const float4*>(xo + o) : make_float4(0.f, 0.f, 0.f, 0.f);
+  const float a = first ? 0.f : (float)(cs.rcur * cs.rprev);
+  float4 w;
+  {
+    const double lm_ = lam ? lam[slot0] : lamc;
+    const float dr = la.mu * la.Kd[i], di = MASS ? w0 * la.Md[i] : 0.f;
+    const float2 d = cdiv<float, float2>(r0, dr, di);
+    const float cc = first ? (float)(1.0 / (0.5 * lm_ * (1.0 + 1.0 / ratio)))
+                           : (float)(2.0 * cs.rcur / (0.5 * lm_ * (1.0 - 1.0 / ratio)));
+    w.x = xv.x + a * (xv.x - x0.x) + cc * d.x;
+    w.y = xv.y + a * (xv.y - x0.y) + cc * d.y;
+  }
+  {
+    const double lm_ = lam ? lam[slot1] : lamc;
+    const float dr = la.mu * la.Kd[i], di = MASS ? w1 * la.Md[i] : 0.f;
+    const float2 d = cdiv<float, float2>(r1, dr, di);
+    const float cc = first ? (float)(1.0 / (0.5 * lm_ * (1.0 + 1.0 / ratio)))
+                           : (float)(2.0 * cs.rcur / (0.5 * lm_ * (1.0 - 1.0 / ratio)));
+    w.z = xv.z + a * (xv.z - x0.z) + cc * d.x;
+    w.w = xv.w + a * (xv.w - x0.w) + cc * d.y;
+  }
+  *reinterpret_cast<float4*>(xn + o) = w;
+}
+
 // k_mg_restrict for long restriction rows.
 template <class R, int PD, bool MASS>
 __global__ void __launch_bounds__(256) k_mg_restrict_split(XferArgs<R> rt, LevelArgs<R> lc, Batch b, SplitMap sm,
@@ -1260,6 +1378,15 @@ int mg_cycle(const MgHier& H, const std::vector<LevelArgs<R>>& las, const SellAr
   const unsigned nbsell2 = (unsigned)((sell0.nslot + 4 * sm2.R - 1) / (4 * sm2.R));
   auto step = [&](int mode, ChebStep cs, int first, const C* xk, const C* xo, C* xn) {
     if constexpr (sizeof(R) == 4) {
+      if (l == 0 && sell0.off && two && sm2.W == 4) {
+        if (mode == MG_STEP)
+          k_mg_step_sell4<PD, MASS, MG_STEP><<<nbsell2, 256, 0, s>>>(la, sell0, b, sm2, lam, lamc, ratio, cs, first,
+                                                                      xk, xo, arr(0), xn);
+        else
+          k_mg_step_sell4<PD, MASS, MG_RESID><<<nbsell2, 256, 0, s>>>(la, sell0, b, sm2, lam, lamc, ratio, cs, first,
+                                                                       xk, xo, arr(0), xn);
+        return;
+      }
       if (l == 0 && sell0.off && two) {
         if (mode == MG_STEP)
           k_mg_step_sell2<PD, MASS, MG_STEP><<<nbsell2, 256, 0, s>>>(la, sell0, b, sm2, lam, lamc, ratio, cs, first,
