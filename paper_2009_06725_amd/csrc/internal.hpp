@@ -149,19 +149,7 @@ namespace scvs {
 // One level of an aggregation multigrid hierarchy (device): its operator pair (K, M;
 // M empty for a single-matrix hierarchy) with diagonals, FP32 copies, and the
 // transfer to the next coarser level, P (n x nc) and R = P^T (nc x n).
-struct MgLevel {
-  int64_t n = 0, nnz = 0, nc = 0;
-  DBuf<int64_t> ptr;
-  DBuf<int32_t> col;
-  DBuf<double> K, M, Kd, Md;
-  DBuf<float> K32, M32, Kd32, Md32;
-  DBuf<int64_t> pptr, rptr;
-  DBuf<int32_t> pcol, rcol;
-  DBuf<double> pval, rval;
-  DBuf<float> pval32, rval32;
-  double lam = 0.0;  // Gershgorin bound of D^-1 K (single-matrix hierarchies)
-};
-// Sliced rows of a level-0 operator for the wide row kernels: rows are ordered by
+// Sliced rows of an operator for the wide row kernels: rows are ordered by
 // length (longest first, ties by index) inside windows of SELL_WIN consecutive rows
 // and cut into slices of SELL_C rows; entry t of the r-th row of slice s sits at
 // off[s] + t * SELL_C + r, so that one wavefront load of entry t covers SELL_C rows
@@ -180,6 +168,20 @@ struct Sell {
   DBuf<float> K32, M32;
   DBuf<double> K, M;
 };
+
+struct MgLevel {
+  int64_t n = 0, nnz = 0, nc = 0;
+  DBuf<int64_t> ptr;
+  DBuf<int32_t> col;
+  DBuf<double> K, M, Kd, Md;
+  DBuf<float> K32, M32, Kd32, Md32;
+  DBuf<int64_t> pptr, rptr;
+  DBuf<int32_t> pcol, rcol;
+  DBuf<double> pval, rval;
+  DBuf<float> pval32, rval32;
+  double lam = 0.0;  // Gershgorin bound of D^-1 K (single-matrix hierarchies)
+  Sell sell;         // levels below 0 with at least MG_SELL_MIN rows: the operator in sliced rows
+};
 struct MgHier {
   std::vector<MgLevel> lv;
   Sell sell0;  // pressure: level 0 in sliced rows (the velocity's level 0 is the mesh's S2)
@@ -188,6 +190,7 @@ struct MgHier {
   DBuf<float2> cinv32;
 };
 constexpr int MG_COARSE_MAX = 256;  // rows of the coarsest level (inverted densely)
+constexpr int64_t MG_SELL_MIN = 65536;  // coarse levels at least this large also get sliced rows
 struct MgData {
   uint64_t gen = ~0ull;  // operator generation it was built for
   MgHier vel;            // lv[0]: the quadratic pattern (transfer only), then P1 and aggregates

@@ -348,6 +348,16 @@ void build_below(MgHier& H, HCsr A, int coarse_max, double theta, hipStream_t s)
     HCsr Ac = spgemm(transpose(P), AP);
     upload_level(L, A, s);
     upload_transfer(L, P, s);
+    if (H.lv.size() > 1 && A.n >= MG_SELL_MIN) {  // large coarse levels: sliced rows too
+      sell_build(L.sell, A.ptr, A.n, A.n, L.ptr, L.col, s);
+      sell_values<double>(L.sell, L.ptr, L.K.p, L.sell.K, s);
+      sell_values<float>(L.sell, L.ptr, L.K32.p, L.sell.K32, s);
+      if (!A.b.empty()) {
+        sell_values<double>(L.sell, L.ptr, L.M.p, L.sell.M, s);
+        sell_values<float>(L.sell, L.ptr, L.M32.p, L.sell.M32, s);
+      }
+      SCVS_HIP(hipStreamSynchronize(s));
+    }
     A = std::move(Ac);
   }
 }
@@ -1334,6 +1344,23 @@ struct CoarseInv {
   int64_t ist;      // elements between the inverses of two slots (0: one for all)
 };
 
+// A level in sliced rows with values in precision R; all null (the CSR kernels run)
+// when it has no sliced copy or those values were not filled.
+template <class R>
+SellArgs<R> sell_args(const Sell& S, bool mass) {
+  const R* K;
+  const R* M;
+  if constexpr (sizeof(R) == 4) {
+    K = S.K32.p;
+    M = S.M32.p;
+  } else {
+    K = S.K.p;
+    M = S.M.p;
+  }
+  if (!K || (mass && !M)) return {0, nullptr, nullptr, nullptr, nullptr, nullptr};
+  return {S.nslot, S.off, S.row, S.col, K, mass ? M : nullptr};
+}
+
 template <class R, int PD, bool MASS>
 int mg_cycle(const MgHier& H, const std::vector<LevelArgs<R>>& las, const SellArgs<R>& sell0,
              const std::vector<void*>& bufs, const std::vector<const double*>& lams, int l, const Batch& b, int nu,
@@ -1368,41 +1395,43 @@ int mg_cycle(const MgHier& H, const std::vector<LevelArgs<R>>& las, const SellAr
   // one smoothing or residual launch on this level: split rows when they are long
   const SplitMap sm = split_map(lm, la.n ? (double)nnz / (double)la.n : 0.0);
   const unsigned nbs = (unsigned)((la.n + sm.RB - 1) / sm.RB);
+  // level 0: the caller's sliced rows; large coarse levels: their own
+  const SellArgs<R> sl = l == 0 ? sell0 : sell_args<R>(H.lv[l].sell, MASS);
   const SellMap ssm = sell_map(b.nact, PD);
-  const unsigned nbsell = (unsigned)((sell0.nslot + 4 * ssm.R - 1) / (4 * ssm.R));
+  const unsigned nbsell = (unsigned)((sl.nslot + 4 * ssm.R - 1) / (4 * ssm.R));
   // two pairs per lane (FP32, even G): W lanes per row cover the G pairs in 16-byte loads
   const bool two = sizeof(R) == 4 && lm.G % 2 == 0;
   SellMap sm2{lm.G, 1, 64};
   while (sm2.W < lm.G / 2 && sm2.W < 64) sm2.W <<= 1;
   sm2.R = 64 / sm2.W;
-  const unsigned nbsell2 = (unsigned)((sell0.nslot + 4 * sm2.R - 1) / (4 * sm2.R));
+  const unsigned nbsell2 = (unsigned)((sl.nslot + 4 * sm2.R - 1) / (4 * sm2.R));
   auto step = [&](int mode, ChebStep cs, int first, const C* xk, const C* xo, C* xn) {
     if constexpr (sizeof(R) == 4) {
-      if (l == 0 && sell0.off && two && sm2.W == 4) {
+      if (sl.off && two && sm2.W == 4) {
         if (mode == MG_STEP)
-          k_mg_step_sell4<PD, MASS, MG_STEP><<<nbsell2, 256, 0, s>>>(la, sell0, b, sm2, lam, lamc, ratio, cs, first,
+          k_mg_step_sell4<PD, MASS, MG_STEP><<<nbsell2, 256, 0, s>>>(la, sl, b, sm2, lam, lamc, ratio, cs, first,
                                                                       xk, xo, arr(0), xn);
         else
-          k_mg_step_sell4<PD, MASS, MG_RESID><<<nbsell2, 256, 0, s>>>(la, sell0, b, sm2, lam, lamc, ratio, cs, first,
+          k_mg_step_sell4<PD, MASS, MG_RESID><<<nbsell2, 256, 0, s>>>(la, sl, b, sm2, lam, lamc, ratio, cs, first,
                                                                        xk, xo, arr(0), xn);
         return;
       }
-      if (l == 0 && sell0.off && two) {
+      if (sl.off && two) {
         if (mode == MG_STEP)
-          k_mg_step_sell2<PD, MASS, MG_STEP><<<nbsell2, 256, 0, s>>>(la, sell0, b, sm2, lam, lamc, ratio, cs, first,
+          k_mg_step_sell2<PD, MASS, MG_STEP><<<nbsell2, 256, 0, s>>>(la, sl, b, sm2, lam, lamc, ratio, cs, first,
                                                                       xk, xo, arr(0), xn);
         else
-          k_mg_step_sell2<PD, MASS, MG_RESID><<<nbsell2, 256, 0, s>>>(la, sell0, b, sm2, lam, lamc, ratio, cs, first,
+          k_mg_step_sell2<PD, MASS, MG_RESID><<<nbsell2, 256, 0, s>>>(la, sl, b, sm2, lam, lamc, ratio, cs, first,
                                                                        xk, xo, arr(0), xn);
         return;
       }
     }
-    if (l == 0 && sell0.off) {
+    if (sl.off) {
       if (mode == MG_STEP)
-        k_mg_step_sell<R, PD, MASS, MG_STEP><<<nbsell, 256, 0, s>>>(la, sell0, b, ssm, lam, lamc, ratio, cs, first,
+        k_mg_step_sell<R, PD, MASS, MG_STEP><<<nbsell, 256, 0, s>>>(la, sl, b, ssm, lam, lamc, ratio, cs, first,
                                                                      xk, xo, arr(0), xn);
       else
-        k_mg_step_sell<R, PD, MASS, MG_RESID><<<nbsell, 256, 0, s>>>(la, sell0, b, ssm, lam, lamc, ratio, cs, first,
+        k_mg_step_sell<R, PD, MASS, MG_RESID><<<nbsell, 256, 0, s>>>(la, sl, b, ssm, lam, lamc, ratio, cs, first,
                                                                       xk, xo, arr(0), xn);
     } else if (sm.S > 1) {
       if (mode == MG_STEP)
@@ -1523,22 +1552,6 @@ std::vector<LevelArgs<R>> pres_levels(scvs_mesh m) {
   return las;
 }
 
-// Level 0 in sliced rows with values in precision R; all null (the CSR kernels run)
-// when those values were not filled.
-template <class R>
-SellArgs<R> sell_args(const Sell& S, bool mass) {
-  const R* K;
-  const R* M;
-  if constexpr (sizeof(R) == 4) {
-    K = S.K32.p;
-    M = S.M32.p;
-  } else {
-    K = S.K.p;
-    M = S.M.p;
-  }
-  if (!K || (mass && !M)) return {0, nullptr, nullptr, nullptr, nullptr, nullptr};
-  return {S.nslot, S.off, S.row, S.col, K, mass ? M : nullptr};
-}
 
 template <class R, int D>
 void vel_cycle(scvs_mesh m, const Batch& b, const PrecondArgs& pa, void* zil, SV<typename CplxOf<R>::C> z,

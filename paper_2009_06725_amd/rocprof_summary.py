@@ -45,15 +45,20 @@ def short_name(demangled: str) -> str:
     if base == "k_full":
         mode = targs.split(",")[1].strip() if "," in targs else "0"
         return {"0": "k_full_apply", "1": "k_full_resid", "2": "k_full_rhs"}.get(mode, "k_full") + ("32" if f32 else "")
+    if base == "k_full_sell":  # the FP32 operator product of the Krylov cycles in sliced rows
+        return "k_full_apply32"
+    if base == "k_vinit_sell":
+        return "k_vinit32"
     if base in ("k_vstep", "k_vinit"):
         return base + ("32" if f32 else "")
     if base in ("k_pstep", "k_pinit"):  # <input type, recurrence real type>
         return base + ("32" if targs.split(",")[-1].strip() == "float" else "")
-    if base in ("k_mg_step", "k_mg_step_split", "k_mg_step_sell"):  # <real, PD, mass, mode>
+    if base.startswith("k_mg_step"):  # <real, PD, mass, mode> or (two-pair forms) <PD, mass, mode>
         ta = [t.strip() for t in targs.split(",")]
-        if len(ta) == 4:  # level 0 runs in sliced rows, the coarse levels in CSR
-            return (f"k_mg{'p' if ta[1] == '1' else 'v'}_{'smooth' if ta[3] == '0' else 'resid'}"
-                    + ("0" if base == "k_mg_step_sell" else ""))
+        if len(ta) in (3, 4):  # level 0 runs in sliced rows (so do large coarse levels: see traffic)
+            pd, mode = ta[-3], ta[-1]
+            return (f"k_mg{'p' if pd == '1' else 'v'}_{'smooth' if mode == '0' else 'resid'}"
+                    + ("0" if base.startswith("k_mg_step_sell") else ""))
     if base == "k_dots" and targs.strip() == "1":
         return "k_dots1"
     if base == "k_update" and targs.strip() == "2":
@@ -101,8 +106,13 @@ def traffic(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, copy_bytes, ou
     kf = cf[ck][0] * 1024.0 / copy_bytes  # counter KiB * 1024 per byte actually read
     kw = cw[ck][0] * 1024.0 / copy_bytes if ck in cw else 1.0
     per = {}
+    top = defaultdict(int)  # largest grid per kernel: a sliced-row multigrid kernel's level 0
+    for (k, g) in fetch:
+        top[k] = max(top[k], g)
     for k, (fv, n) in fetch.items():
         sk = short_name(k[0])
+        if "k_mg_step_sell" in k[0] and k[1] < top[k[0]]:
+            sk = sk[:-1]  # the same kernel on a large coarse level
         wv = write.get(k, (0.0, 0))[0]
         b = fv * 1024.0 / kf + wv * 1024.0 / kw
         if sk in per:  # several instantiations with one profiler name: weight by dispatches

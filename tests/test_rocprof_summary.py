@@ -25,7 +25,11 @@ from paper_2009_06725_amd.rocprof_summary import short_name, traffic
     ("void scvs::(anonymous namespace)::k_mg_step_sell<float, 3, true, 1>(...)", "k_mgv_resid0"),
     ("void scvs::(anonymous namespace)::k_mg_step_sell<double, 1, false, 0>(...)", "k_mgp_smooth0"),
     ("void scvs::(anonymous namespace)::k_mg_step<float, 3, true, 0>(...)", "k_mgv_smooth"),
+    ("void scvs::(anonymous namespace)::k_mg_step_sell4<3, true, 0>(...)", "k_mgv_smooth0"),
+    ("void scvs::(anonymous namespace)::k_mg_step_sell2<1, false, 1>(...)", "k_mgp_resid0"),
     ("void scvs::(anonymous namespace)::k_mg_step_split<float, 1, false, 1>(...)", "k_mgp_resid"),
+    ("void scvs::(anonymous namespace)::k_full_sell<3, HIP_vector_type<double, 2u> >(...)", "k_full_apply32"),
+    ("void scvs::(anonymous namespace)::k_vinit_sell<3, HIP_vector_type<double, 2u> >(...)", "k_vinit32"),
     ("__amd_rocclr_copyBuffer", "__amd_rocclr_copyBuffer"),
 ])
 def test_short_names(demangled, name):
@@ -39,6 +43,26 @@ def _write(dirpath, counter, rows):
         w.writeheader()
         for k, v in rows:
             w.writerow({"Kernel_Name": k, "Grid_Size": 256, "Counter_Name": counter, "Counter_Value": v})
+
+
+def test_sliced_kernel_on_a_coarse_level(tmp_path):
+    """A sliced-row multigrid kernel's largest grid is level 0; smaller grids are coarse levels."""
+    copy = "__amd_rocclr_copyBuffer"
+    nbytes = 1 << 20
+    _write(tmp_path / "cf", "FETCH_SIZE", [(copy, nbytes / 1024 / 2)])
+    _write(tmp_path / "cw", "WRITE_SIZE", [(copy, nbytes / 1024)])
+    k = "void scvs::(anonymous namespace)::k_mg_step_sell2<1, false, 0>(...)"
+    for d, c in (("f", "FETCH_SIZE"), ("w", "WRITE_SIZE")):
+        (tmp_path / d).mkdir()
+        with open(tmp_path / d / "run_counter_collection.csv", "w", newline="") as fh:
+            w = csv.DictWriter(fh, fieldnames=["Kernel_Name", "Grid_Size", "Counter_Name", "Counter_Value"])
+            w.writeheader()
+            w.writerow({"Kernel_Name": k, "Grid_Size": 4096, "Counter_Name": c, "Counter_Value": 10.0})
+            w.writerow({"Kernel_Name": k, "Grid_Size": 512, "Counter_Name": c, "Counter_Value": 1.0})
+    r = traffic(str(tmp_path / "f"), str(tmp_path / "w"), str(tmp_path / "cf"), str(tmp_path / "cw"), nbytes,
+                str(tmp_path / "t.json"))
+    assert r["dispatches"] == {"k_mgp_smooth0": 1, "k_mgp_smooth": 1}
+    assert r["bytes_per_launch"]["k_mgp_smooth0"] == pytest.approx((20.0 + 10.0) * 1024)
 
 
 def test_traffic_scaling(tmp_path):
