@@ -456,7 +456,7 @@ __global__ void __launch_bounds__(RBS) k_lag_dots(KArgs a, int j, int final) {
   if (st.jstop >= 0) return;
   const int t = threadIdx.x;
   const int nrow = final ? j + 1 : j + 2;  // V_0..V_j, and W = V_{j+1}
-  int tn = 32;
+  int tn = 128;  // the widest tile that fits: longer contiguous runs of every vector
   while (tn > 4 && nrow * tn > TL) tn >>= 1;
   const int tp = tn + 1;
   int64_t b0, b1;
