@@ -155,7 +155,11 @@ int scvs_assemble(scvs_mesh mesh, double rho, double mu);
  *  SCVS_X_DIRNODES int32[ndir]       ascending DIRICHLET node ids
  *  SCVS_X_DMASK    int32[n2]         0 free, 1 wall, 2 Dirichlet
  *  SCVS_X_LOADS    double[ntraction][n2][dim]
- *  SCVS_X_NODEXYZ  double[n2][dim]   node coordinates (vertices, then midside) */
+ *  SCVS_X_NODEXYZ  double[n2][dim]   node coordinates (vertices, then midside)
+ *  SCVS_X_C21PTR   int64[n2+1]       C21 row pointers (quadratic node -> vertex
+ *                                    columns of the cells containing it)
+ *  SCVS_X_C21COL   int32[nnz_c21]    C21 columns, ascending per row (the S2 row's
+ *                                    vertex-column prefix; section 2.3, Eq. shape_fun) */
 #define SCVS_X_EDGES 0
 #define SCVS_X_C2N 1
 #define SCVS_X_ROWPTR 2
@@ -168,6 +172,8 @@ int scvs_assemble(scvs_mesh mesh, double rho, double mu);
 #define SCVS_X_DMASK 9
 #define SCVS_X_LOADS 10
 #define SCVS_X_NODEXYZ 11
+#define SCVS_X_C21PTR 12
+#define SCVS_X_C21COL 13
 int scvs_mesh_export(scvs_mesh mesh, int which, void* out_host);
 
 /* ---- a4: multi-system complex SpMV (section 2.3, Eq. linear_sys_def) ----

@@ -301,6 +301,19 @@ int scvs_mesh_export(scvs_mesh m, int which, void* out) {
         memcpy((double*)out + h.size(), e.data(), e.size() * sizeof(double));
         break;
       }
+      case SCVS_X_C21PTR: scvs::download((int64_t*)out, m->rowptr21.p, m->n2 + 1, s); break;
+      case SCVS_X_C21COL: {
+        // C21 is stored as the vertex-column prefix of each S2 row
+        std::vector<int64_t> rp(m->n2 + 1);
+        std::vector<int32_t> col(m->nnz), nvc(m->n2);
+        scvs::download(rp.data(), m->rowptr.p, m->n2 + 1, s);
+        scvs::download(col.data(), m->col.p, m->nnz, s);
+        scvs::download(nvc.data(), m->nvc.p, m->n2, s);
+        int32_t* o = (int32_t*)out;
+        for (int64_t a = 0; a < m->n2; ++a)
+          for (int32_t k = 0; k < nvc[a]; ++k) *o++ = col[rp[a] + k];
+        break;
+      }
       default: fail(SCVS_E_INVALID, "unknown export selector");
     }
   });

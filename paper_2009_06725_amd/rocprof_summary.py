@@ -80,6 +80,30 @@ def kernels_table(db: str, top: int = 20) -> str:
     return "\n".join(out)
 
 
+def level_table(db: str) -> str:
+    """Per grid size (largest first: level 0, then the large coarse levels) the
+    dispatches and mean duration of the sliced-row multigrid kernels, which serve
+    several levels under one name."""
+    con = sqlite3.connect(db)
+    q = ("select s.display_name, d.grid_size_x, d.end - d.start from rocpd_kernel_dispatch d "
+         "join rocpd_info_kernel_symbol s on d.kernel_id = s.id")
+    agg = defaultdict(lambda: [0, 0.0])
+    for name, grid, dur in con.execute(q):
+        if "k_mg_step_sell" not in name:
+            continue
+        nm = name.replace("scvs::(anonymous namespace)::", "").replace("void ", "").split("(")[0]
+        a = agg[(nm, int(grid))]
+        a[0] += 1
+        a[1] += dur
+    top = defaultdict(int)
+    for (nm, g) in agg:
+        top[nm] = max(top[nm], g)
+    out = ["| kernel | level | grid (threads) | calls | avg us |", "|---|---|---|---|---|"]
+    for (nm, g), (n, t) in sorted(agg.items(), key=lambda kv: (kv[0][0], -kv[0][1])):
+        out.append(f"| {nm} | {'0' if g == top[nm] else 'coarse'} | {g} | {n} | {t / n / 1e3:.1f} |")
+    return "\n".join(out)
+
+
 def counter_means(path: str, counter: str) -> dict:
     """Mean value per dispatch of `counter` for every (kernel, grid size) in a
     --pmc CSV run (the multigrid kernels serve several levels of different sizes)."""
@@ -135,6 +159,8 @@ def main():
     k = sub.add_parser("kernels")
     k.add_argument("db")
     k.add_argument("--top", type=int, default=20)
+    lv = sub.add_parser("levels")
+    lv.add_argument("db")
     t = sub.add_parser("traffic")
     t.add_argument("--fetch", required=True)
     t.add_argument("--write", required=True)
@@ -145,6 +171,8 @@ def main():
     a = ap.parse_args()
     if a.cmd == "kernels":
         print(kernels_table(a.db, a.top))
+    elif a.cmd == "levels":
+        print(level_table(a.db))
     else:
         r = traffic(a.fetch, a.write, a.copy_fetch, a.copy_write, a.copy_bytes, a.out)
         print(json.dumps(r, indent=1))

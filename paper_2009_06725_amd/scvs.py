@@ -17,7 +17,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libscvs.so")
 
 BC_FREE, BC_WALL, BC_DIRICHLET, BC_TRACTION = 0, 1, 2, 3
-X_EDGES, X_C2N, X_ROWPTR, X_COL, X_KS, X_M, X_G, X_MP, X_DIRNODES, X_DMASK, X_LOADS, X_NODEXYZ = range(12)
+(X_EDGES, X_C2N, X_ROWPTR, X_COL, X_KS, X_M, X_G, X_MP, X_DIRNODES, X_DMASK, X_LOADS, X_NODEXYZ, X_C21PTR,
+ X_C21COL) = range(14)
 
 EXPORTED = [
     "scvs_last_error", "scvs_version", "scvs_ctx_create", "scvs_ctx_destroy", "scvs_mesh_create",
@@ -279,7 +280,8 @@ class Mesh:
                 X_KS: (np.float64, (i.nnz_s2,)), X_M: (np.float64, (i.nnz_s2,)),
                 X_G: (np.float64, (d, i.nnz_c21)), X_MP: (np.float64, (i.nv,)),
                 X_DIRNODES: (np.int32, (i.ndir,)), X_DMASK: (np.int32, (i.n2,)),
-                X_LOADS: (np.float64, (i.ntraction, i.n2, d)), X_NODEXYZ: (np.float64, (i.n2, d))}
+                X_LOADS: (np.float64, (i.ntraction, i.n2, d)), X_NODEXYZ: (np.float64, (i.n2, d)),
+                X_C21PTR: (np.int64, (i.n2 + 1,)), X_C21COL: (np.int32, (i.nnz_c21,))}
         dt, shape = spec[which]
         out = np.zeros(max(1, int(np.prod(shape))), dt)
         _check(lib().scvs_mesh_export(self.h, which, out.ctypes.data_as(C.c_void_p)))

@@ -77,6 +77,9 @@ def test_numbering_and_pattern_bitexact(setup):
     assert np.array_equal(m.export(scvs.X_ROWPTR), rp)
     assert np.array_equal(m.export(scvs.X_COL), col)
     assert info.nnz_c21 == asm["C21"][1].size
+    rp21, col21 = asm["C21"]
+    assert np.array_equal(m.export(scvs.X_C21PTR), rp21)
+    assert np.array_equal(m.export(scvs.X_C21COL), col21)
 
 
 def test_boundary_sets_bitexact(setup):
