@@ -1066,6 +1066,48 @@ __global__ void __launch_bounds__(256) k_mg_step_sell2(LevelArgs<float> la, Sell
   }
 }
 
+// k_mg_bound on level 0 in sliced rows: one lane per (row, system), the same sums in
+// the same entry order, FP64 accumulation of the sliced values (FP32 values on the
+// mixed path).
+template <class R>
+__global__ void __launch_bounds__(256) k_mg_bound_sell(LevelArgs<double> la, SellArgs<R> sa, Batch b, int W, int RW,
+                                                       unsigned long long* __restrict__ out) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t q = (row_block() * 4 + wave) * RW + lane / W;
+  if (q >= sa.nslot) return;
+  const int32_t i = sa.row[q];
+  if (i < 0) return;
+  if (la.dmask && la.dmask[i] != 0) return;
+  const int64_t sl = q / SELL_C, e0 = sa.off[sl] + q % SELL_C;
+  const int len = (int)((sa.off[sl + 1] - sa.off[sl]) / SELL_C);
+  for (int si = lane & (W - 1); si < b.nact; si += W) {
+    const int slot = b.act[si];
+    const double wr = b.omega[slot] * la.rho;
+    double sum = 0.0;
+    for (int t = 0; t < len; t += 4) {
+      int32_t c[4];
+      double k[4], m[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const bool v = t + u < len;
+        const int64_t e = e0 + (int64_t)(t + u) * SELL_C;
+        c[u] = v ? sa.col[e] : -1;
+        k[u] = v ? (double)sa.K[e] : 0.0;
+        m[u] = v ? (double)sa.M[e] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if (c[u] < 0 || (la.dmask && la.dmask[c[u]] != 0)) continue;
+        const double re = la.mu * k[u], im = wr * m[u];
+        sum += sqrt(re * re + im * im);
+      }
+    }
+    const double dr = la.mu * la.Kd[i], di = wr * la.Md[i];
+    const double v = sum / sqrt(dr * dr + di * di);
+    atomicMax(&out[slot], (unsigned long long)__double_as_longlong(v));
+  }
+}
+
 // Value of lane U of each group of four lanes (DPP quad broadcast).
 template <int U>
 __device__ __forceinline__ int quad_bcast(int v) {
@@ -1657,10 +1699,21 @@ void mg_prepare(scvs_mesh m, const Batch& b, double* lam, int slots, double2* in
   const MgHier& H = m->mg->vel;
   const LaneMap lm = lane_map(b.nact, 1);
   const auto las = vel_levels<double>(m);
+  int W = 1;
+  while (W < b.nact && W < 64) W <<= 1;
+  const int RW = 64 / W;
+  const SellArgs<float> s32 = sell_args<float>(m->s2sell, true);
+  const SellArgs<double> s64 = sell_args<double>(m->s2sell, true);
   for (size_t l = 0; l < H.lv.size(); ++l) {
     SCVS_HIP(hipMemsetAsync(lam + l * slots, 0, sizeof(double) * slots, s));
-    k_mg_bound<true><<<row_blocks(las[l].n, lm), 256, 0, s>>>(
-        las[l], b, lm, reinterpret_cast<unsigned long long*>(lam + l * slots));
+    unsigned long long* o = reinterpret_cast<unsigned long long*>(lam + l * slots);
+    // level 0 from its sliced rows in the cycle's precision when they are there
+    if (l == 0 && inv32 && s32.off)
+      k_mg_bound_sell<float><<<(unsigned)((s32.nslot + 4 * RW - 1) / (4 * RW)), 256, 0, s>>>(las[0], s32, b, W, RW, o);
+    else if (l == 0 && !inv32 && s64.off)
+      k_mg_bound_sell<double><<<(unsigned)((s64.nslot + 4 * RW - 1) / (4 * RW)), 256, 0, s>>>(las[0], s64, b, W, RW, o);
+    else
+      k_mg_bound<true><<<row_blocks(las[l].n, lm), 256, 0, s>>>(las[l], b, lm, o);
     launch_check(s);
   }
   ProfScope ps(&m->ctx->prof, s, "k_mg_cinv", 0.0);
