@@ -84,7 +84,9 @@ def parse(argv=None):
     ap.add_argument("--pres-block", choices=["cheb", "mg"], default="mg",
                     help="pressure-Laplacian inverse in the Schur block: Chebyshev polynomial or multigrid")
     ap.add_argument("--mg-smooth", type=int, default=2, help="multigrid smoothing steps per side")
-    ap.add_argument("--mg-ratio", type=float, default=10.0, help="multigrid smoother interval ratio")
+    ap.add_argument("--mg-ratio", type=float, default=None,
+                    help="multigrid smoother interval ratio; default 10 (tree, pipe: every mode converges and "
+                         "it is the fastest there), 4 (ybatch: the library default, robust on the Y meshes)")
     ap.add_argument("--steady-schur-omega", type=float, default=-1.0,
                     help="w of the steady systems' Schur Laplacian term (-1: the largest |w| of the case, 0: off)")
     ap.add_argument("--orth", type=int, choices=[0, 1], default=1,
@@ -116,6 +118,8 @@ def parse(argv=None):
         a.ntimes = 16 if tree else 64
     if a.rtol is None:
         a.rtol = 4e-12 if a.workload == "pipe" else 2e-12
+    if a.mg_ratio is None:
+        a.mg_ratio = 4.0 if a.workload == "ybatch" else 10.0
     if a.batch is None:
         a.batch = 2 if tree else 0
     if a.compare_systems is None:
@@ -370,7 +374,7 @@ def run_ybatch(args):
                       "config": {"workload": "Y-bifurcations (radii 1.0/0.7/0.7, 60 degrees) of about "
                                  f"{'/'.join(f'{x / 1e6:g}' for x in sizes)}M tets, 12 cases each of 32 harmonics "
                                  f"+ mean, own period per case: {solved} systems", "rtol": args.rtol, "restart": args.restart,
-                                 "precision": args.precision},
+                                 "precision": args.precision, "mg_ratio": args.mg_ratio, "mg_smooth": args.mg_smooth},
                       "dof_modes_per_s": dof_modes / total, "setup_seconds": round(t_setup, 1),
                       "converged": conv, "per_mesh": per}), flush=True)
 

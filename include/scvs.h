@@ -241,7 +241,9 @@ typedef struct {
   int32_t mg_smooth;  /* multigrid: Chebyshev smoothing steps before and after each coarse
                          correction, >= 1 */
   double mg_ratio;    /* multigrid: smoothers target [lambda / mg_ratio, lambda] of the level
-                         operator scaled by its complex diagonal, > 1 */
+                         operator scaled by its complex diagonal, > 1 (default 4: wider
+                         intervals smooth less of the complex spectrum, and at some middle
+                         frequencies the cycle then stalls) */
   double steady_schur_omega; /* >= 0: for steady systems (w = 0) the Schur block uses this
                          w in its Laplacian term, mu Mp^-1 + j w_s rho L^-1, instead of the
                          pressure mass alone. The preconditioner acts from the right, so the

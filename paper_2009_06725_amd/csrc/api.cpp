@@ -374,7 +374,7 @@ void scvs_solve_opts_default(scvs_solve_opts* o) {
   o->vel_block = 0;
   o->pres_block = 0;
   o->mg_smooth = 2;
-  o->mg_ratio = 10.0;
+  o->mg_ratio = 4.0;
   o->steady_schur_omega = 0.0;
 }
 
