@@ -825,6 +825,12 @@ __global__ void k_init_x(VArg x, const double2* __restrict__ x0, int64_t x0st, c
     xs[(int64_t)dirnodes[i / D] * D + (i % D)] = g[(int64_t)sys * gst + i];
 }
 
+// a[idx[k]] = 0 for the listed slots (a fill kernel: no memset node in captured work)
+__global__ void k_zero_at(double* a, const int* idx, int n) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) a[idx[k]] = 0.0;
+}
+
 __global__ void k_init_state(SlotState* st, const int* act, int nact) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= nact) return;
@@ -861,7 +867,7 @@ struct Pool {
   DBuf<float2> vt32, z32;
   DBuf<SlotState> st;
   DBuf<double> omega, lv, info;
-  DBuf<int> act, act_all, act_run, stops;
+  DBuf<int> act, act_all, act_run, act_new, stops;
   DBuf<double2> zil;  // interleaved preconditioner output inside a cycle (FP32 pairs in mixed mode)
   DBuf<char> mgbuf;   // multigrid temporaries below level 0
   DBuf<double> mglam; // [velocity level][slot] smoother bounds
@@ -1169,226 +1175,282 @@ int solve_systems(scvs_mesh m, int64_t nsys, const double* omega, const double* 
   std::vector<int> all(B);
   for (int k = 0; k < B; ++k) all[k] = k;
   SCVS_HIP(hipMemcpyAsync(P.act_all.p, all.data(), sizeof(int) * B, hipMemcpyHostToDevice, s));
+  P.act_new.alloc(B);
   int rc = SCVS_OK;
-  for (int64_t first = 0; first < nsys; first += B) {
-    const int nb = (int)std::min<int64_t>(B, nsys - first);
-    SCVS_HIP(hipMemcpyAsync(P.omega.p, omega + first, sizeof(double) * nb, hipMemcpyHostToDevice, s));
-    if (ntr)
-      SCVS_HIP(hipMemcpyAsync(P.trac.p, traction + 2 * first * ntr, sizeof(double2) * nb * ntr,
-                              hipMemcpyHostToDevice, s));
-    SCVS_HIP(hipMemsetAsync(P.lv.p, 0, sizeof(double) * nb, s));
-    Batch b;
-    b.nact = nb;
-    b.act = P.act_all;
-    b.omega = P.omega;
-    b.lv = P.lv;
-    b.pen = o->penalty / m->mu;
-    b.wsteady = o->steady_schur_omega;
-    k_init_state<<<(nb + 63) / 64, 64, 0, s>>>(P.st, P.act_all, nb);
-    const int nch0 = choose_nch(nb, ndof);
-    KArgs a0 = kargs(P, ndof, nch0);
-    a0.act = P.act_all;
-    const dim3 g0((unsigned)nch0, (unsigned)nb);
-    // right-hand sides: F = RHS(x_g), then x = x0 with Dirichlet data
-    const dim3 gi(256, (unsigned)nb);
-    const double2* gp = (const double2*)g;
-    const double2* x0p = (const double2*)x0;
-    if (D == 2) {
-      k_init_x<2><<<gi, 256, 0, s>>>(P.T(), nullptr, 0, gp, m->ndir * D, m->dmask, m->dirnodes, m->ndir, m->n2,
-                                     ndof, P.act_all, (int)first);
-      k_init_x<2><<<gi, 256, 0, s>>>(P.X(), x0p, ndof, gp, m->ndir * D, m->dmask, m->dirnodes, m->ndir, m->n2,
-                                     ndof, P.act_all, (int)first);
+  // Work queue over the slots: a slot whose system has finished takes the next pending
+  // system at the next restart boundary, so a batch never waits for its slowest system
+  // with idle slots. Largest work first: steady systems (w = 0) take the most
+  // iterations and start first; the others keep their order.
+  std::vector<int64_t> queue;
+  for (int64_t k = 0; k < nsys; ++k)
+    if (omega[k] == 0.0) queue.push_back(k);
+  for (int64_t k = 0; k < nsys; ++k)
+    if (omega[k] != 0.0) queue.push_back(k);
+  size_t qnext = 0;
+  std::vector<int64_t> sys_of(B, -1);  // system held by each slot (-1: free)
+  std::vector<int> iters(B, 0), cycles(B, 0), warm(B, 0);
+  std::vector<double> info(4 * B);
+  Batch b;
+  b.nact = B;
+  b.act = P.act_all;
+  b.omega = P.omega;
+  b.lv = P.lv;
+  b.pen = o->penalty / m->mu;
+  b.wsteady = o->steady_schur_omega;
+  const double2* gp = (const double2*)g;
+  const double2* x0p = (const double2*)x0;
+  // initial residual into V_0 of every listed slot, and its norm
+  auto residual0 = [&](const Batch& bb, const KArgs& ka, dim3 gn) {
+    const int64_t vst = (int64_t)(mk + 1) * P.ld;
+    if (P.v32) {
+      spmv_resid32(m, bb, P.X(), VArg32{reinterpret_cast<float2*>(P.V.p), vst}, P.F(), s, P.T());
+      k_norm<1, float2><<<gn, RBS, 0, s>>>(ka, VArg{}, o->rtol, o->inner_rtol);
     } else {
-      k_init_x<3><<<gi, 256, 0, s>>>(P.T(), nullptr, 0, gp, m->ndir * D, m->dmask, m->dirnodes, m->ndir, m->n2,
-                                     ndof, P.act_all, (int)first);
-      k_init_x<3><<<gi, 256, 0, s>>>(P.X(), x0p, ndof, gp, m->ndir * D, m->dmask, m->dirnodes, m->ndir, m->n2,
-                                     ndof, P.act_all, (int)first);
+      spmv_full(m, bb, P.X(), VArg{P.V.p, vst}, SPMV_RESID, true, P.F(), nullptr, s);
+      k_norm<1, double2><<<gn, RBS, 0, s>>>(ka, VArg{}, o->rtol, mixed ? o->inner_rtol : 0.0);
+    }
+  };
+  // the initial guess (x0, else zero) with the system's Dirichlet data in the listed slots
+  auto init_x = [&](const std::vector<int>& slots, bool use_x0) {
+    for (size_t i = 0; i < slots.size(); ++i) {
+      const int k = slots[i];
+      const int first = (int)(sys_of[k] - k);  // k_init_x reads system first + slot
+      const dim3 g1(256, 1);
+      const int* ak = P.act_all.p + k;
+      if (D == 2)
+        k_init_x<2><<<g1, 256, 0, s>>>(P.X(), use_x0 ? x0p : nullptr, use_x0 ? ndof : 0, gp, m->ndir * D, m->dmask,
+                                       m->dirnodes, m->ndir, m->n2, ndof, ak, first);
+      else
+        k_init_x<3><<<g1, 256, 0, s>>>(P.X(), use_x0 ? x0p : nullptr, use_x0 ? ndof : 0, gp, m->ndir * D, m->dmask,
+                                       m->dirnodes, m->ndir, m->n2, ndof, ak, first);
     }
     launch_check(s);
-    spmv_full(m, b, P.T(), P.F(), SPMV_RHS, false, VArg{}, P.trac, s);
-    k_norm<0><<<g0, RBS, 0, s>>>(a0, P.F(), o->rtol);
+  };
+  // loads the systems of sys_of into the listed slots: solver state, right-hand side and
+  // its norm, preconditioner bounds, initial guess and residual
+  auto load = [&](const std::vector<int>& slots) {
+    const int n = (int)slots.size();
+    for (int k : slots) {
+      const int64_t sy = sys_of[k];
+      SCVS_HIP(hipMemcpyAsync(P.omega.p + k, omega + sy, sizeof(double), hipMemcpyHostToDevice, s));
+      if (ntr)
+        SCVS_HIP(hipMemcpyAsync(P.trac.p + (int64_t)k * ntr, traction + 2 * sy * ntr, sizeof(double2) * ntr,
+                                hipMemcpyHostToDevice, s));
+      iters[k] = cycles[k] = 0;
+      warm[k] = x0 ? 1 : 0;
+    }
+    SCVS_HIP(hipMemcpyAsync(P.act_new.p, slots.data(), sizeof(int) * n, hipMemcpyHostToDevice, s));
+    Batch bs = b;
+    bs.nact = n;
+    bs.act = P.act_new;
+    k_zero_at<<<(n + 63) / 64, 64, 0, s>>>(P.lv, P.act_new, n);
+    k_init_state<<<(n + 63) / 64, 64, 0, s>>>(P.st, P.act_new, n);
+    // right-hand sides: F = RHS(x_g) with T holding the Dirichlet lift
+    for (int k : slots) {
+      const int first = (int)(sys_of[k] - k);
+      const int* ak = P.act_all.p + k;
+      if (D == 2)
+        k_init_x<2><<<dim3(256, 1), 256, 0, s>>>(P.T(), nullptr, 0, gp, m->ndir * D, m->dmask, m->dirnodes, m->ndir,
+                                                 m->n2, ndof, ak, first);
+      else
+        k_init_x<3><<<dim3(256, 1), 256, 0, s>>>(P.T(), nullptr, 0, gp, m->ndir * D, m->dmask, m->dirnodes, m->ndir,
+                                                 m->n2, ndof, ak, first);
+    }
+    init_x(slots, x0 != nullptr);
+    spmv_full(m, bs, P.T(), P.F(), SPMV_RHS, false, VArg{}, P.trac, s);
+    const int nchn = choose_nch(n, ndof);
+    KArgs an = kargs(P, ndof, nchn);
+    an.act = P.act_new;
+    const dim3 gn((unsigned)nchn, (unsigned)n);
+    k_norm<0><<<gn, RBS, 0, s>>>(an, P.F(), o->rtol);
     if (vmg)
-      mg_prepare(m, b, P.mglam.p, B, P.mginv.p, mixed ? P.mginv32.p : nullptr, s);
+      mg_prepare(m, bs, P.mglam.p, B, P.mginv.p, mixed ? P.mginv32.p : nullptr, s);
     else
-      velocity_bounds(m, b, P.lv, s);
-    // initial residual into V_0 of every slot, and its norm
-    auto residual0 = [&](const Batch& bb, const KArgs& ka, dim3 gn) {
-      const int64_t vst = (int64_t)(mk + 1) * P.ld;
-      if (P.v32) {
-        spmv_resid32(m, bb, P.X(), VArg32{reinterpret_cast<float2*>(P.V.p), vst}, P.F(), s, P.T());
-        k_norm<1, float2><<<gn, RBS, 0, s>>>(ka, VArg{}, o->rtol, o->inner_rtol);
-      } else {
-        spmv_full(m, bb, P.X(), VArg{P.V.p, vst}, SPMV_RESID, true, P.F(), nullptr, s);
-        k_norm<1, double2><<<gn, RBS, 0, s>>>(ka, VArg{}, o->rtol, mixed ? o->inner_rtol : 0.0);
-      }
-    };
-    residual0(b, a0, g0);
+      velocity_bounds(m, bs, P.lv, s);
+    residual0(bs, an, gn);
     launch_check(s);
-    std::vector<double> info(4 * nb);
-    std::vector<int> warm(nb, x0 ? 1 : 0);
     if (x0) {
       // keep a supplied initial guess only where its residual is below ||f||
-      download(info.data(), P.info.p, 4 * nb, s);
+      download(info.data(), P.info.p, 4 * B, s);
       std::vector<int> back;
-      for (int k = 0; k < nb; ++k)
+      for (int k : slots)
         if (!(info[4 * k] < 1.0)) {
           back.push_back(k);
           warm[k] = 0;
         }
       if (!back.empty()) {
-        SCVS_HIP(hipMemcpyAsync(P.act.p, back.data(), sizeof(int) * back.size(), hipMemcpyHostToDevice, s));
+        SCVS_HIP(hipMemcpyAsync(P.act_new.p, back.data(), sizeof(int) * back.size(), hipMemcpyHostToDevice, s));
         Batch bb = b;
         bb.nact = (int)back.size();
-        bb.act = P.act;
+        bb.act = P.act_new;
         KArgs ab = kargs(P, ndof, choose_nch(bb.nact, ndof));
-        const dim3 gb(256, (unsigned)bb.nact), gn((unsigned)ab.nch, (unsigned)bb.nact);
-        if (D == 2)
-          k_init_x<2><<<gb, 256, 0, s>>>(P.X(), nullptr, 0, gp, m->ndir * D, m->dmask, m->dirnodes, m->ndir,
-                                         m->n2, ndof, P.act, (int)first);
-        else
-          k_init_x<3><<<gb, 256, 0, s>>>(P.X(), nullptr, 0, gp, m->ndir * D, m->dmask, m->dirnodes, m->ndir,
-                                         m->n2, ndof, P.act, (int)first);
-        residual0(bb, ab, gn);
+        ab.act = P.act_new;
+        init_x(back, false);
+        residual0(bb, ab, dim3((unsigned)ab.nch, (unsigned)bb.nact));
         launch_check(s);
       }
     }
-    std::vector<int> iters(nb, 0), cycles(nb, 0), done(nb, 0);
-    // captured graphs keyed by (kind: 0 steps of all active systems, 1 steps of the
-    // still-running subset, 2 cycle end; systems in the launch; chunk index)
-    std::map<std::tuple<int, int, int>, std::pair<hipGraph_t, hipGraphExec_t>> graphs;
-    const int chunk = std::min(mk, 30);
-    std::vector<int> act_prev;
-    for (;;) {
-      download(info.data(), P.info.p, 4 * nb, s);
-      m->ctx->prof.resolve();
-      std::vector<int> act;
-      for (int k = 0; k < nb; ++k) {
-        if (done[k]) continue;
-        if (cycles[k] > 0) iters[k] += (int)info[4 * k + 1];
-        const double rel = info[4 * k];
-        if (rel <= o->rtol || info[4 * k + 2] != 0.0 || !std::isfinite(rel) || iters[k] >= o->max_iters) {
-          done[k] = 1;
+  };
+  // a finished slot: its solution to the outputs and its report
+  auto finish = [&](int k) {
+    const int64_t sy = sys_of[k];
+    k_copy_out<<<dim3(256, 1), 256, 0, s>>>(P.X(), P.act_all.p + k, (int)sy, 1, m->n2, D, m->nv, (double2*)u_out,
+                                            (double2*)p_out);
+    launch_check(s);
+    if (rep) {
+      scvs_report& r = rep[sy];
+      const double rel = info[4 * k];
+      r.iterations = iters[k];
+      r.restarts = cycles[k];
+      r.rel_residual = rel;
+      r.status = (info[4 * k + 2] != 0.0 || !std::isfinite(rel)) ? 3 : (rel <= o->rtol ? 0 : 1);
+      r.warm = warm[k];
+    }
+    sys_of[k] = -1;
+  };
+  {
+    std::vector<int> fill;
+    for (int k = 0; k < B && qnext < queue.size(); ++k) {
+      sys_of[k] = queue[qnext++];
+      fill.push_back(k);
+    }
+    load(fill);
+  }
+  // captured graphs keyed by (kind: 0 steps of all active systems, 1 steps of the
+  // still-running subset, 2 cycle end; systems in the launch; chunk index)
+  std::map<std::tuple<int, int, int>, std::pair<hipGraph_t, hipGraphExec_t>> graphs;
+  const int chunk = std::min(mk, 30);
+  std::vector<int> act_prev;
+  for (;;) {
+    download(info.data(), P.info.p, 4 * B, s);
+    m->ctx->prof.resolve();
+    std::vector<int> act, freed;
+    for (int k = 0; k < B; ++k) {
+      if (sys_of[k] < 0) continue;
+      const double rel = info[4 * k];
+      if (rel <= o->rtol || info[4 * k + 2] != 0.0 || !std::isfinite(rel) || iters[k] >= o->max_iters) {
+        finish(k);
+        freed.push_back(k);
+        continue;
+      }
+      act.push_back(k);
+    }
+    if (o->verbose) {
+      fprintf(stderr, "[scvs] slots %d active %zu pending %zu:", B, act.size(), queue.size() - qnext);
+      for (int k = 0; k < B && k < 24; ++k) fprintf(stderr, " %.2e", sys_of[k] >= 0 ? info[4 * k] : 0.0);
+      fprintf(stderr, "\n");
+    }
+    if (!freed.empty() && qnext < queue.size()) {
+      std::vector<int> fill;
+      for (int k : freed)
+        if (qnext < queue.size()) {
+          sys_of[k] = queue[qnext++];
+          fill.push_back(k);
+        }
+      load(fill);
+      continue;  // the new systems' initial residuals decide whether they run
+    }
+    if (act.empty()) break;
+    if (act != act_prev) {
+      SCVS_HIP(hipMemcpyAsync(P.act.p, act.data(), sizeof(int) * act.size(), hipMemcpyHostToDevice, s));
+      act_prev = act;
+    }
+    Batch bc = b;
+    bc.nact = (int)act.size();
+    bc.act = P.act;
+    const int na = bc.nact;
+    // the cycle runs in chunks of steps; between chunks the host drops the systems that
+    // stopped, and the cycle ends as soon as none is running
+    const bool use_graph = o->use_graph && !m->ctx->prof.on;
+    auto launch = [&](std::tuple<int, int, int> key, const std::function<void(hipStream_t)>& body) {
+      if (!use_graph) {
+        body(s);
+        return;
+      }
+      auto it = graphs.find(key);
+      if (it == graphs.end()) {
+        hipGraph_t gph;
+        hipGraphExec_t ex;
+        hipStream_t cs = m->ctx->capture;
+        SCVS_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+        try {
+          body(cs);
+        } catch (...) {
+          hipGraph_t bad = nullptr;
+          (void)hipStreamEndCapture(cs, &bad);
+          if (bad) (void)hipGraphDestroy(bad);
+          (void)hipGetLastError();
+          throw;
+        }
+        SCVS_HIP(hipStreamEndCapture(cs, &gph));
+        SCVS_HIP(hipGraphInstantiate(&ex, gph, nullptr, nullptr, 0));
+        it = graphs.emplace(key, std::make_pair(gph, ex)).first;
+      }
+      SCVS_HIP(hipGraphLaunch(it->second.second, s));
+      SCVS_HIP(hipGetLastError());
+    };
+    std::vector<int> run = act;
+    std::vector<int> stops(na), jend(B, mk);
+    for (int j0 = 0; j0 < mk; j0 += chunk) {
+      const int j1 = std::min(mk, j0 + chunk);
+      const bool all_run = run.size() == act.size();
+      Batch br = bc;
+      br.nact = (int)run.size();
+      br.act = all_run ? P.act.p : P.act_run.p;
+      launch(std::make_tuple(all_run ? 0 : 1, br.nact, j0 / chunk),
+             [&](hipStream_t st) { cycle_steps(m, P, br, pa, ndof, j0, j1, lagged, st); });
+      const bool prof_on = m->ctx->prof.on;
+      if (j1 == mk && !prof_on) break;
+      k_stops<<<(br.nact + 63) / 64, 64, 0, s>>>(P.st, br.act, br.nact, P.stops);
+      launch_check(s);
+      download(stops.data(), P.stops.p, br.nact, s);
+      std::vector<int> next;
+      for (int k = 0; k < br.nact; ++k) {
+        const int J = stops[k];
+        if (J < 0) {
+          next.push_back(run[k]);
           continue;
         }
-        act.push_back(k);
-      }
-      if (o->verbose) {
-        fprintf(stderr, "[scvs] batch@%lld active %zu:", (long long)first, act.size());
-        for (int k = 0; k < nb && k < 24; ++k) fprintf(stderr, " %.2e", info[4 * k]);
-        fprintf(stderr, "\n");
-      }
-      if (act.empty()) break;
-      if (act != act_prev) {
-        SCVS_HIP(hipMemcpyAsync(P.act.p, act.data(), sizeof(int) * act.size(), hipMemcpyHostToDevice, s));
-        act_prev = act;
-      }
-      Batch bc = b;
-      bc.nact = (int)act.size();
-      bc.act = P.act;
-      const int na = bc.nact;
-      // the cycle runs in chunks of steps; between chunks the host drops the systems that
-      // stopped, and the cycle ends as soon as none is running
-      const bool use_graph = o->use_graph && !m->ctx->prof.on;
-      auto launch = [&](std::tuple<int, int, int> key, const std::function<void(hipStream_t)>& body) {
-        if (!use_graph) {
-          body(s);
-          return;
-        }
-        auto it = graphs.find(key);
-        if (it == graphs.end()) {
-          hipGraph_t gph;
-          hipGraphExec_t ex;
-          hipStream_t cs = m->ctx->capture;
-          SCVS_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-          try {
-            body(cs);
-          } catch (...) {
-            hipGraph_t bad = nullptr;
-            (void)hipStreamEndCapture(cs, &bad);
-            if (bad) (void)hipGraphDestroy(bad);
-            (void)hipGetLastError();
-            throw;
-          }
-          SCVS_HIP(hipStreamEndCapture(cs, &gph));
-          SCVS_HIP(hipGraphInstantiate(&ex, gph, nullptr, nullptr, 0));
-          it = graphs.emplace(key, std::make_pair(gph, ex)).first;
-        }
-        SCVS_HIP(hipGraphLaunch(it->second.second, s));
-        SCVS_HIP(hipGetLastError());
-      };
-      std::vector<int> run = act;
-      std::vector<int> stops(na), jend(nb, mk);
-      for (int j0 = 0; j0 < mk; j0 += chunk) {
-        const int j1 = std::min(mk, j0 + chunk);
-        const bool all = run.size() == act.size();
-        Batch br = bc;
-        br.nact = (int)run.size();
-        br.act = all ? P.act.p : P.act_run.p;
-        launch(std::make_tuple(all ? 0 : 1, br.nact, j0 / chunk),
-               [&](hipStream_t st) { cycle_steps(m, P, br, pa, ndof, j0, j1, lagged, st); });
-        const bool prof_on = m->ctx->prof.on;
-        if (j1 == mk && !prof_on) break;
-        k_stops<<<(br.nact + 63) / 64, 64, 0, s>>>(P.st, br.act, br.nact, P.stops);
-        launch_check(s);
-        download(stops.data(), P.stops.p, br.nact, s);
-        std::vector<int> next;
-        for (int k = 0; k < br.nact; ++k) {
-          const int J = stops[k];
-          if (J < 0) {
-            next.push_back(run[k]);
-            continue;
-          }
-          jend[run[k]] = J;
-          // Arnoldi launches of steps J.. returned at once (lagged: pass 2 from J, pass 1 from
-          // J + 1, since pass 1 of step J found the stop): take back their bytes
-          for (int jj = std::max(J, j0); jj < j1; ++jj) {
-            const double v = (double)ndof * (P.v32 ? 8.0 : 16.0);
-            if (lagged) {
-              if (jj > J) m->ctx->prof.correct("k_lag_dots", -v * (jj + 2));
-              m->ctx->prof.correct("k_lag_update", -v * (jj + 4));
-            } else {
-              m->ctx->prof.correct("k_dots1", -v * (jj + 2));
-              m->ctx->prof.correct("k_upd_dots", -v * (jj + 3));
-              m->ctx->prof.correct("k_update2", -v * (jj + 3));
-            }
+        jend[run[k]] = J;
+        // Arnoldi launches of steps J.. returned at once (lagged: pass 2 from J, pass 1 from
+        // J + 1, since pass 1 of step J found the stop): take back their bytes
+        for (int jj = std::max(J, j0); jj < j1; ++jj) {
+          const double v = (double)ndof * (P.v32 ? 8.0 : 16.0);
+          if (lagged) {
+            if (jj > J) m->ctx->prof.correct("k_lag_dots", -v * (jj + 2));
+            m->ctx->prof.correct("k_lag_update", -v * (jj + 4));
+          } else {
+            m->ctx->prof.correct("k_dots1", -v * (jj + 2));
+            m->ctx->prof.correct("k_upd_dots", -v * (jj + 3));
+            m->ctx->prof.correct("k_update2", -v * (jj + 3));
           }
         }
-        if (next.empty() || j1 == mk) break;
-        if (next.size() != run.size()) {
-          SCVS_HIP(hipMemcpyAsync(P.act_run.p, next.data(), sizeof(int) * next.size(), hipMemcpyHostToDevice, s));
-          run.swap(next);
-        }
       }
-      for (int k : act) {
-        const double vb = (double)ndof * (P.v32 ? 8.0 : 16.0);
-        m->ctx->prof.correct("k_combine", -vb * (mk - jend[k]));
-        if (lagged && jend[k] < mk) m->ctx->prof.correct("k_lag_dots", -vb * (mk + 1));
+      if (next.empty() || j1 == mk) break;
+      if (next.size() != run.size()) {
+        SCVS_HIP(hipMemcpyAsync(P.act_run.p, next.data(), sizeof(int) * next.size(), hipMemcpyHostToDevice, s));
+        run.swap(next);
       }
-      launch(std::make_tuple(2, na, 0),
-             [&](hipStream_t st) { cycle_end(m, P, bc, pa, ndof, o->rtol, o->inner_rtol, lagged, st); });
-      for (int k : act) cycles[k]++;
     }
-    for (auto& kv : graphs) {
-      (void)hipGraphExecDestroy(kv.second.second);
-      (void)hipGraphDestroy(kv.second.first);
+    for (int k : act) {
+      const double vb = (double)ndof * (P.v32 ? 8.0 : 16.0);
+      m->ctx->prof.correct("k_combine", -vb * (mk - jend[k]));
+      if (lagged && jend[k] < mk) m->ctx->prof.correct("k_lag_dots", -vb * (mk + 1));
     }
-    const dim3 gc(256, (unsigned)nb);
-    k_copy_out<<<gc, 256, 0, s>>>(P.X(), P.act_all, (int)first, nb, m->n2, D, m->nv, (double2*)u_out,
-                                  (double2*)p_out);
-    launch_check(s);
-    SCVS_HIP(hipStreamSynchronize(s));
-    if (rep) {
-      for (int k = 0; k < nb; ++k) {
-        scvs_report& r = rep[first + k];
-        const double rel = info[4 * k];
-        r.iterations = iters[k];
-        r.restarts = cycles[k];
-        r.rel_residual = rel;
-        r.status = (info[4 * k + 2] != 0.0 || !std::isfinite(rel)) ? 3 : (rel <= o->rtol ? 0 : 1);
-        r.warm = warm[k];
-      }
+    launch(std::make_tuple(2, na, 0),
+           [&](hipStream_t st) { cycle_end(m, P, bc, pa, ndof, o->rtol, o->inner_rtol, lagged, st); });
+    // this cycle's iterations (the cycle end wrote them beside the new residuals)
+    download(info.data(), P.info.p, 4 * B, s);
+    for (int k : act) {
+      iters[k] += (int)info[4 * k + 1];
+      cycles[k]++;
     }
   }
+  for (auto& kv : graphs) {
+    (void)hipGraphExecDestroy(kv.second.second);
+    (void)hipGraphDestroy(kv.second.first);
+  }
+  SCVS_HIP(hipStreamSynchronize(s));
   return rc;
 }
 

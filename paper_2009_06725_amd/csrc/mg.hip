@@ -1066,6 +1066,12 @@ __global__ void __launch_bounds__(256) k_mg_step_sell2(LevelArgs<float> la, Sell
   }
 }
 
+// a[act[k]] = 0 for the batch's slots
+__global__ void k_zero_slots(double* a, const int* act, int n) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) a[act[k]] = 0.0;
+}
+
 // k_mg_bound on level 0 in sliced rows: one lane per (row, system), the same sums in
 // the same entry order, FP64 accumulation of the sliced values (FP32 values on the
 // mixed path).
@@ -1705,7 +1711,8 @@ void mg_prepare(scvs_mesh m, const Batch& b, double* lam, int slots, double2* in
   const SellArgs<float> s32 = sell_args<float>(m->s2sell, true);
   const SellArgs<double> s64 = sell_args<double>(m->s2sell, true);
   for (size_t l = 0; l < H.lv.size(); ++l) {
-    SCVS_HIP(hipMemsetAsync(lam + l * slots, 0, sizeof(double) * slots, s));
+    // only the listed slots: other slots of the pool may be running
+    k_zero_slots<<<(b.nact + 63) / 64, 64, 0, s>>>(lam + l * slots, b.act, b.nact);
     unsigned long long* o = reinterpret_cast<unsigned long long*>(lam + l * slots);
     // level 0 from its sliced rows in the cycle's precision when they are there
     if (l == 0 && inv32 && s32.off)
