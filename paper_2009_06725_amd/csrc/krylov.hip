@@ -442,74 +442,63 @@ __global__ void __launch_bounds__(RBS) k_upd_dots(KArgs a, int j) {
 // Pass 2 (k_lag_update) writes q_j = (u - Q s) / sigma over V_j and the next first-pass
 // vector (W - Q a - gamma q_j) / sigma over V_{j+1}, sharing one read of the basis, and
 // its norm rho_j. After the last step one more pass 1 (final) completes the last column.
-constexpr int VS2 = TILE + MM + 2 + 64;
+constexpr int VS2 = (RBS / 64) * 2 * (MM + 1);  // per-wavefront partials, then the final sums
 template <class VT>
 __global__ void __launch_bounds__(RBS) k_lag_dots(KArgs a, int j, int final) {
-  static_assert((RBS / 64) * 2 * (MM + 1) <= VS2, "partials reuse the tile buffer");
-  // the tile holds basis values in their storage type: FP32 pairs fit twice as many
-  constexpr int TL = TILE * (int)(sizeof(double2) / sizeof(VT));
-  static_assert((TL + MM + 2 + 64) * sizeof(VT) <= VS2 * sizeof(double2), "tile fits");
   __shared__ double2 vsd[VS2];
-  VT* vs = reinterpret_cast<VT*>(vsd);
   const int slot = a.act[blockIdx.y];
   SlotState& st = a.st[slot];
   if (st.jstop >= 0) return;
   const int t = threadIdx.x;
-  const int nrow = final ? j + 1 : j + 2;  // V_0..V_j, and W = V_{j+1}
-  int tn = 128;  // the widest tile that fits: longer contiguous runs of every vector
-  while (tn > 4 && nrow * tn > TL) tn >>= 1;
-  const int tp = tn + 1;
+  // each wavefront streams runs of 64 * E consecutive values of u = V_j, W and every
+  // V_i (as pass 2 does); per vector the lane sums of conj(V_i) u and conj(V_i) W are
+  // reduced across the wavefront and added to the wavefront's partials in LDS, which
+  // are summed over the wavefronts in a fixed order
+  constexpr int E = 16;
   int64_t b0, b1;
   chunk_range(a, b0, b1);
   const VT* __restrict__ V0 = vecT<VT>(a, slot, 0);
-  const int di = t & 63, dq = t >> 6, qlen = tn / 4;
-  double2 accS[NDG], accA[NDG];
-#pragma unroll
-  for (int g = 0; g < NDG; ++g) accS[g] = accA[g] = make_double2(0.0, 0.0);
-  constexpr int PF = TL / RBS;
-  const int nld = nrow * tn;
-  VT pre[PF];
-  auto fetch = [&](int64_t nb) {
-    const int len = (int)min((int64_t)tn, b1 - nb);
-#pragma unroll
-    for (int k = 0; k < PF; ++k) {
-      const int q = t + k * RBS, i = q / tn, e = q % tn;
-      pre[k] = (q < nld && e < len) ? V0[(int64_t)i * a.ld + nb + e] : cvt2<VT>(make_double2(0.0, 0.0));
-    }
-  };
-  if (b0 < b1) fetch(b0);
-  for (int64_t nb = b0; nb < b1; nb += tn) {
-    __syncthreads();  // previous tile consumed
-#pragma unroll
-    for (int k = 0; k < PF; ++k) {
-      const int q = t + k * RBS;
-      if (q < nld) vs[(q / tn) * tp + q % tn] = pre[k];
-    }
-    __syncthreads();
-    if (nb + tn < b1) fetch(nb + tn);
-    for (int e = dq * qlen; e < (dq + 1) * qlen; ++e) {
-      const double2 uv = to_d2(vs[j * tp + e]);
-      const double2 wv = final ? make_double2(0.0, 0.0) : to_d2(vs[(j + 1) * tp + e]);
-#pragma unroll
-      for (int g = 0; g < NDG; ++g)
-        if (di + 64 * g <= j) {
-          const double2 v = to_d2(vs[(di + 64 * g) * tp + e]);
-          accS[g].x += v.x * uv.x + v.y * uv.y;
-          accS[g].y += v.x * uv.y - v.y * uv.x;
-          accA[g].x += v.x * wv.x + v.y * wv.y;
-          accA[g].y += v.x * wv.y - v.y * wv.x;
-        }
-    }
-  }
+  const int lane = t & 63, wave = t >> 6;
   double2* red = vsd;  // [RBS/64][2(MM+1)]
   const int R2 = 2 * (MM + 1);
-  __syncthreads();
+  for (int i = lane; i < 2 * (j + 1); i += 64) red[wave * R2 + i] = make_double2(0.0, 0.0);
+  for (int64_t nb = b0 + (int64_t)wave * 64 * E; nb < b1; nb += (int64_t)RBS * E) {
+    double2 uv[E], wv[E];
 #pragma unroll
-  for (int g = 0; g < NDG; ++g)
-    if (di + 64 * g <= j) {
-      red[dq * R2 + 2 * (di + 64 * g)] = accS[g];
-      red[dq * R2 + 2 * (di + 64 * g) + 1] = accA[g];
+    for (int e = 0; e < E; ++e) {
+      const int64_t n = nb + lane + 64 * e;
+      uv[e] = n < b1 ? to_d2(V0[(int64_t)j * a.ld + n]) : make_double2(0.0, 0.0);
+      wv[e] = (n < b1 && !final) ? to_d2(V0[(int64_t)(j + 1) * a.ld + n]) : make_double2(0.0, 0.0);
     }
+    for (int i = 0; i <= j; ++i) {
+      const VT* __restrict__ vi = V0 + (int64_t)i * a.ld;
+      double sx = 0.0, sy = 0.0, ax = 0.0, ay = 0.0;
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const int64_t n = nb + lane + 64 * e;
+        const double2 v = n < b1 ? to_d2(vi[n]) : make_double2(0.0, 0.0);
+        sx += v.x * uv[e].x + v.y * uv[e].y;
+        sy += v.x * uv[e].y - v.y * uv[e].x;
+        ax += v.x * wv[e].x + v.y * wv[e].y;
+        ay += v.x * wv[e].y - v.y * wv[e].x;
+      }
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) {
+        sx += __shfl_xor(sx, o);
+        sy += __shfl_xor(sy, o);
+        ax += __shfl_xor(ax, o);
+        ay += __shfl_xor(ay, o);
+      }
+      if (lane == 0) {
+        double2& rs = red[wave * R2 + 2 * i];
+        double2& ra = red[wave * R2 + 2 * i + 1];
+        rs.x += sx;
+        rs.y += sy;
+        ra.x += ax;
+        ra.y += ay;
+      }
+    }
+  }
   __syncthreads();
   double2* part = a.part + ((int64_t)slot * a.nch + blockIdx.x) * PSTRIDE;
   for (int i = t; i < 2 * (j + 1); i += RBS) {
