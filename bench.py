@@ -84,6 +84,9 @@ def parse(argv=None):
     ap.add_argument("--pres-block", choices=["cheb", "mg"], default="mg",
                     help="pressure-Laplacian inverse in the Schur block: Chebyshev polynomial or multigrid")
     ap.add_argument("--mg-smooth", type=int, default=2, help="multigrid smoothing steps per side")
+    ap.add_argument("--mg-post0", type=int, default=None,
+                    help="multigrid steps after the coarse correction on the velocity's quadratic level; "
+                         "default 1 (tree), 0 = --mg-smooth (pipe, ybatch)")
     ap.add_argument("--mg-ratio", type=float, default=None,
                     help="multigrid smoother interval ratio; default 10 (tree, pipe: every mode converges and "
                          "it is the fastest there), 4 (ybatch: the library default, robust on the Y meshes)")
@@ -120,6 +123,8 @@ def parse(argv=None):
         a.rtol = 4e-12 if a.workload == "pipe" else 2e-12
     if a.mg_ratio is None:
         a.mg_ratio = 4.0 if a.workload == "ybatch" else 10.0
+    if a.mg_post0 is None:
+        a.mg_post0 = 1 if tree else 0
     if a.batch is None:
         a.batch = 2 if tree else 0
     if a.compare_systems is None:
@@ -137,7 +142,7 @@ def solver_opts(args):
                              inner_rtol=args.inner_rtol, penalty=args.penalty,
                              vel_block=1 if args.vel_block == "mg" else 0,
                              pres_block=1 if args.pres_block == "mg" else 0,
-                             mg_smooth=args.mg_smooth, mg_ratio=args.mg_ratio,
+                             mg_smooth=args.mg_smooth, mg_ratio=args.mg_ratio, mg_post0=args.mg_post0,
                              steady_schur_omega=args.steady_schur_omega if args.steady_schur_omega >= 0 else
                              2.0 * np.pi * args.harmonics)
 
@@ -562,7 +567,7 @@ def main():
                    "rtol": args.rtol, "restart": opts.restart,
                    "velocity_block": "multigrid V-cycle" if opts.vel_block else f"Chebyshev degree {opts.cheb_vel}",
                    "pressure_block": "multigrid V-cycle" if opts.pres_block else f"Chebyshev degree {opts.cheb_pres}",
-                   "mg_smooth": opts.mg_smooth, "mg_ratio": opts.mg_ratio,
+                   "mg_smooth": opts.mg_smooth, "mg_post0": opts.mg_post0, "mg_ratio": opts.mg_ratio,
                    "steady_schur_omega": opts.steady_schur_omega,
                    "autotuned": tuned, "orth": args.orth, "inner_rtol": args.inner_rtol,
                    "precision": args.precision, "penalty": args.penalty,

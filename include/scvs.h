@@ -250,12 +250,15 @@ typedef struct {
                          solution is unchanged; pressure modes that the velocity controls only
                          weakly (corners whose velocity nodes are all prescribed) then no
                          longer stall the steady solve. 0 = off */
+  int32_t mg_post0;   /* multigrid: Chebyshev steps after the coarse correction on the
+                         velocity's level 0 (the quadratic level, the costliest to smooth);
+                         0 = mg_smooth; 0..16 */
 } scvs_solve_opts;
 
 /* Fill `o` with the defaults (rtol 1e-10, m 200, 20000 iterations, degrees 12/50,
  * ratios 300 (velocity) / 1000 (pressure), batch 0, graphs on, FP64, lagged
  * orthogonalization, inner_rtol 3e-5, polynomial blocks (vel_block = pres_block = 0),
- * multigrid smoothing 2 steps, ratio 10, steady_schur_omega 0). */
+ * multigrid smoothing 2 steps, ratio 4, steady_schur_omega 0, mg_post0 0). */
 void scvs_solve_opts_default(scvs_solve_opts* o);
 
 typedef struct {

@@ -60,7 +60,7 @@ scvs_solve_opts checked_opts(const scvs_solve_opts* opts) {
                    std::isfinite(o.penalty) && (o.vel_block == 0 || o.vel_block == 1) &&
                    (o.pres_block == 0 || o.pres_block == 1) && o.mg_smooth >= 1 && o.mg_smooth <= 16 &&
                    o.mg_ratio > 1.0 && std::isfinite(o.mg_ratio) && o.steady_schur_omega >= 0.0 &&
-                   std::isfinite(o.steady_schur_omega),
+                   std::isfinite(o.steady_schur_omega) && o.mg_post0 >= 0 && o.mg_post0 <= 16,
                SCVS_E_INVALID, "bad solve options");
   return o;
 }
@@ -68,9 +68,9 @@ scvs_solve_opts checked_opts(const scvs_solve_opts* opts) {
 // Every option the autotuner does not choose (and that changes the solve), as a key.
 std::string untuned_key(const scvs_solve_opts& o) {
   char buf[512];
-  snprintf(buf, sizeof buf, "%.17g|%d|%.17g|%d|%d|%d|%d|%.17g|%.17g|%.17g|%d|%d|%d|%.17g|%.17g", o.rtol, o.max_iters,
-           o.cheb_ratio, o.max_batch, o.use_graph, o.precision, o.orth, o.cheb_ratio_pres, o.penalty, o.inner_rtol,
-           o.vel_block, o.pres_block, o.mg_smooth, o.mg_ratio, o.steady_schur_omega);
+  snprintf(buf, sizeof buf, "%.17g|%d|%.17g|%d|%d|%d|%d|%.17g|%.17g|%.17g|%d|%d|%d|%.17g|%.17g|%d", o.rtol,
+           o.max_iters, o.cheb_ratio, o.max_batch, o.use_graph, o.precision, o.orth, o.cheb_ratio_pres, o.penalty,
+           o.inner_rtol, o.vel_block, o.pres_block, o.mg_smooth, o.mg_ratio, o.steady_schur_omega, o.mg_post0);
   return buf;
 }
 
@@ -376,6 +376,7 @@ void scvs_solve_opts_default(scvs_solve_opts* o) {
   o->mg_smooth = 2;
   o->mg_ratio = 4.0;
   o->steady_schur_omega = 0.0;
+  o->mg_post0 = 0;
 }
 
 int scvs_solve(scvs_mesh m, int64_t nsys, const double* omega, const double* traction, const void* g,

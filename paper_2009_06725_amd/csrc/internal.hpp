@@ -366,6 +366,7 @@ struct PrecondArgs {
   // multigrid blocks (vt/vt32 then hold 5*d*n2 per slot: level 0 of the velocity cycle)
   int vmg = 0, pmg = 0;
   int mg_nu = 2;
+  int mg_post0 = 0;  // post-smoothing steps on the velocity's level 0 (0: mg_nu)
   double mg_ratio = 10.0;
   MgBufs mg;
 };

@@ -1156,6 +1156,7 @@ int solve_systems(scvs_mesh m, int64_t nsys, const double* omega, const double* 
   pa.vmg = vmg ? 1 : 0;
   pa.pmg = pmg ? 1 : 0;
   pa.mg_nu = o->mg_smooth;
+  pa.mg_post0 = o->mg_post0;
   pa.mg_ratio = o->mg_ratio;
   if (vmg || pmg)
     mg_assign(m, B, esz, vmg, pmg, P.mgbuf.p, mixed ? (void*)P.vt32.p : (void*)P.vt.p, (void*)P.pt.p, P.mglam.p,

@@ -1381,10 +1381,12 @@ double level_bytes(int64_t n, int64_t nnz, bool mass, int vb, int64_t pairs, int
          (double)n * pairs * 2.0 * vb * (1 + streams);
 }
 
-// One V-cycle on the levels from `l` down for the pairs of batch b (PD per system).
+// One V-cycle on the levels from `l` down for the pairs of batch b (PD per system):
+// nu smoothing steps before and after each coarse correction (post0 > 0: post0 after
+// it on level l = 0).
 // On entry level l holds its right-hand side in buffer 0 and the first smoothing
 // iterate x_1 in buffer 2 (x_k lives in buffer 1 + k % 3; buffer 4 takes the
-// residual). Returns the buffer that holds the level's result: 1 + (2 nu) % 3, or 2
+// residual). Returns the buffer that holds the level's result: 1 + (nu + post) % 3, or 2
 // on the coarsest level (its dense inverse applied to buffer 0). With `out` the last
 // post-smoothing step of level l writes there instead (same [n][G] layout).
 struct CoarseInv {
@@ -1412,7 +1414,7 @@ SellArgs<R> sell_args(const Sell& S, bool mass) {
 template <class R, int PD, bool MASS>
 int mg_cycle(const MgHier& H, const std::vector<LevelArgs<R>>& las, const SellArgs<R>& sell0,
              const std::vector<void*>& bufs, const std::vector<const double*>& lams, int l, const Batch& b, int nu,
-             double ratio, CoarseInv coarse, typename CplxOf<R>::C* out, Profiler* prof, hipStream_t s) {
+             int post0, double ratio, CoarseInv coarse, typename CplxOf<R>::C* out, Profiler* prof, hipStream_t s) {
   using C = typename CplxOf<R>::C;
   const LaneMap lm = lane_map(b.nact, PD);
   const int nlev = (int)las.size();
@@ -1523,21 +1525,24 @@ int mg_cycle(const MgHier& H, const std::vector<LevelArgs<R>>& las, const SellAr
                                                                      ratio, arr(4), cb, cb + 2 * ncG);
   }
   launch_check(s);
-  const int kres = mg_cycle<R, PD, MASS>(H, las, sell0, bufs, lams, l + 1, b, nu, ratio, coarse, nullptr, prof, s);
+  const int kres =
+      mg_cycle<R, PD, MASS>(H, las, sell0, bufs, lams, l + 1, b, nu, 0, ratio, coarse, nullptr, prof, s);
   {
     const double tb = (double)H.lv[l].pval.n * (4.0 + vb) + (double)la.n * 8.0 + (double)la.n * lm.G * 4.0 * vb +
                       (double)lc.n * lm.G * 2.0 * vb;
     ProfScope ps(prof, s, n_prol, tb);
     k_mg_prolong<R><<<nb, 256, 0, s>>>(p_args<R>(H.lv[l]), lm, cb + (int64_t)kres * ncG, iter(nu));
   }
+  // post-smoothing: post0 steps on level 0 when given, else nu
+  const int npost = (l == 0 && post0 > 0) ? post0 : nu;
   {
-    ProfScope ps(prof, s, n_smooth, level_bytes(la.n, nnz, MASS, vb, lm.G, 2) * nu, nu);
-    for (int j = 1; j <= nu; ++j)
+    ProfScope ps(prof, s, n_smooth, level_bytes(la.n, nnz, MASS, vb, lm.G, 2) * npost, npost);
+    for (int j = 1; j <= npost; ++j)
       step(MG_STEP, cheb_step(ratio, j - 1), j == 1 ? 1 : 0, iter(nu + j - 1), j == 1 ? nullptr : iter(nu + j - 2),
-           (j == nu && out) ? out : iter(nu + j));
+           (j == npost && out) ? out : iter(nu + j));
   }
   launch_check(s);
-  return 1 + (2 * nu) % 3;
+  return 1 + (nu + npost) % 3;
 }
 
 // z[slot][i*D + c] = buf[i*G + p] (p = si*D + c): the interleaved result in the
@@ -1617,7 +1622,7 @@ void vel_cycle(scvs_mesh m, const Batch& b, const PrecondArgs& pa, void* zil, SV
   Profiler* prof = &m->ctx->prof;
   const int64_t nc = H.lv.back().n;
   const CoarseInv ci{pa.mg.vinv, nc * nc};
-  const int k = mg_cycle<R, D, true>(H, las, s0, bufs, lams, 0, b, pa.mg_nu, pa.mg_ratio, ci,
+  const int k = mg_cycle<R, D, true>(H, las, s0, bufs, lams, 0, b, pa.mg_nu, pa.mg_post0, pa.mg_ratio, ci,
                                      reinterpret_cast<C*>(zil), prof, s);
   if (!zil) {
     const int64_t G = (int64_t)b.nact * D;
@@ -1639,7 +1644,7 @@ void pres_cycle(scvs_mesh m, const Batch& b, const PrecondArgs& pa, SV<VI> v, VA
   for (size_t l = 0; l < H.lv.size(); ++l) bufs[l] = pa.mg.p[l];
   Profiler* prof = &m->ctx->prof;
   const CoarseInv ci{sizeof(R) == 4 ? (const void*)H.cinv32.p : (const void*)H.cinv.p, 0};
-  const int k = mg_cycle<R, 1, false>(H, las, s0, bufs, lams, 0, b, pa.mg_nu, pa.mg_ratio, ci, nullptr, prof, s);
+  const int k = mg_cycle<R, 1, false>(H, las, s0, bufs, lams, 0, b, pa.mg_nu, 0, pa.mg_ratio, ci, nullptr, prof, s);
   const C* res = reinterpret_cast<C*>(pa.mg.p[0]) + (int64_t)k * m->nv * b.nact;
   ProfScope ps(prof, s, "k_p_combine", (double)m->nv * (8.0 + b.nact * (sizeof(C) + sizeof(VI) + 16.0)));
   k_p_combine<C, VI><<<1024, 256, 0, s>>>(res, m->nv, (int64_t)m->dim * m->n2, b, m->Mp, m->mu, m->rho, v, z);

@@ -52,7 +52,8 @@ class SolveOpts(C.Structure):
                 ("max_batch", C.c_int32), ("use_graph", C.c_int32), ("verbose", C.c_int32),
                 ("precision", C.c_int32), ("orth", C.c_int32), ("cheb_ratio_pres", C.c_double), ("penalty", C.c_double),
                 ("inner_rtol", C.c_double), ("vel_block", C.c_int32), ("pres_block", C.c_int32),
-                ("mg_smooth", C.c_int32), ("mg_ratio", C.c_double), ("steady_schur_omega", C.c_double)]
+                ("mg_smooth", C.c_int32), ("mg_ratio", C.c_double), ("steady_schur_omega", C.c_double),
+                ("mg_post0", C.c_int32)]
 
 
 class SolveGroup(C.Structure):

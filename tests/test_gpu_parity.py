@@ -265,6 +265,25 @@ def test_solve_multigrid_matches_lu(setup, precision):
         assert eu <= tol and ep <= tol, (s, eu, ep)
 
 
+def test_solve_multigrid_one_post_step_on_level0(setup):
+    """The bench's tree cycle: one smoothing step after the coarse correction on the
+    velocity's quadratic level (mg_post0 = 1), mixed precision: modes within 1e-8 of LU."""
+    from paper_2009_06725_amd import scvs
+    c, asm, m = setup["case"], setup["asm"], setup["m"]
+    u_o, p_o = _lu(setup)
+    g = gpu_dirichlet(m, c, torch)
+    wmax = float(np.abs(c["omega"]).max())
+    opts = scvs.default_opts(rtol=1e-12, precision=1, vel_block=1, pres_block=1, restart=40,
+                             steady_schur_omega=wmax, mg_post0=1)
+    u, p, rep = m.solve(c["omega"], c["traction"], g, opts=opts)
+    u, p = u.cpu().numpy(), p.cpu().numpy()
+    print("[gpu]", setup["name"], "multigrid post0=1 iterations", [r.iterations for r in rep], flush=True)
+    for s in range(len(c["omega"])):
+        assert rep[s].status == 0, (s, rep[s].status, rep[s].rel_residual)
+        eu, ep = rel_l2(asm, u[s], u_o[s], p[s], p_o[s])
+        assert eu <= 1e-8 and ep <= 1e-8, (s, eu, ep)
+
+
 def test_orthogonalization_variants_agree(setup):
     """Lagged (DCGS2) and classical two-pass Gram-Schmidt give the same modes."""
     from paper_2009_06725_amd import scvs
