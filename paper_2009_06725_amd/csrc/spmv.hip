@@ -412,6 +412,142 @@ __global__ void __launch_bounds__(256) k_full_sell(MeshArgs ma, S2SellArgs sa, B
   }
 }
 
+// Value of lane U of each group of four lanes (DPP quad broadcast).
+template <int U>
+__device__ __forceinline__ int qbc(int v) {
+  return __builtin_amdgcn_mov_dpp(v, U * 0x55, 0xF, 0xF, false);
+}
+template <int U>
+__device__ __forceinline__ float qbc(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), U * 0x55, 0xF, 0xF, false));
+}
+
+// k_full_sell for rows of 6 or 8 (system, component) pairs: four lanes per row, each
+// with two pairs gathered by one 16-byte load; the four lanes load four entries'
+// (column, Ks, M) at once and share them by quad broadcasts. A vertex row's divergence
+// sums are per pair and are summed per system over the four lanes. Same products as
+// k_full_sell; outputs per pair and, on vertex rows, per system.
+template <int D, class YT>
+__global__ void __launch_bounds__(256) k_full_sell4(MeshArgs ma, S2SellArgs sa, Batch b,
+                                                    const float2* __restrict__ xil, SV<YT> y) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t q = (row_block() * 4 + wave) * 16 + lane / 4;
+  if (q >= sa.nslot) return;
+  const int32_t A = sa.row[q];
+  if (A < 0) return;  // uniform over the four lanes of the row
+  const int64_t sl = q / SELL_C, r = q % SELL_C;
+  const int64_t e0 = sa.off[sl] + r, g0 = sa.goff[sl] + r;
+  const int len = (int)((sa.off[sl + 1] - sa.off[sl]) / SELL_C);
+  const int glen = (int)((sa.goff[sl + 1] - sa.goff[sl]) / SELL_C);
+  const bool isv = q < sa.vslots;  // uniform over a slice
+  const int32_t dm = ma.dmask[A];
+  const int nvr = ma.nvc[A];
+  const int G = b.nact * D, li = lane & 3, p0 = 2 * li;
+  const bool act = p0 < G;
+  const int s0 = act ? p0 / D : 0, s1 = act ? (p0 + 1) / D : 0;
+  const int d0 = p0 % D, d1 = (p0 + 1) % D;
+  const int slot0 = b.act[s0], slot1 = b.act[s1];
+  const float mu = (float)ma.mu;
+  const float w0 = (float)(b.omega[slot0] * ma.rho), w1 = (float)(b.omega[slot1] * ma.rho);
+  const float2* __restrict__ pil = xil + ma.n2 * G;  // pressures: [nv][nact]
+  float2 a0 = make_float2(0.f, 0.f), a1 = make_float2(0.f, 0.f);
+  float2 q0 = make_float2(0.f, 0.f), q1 = make_float2(0.f, 0.f);  // divergence parts per pair
+  if (dm == 0 || isv) {
+    for (int t = 0; t < len; t += 4) {
+      const bool vl = t + li < len;
+      const int64_t el = e0 + (int64_t)(t + li) * SELL_C;
+      const int32_t cl = vl ? sa.col[el] : -1;
+      const float kl = vl ? sa.K[el] : 0.f, ml = vl ? sa.M[el] : 0.f;
+      int32_t c[4];
+      float k[4], m[4];
+      c[0] = qbc<0>(cl); c[1] = qbc<1>(cl); c[2] = qbc<2>(cl); c[3] = qbc<3>(cl);
+      k[0] = qbc<0>(kl); k[1] = qbc<1>(kl); k[2] = qbc<2>(kl); k[3] = qbc<3>(kl);
+      m[0] = qbc<0>(ml); m[1] = qbc<1>(ml); m[2] = qbc<2>(ml); m[3] = qbc<3>(ml);
+      float4 xv[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        xv[u] = (act && c[u] >= 0) ? *reinterpret_cast<const float4*>(xil + (int64_t)c[u] * G + p0)
+                                   : make_float4(0.f, 0.f, 0.f, 0.f);
+      if (dm == 0 && act) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const float kr = mu * k[u], ki0 = w0 * m[u], ki1 = w1 * m[u];
+          a0.x += kr * xv[u].x - ki0 * xv[u].y;
+          a0.y += kr * xv[u].y + ki0 * xv[u].x;
+          a1.x += kr * xv[u].z - ki1 * xv[u].w;
+          a1.y += kr * xv[u].w + ki1 * xv[u].z;
+        }
+        if (t < glen) {  // G p over the vertex-column prefix
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            if (t + u < nvr) {
+              const int64_t ge = (g0 + (int64_t)(t + u) * SELL_C) * D;
+              const float2 pv0 = pil[(int64_t)c[u] * b.nact + s0];
+              const float2 pv1 = pil[(int64_t)c[u] * b.nact + s1];
+              const float g0v = sa.G[ge + d0], g1v = sa.G[ge + d1];
+              a0.x += g0v * pv0.x;
+              a0.y += g0v * pv0.y;
+              a1.x += g1v * pv1.x;
+              a1.y += g1v * pv1.y;
+            }
+          }
+        }
+      }
+      if (isv && act) {  // divergence row: G^T^d x_(s, d) per pair
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          if (c[u] >= 0) {
+            const int64_t e = (e0 + (int64_t)(t + u) * SELL_C) * D;
+            const float g0v = sa.Gt[e + d0], g1v = sa.Gt[e + d1];
+            q0.x += g0v * xv[u].x;
+            q0.y += g0v * xv[u].y;
+            q1.x += g1v * xv[u].z;
+            q1.y += g1v * xv[u].w;
+          }
+        }
+      }
+    }
+  }
+  if (act) {
+    const int64_t o = (int64_t)A * G + p0;
+    double2 y0, y1;
+    const double sc0 = in_scale(b, slot0), sc1 = in_scale(b, slot1);
+    if (dm != 0) {
+      const float4 xa = *reinterpret_cast<const float4*>(xil + o);
+      y0 = make_double2(sc0 * (double)xa.x, sc0 * (double)xa.y);
+      y1 = make_double2(sc1 * (double)xa.z, sc1 * (double)xa.w);
+    } else {
+      y0 = make_double2(sc0 * (double)a0.x, sc0 * (double)a0.y);
+      y1 = make_double2(sc1 * (double)a1.x, sc1 * (double)a1.y);
+    }
+    y.at(slot0)[(int64_t)A * D + d0] = cvt2<YT>(y0);
+    y.at(slot1)[(int64_t)A * D + d1] = cvt2<YT>(y1);
+  }
+  if (isv) {
+    // per system s: the sum over its D pairs, in pair order, gathered from the quad
+    for (int si = 0; si < b.nact; ++si) {
+      float2 part = make_float2(0.f, 0.f);
+      if (act && s0 == si) { part.x += q0.x; part.y += q0.y; }
+      if (act && s1 == si) { part.x += q1.x; part.y += q1.y; }
+      float px[4], py[4];
+      px[0] = qbc<0>(part.x); px[1] = qbc<1>(part.x); px[2] = qbc<2>(part.x); px[3] = qbc<3>(part.x);
+      py[0] = qbc<0>(part.y); py[1] = qbc<1>(part.y); py[2] = qbc<2>(part.y); py[3] = qbc<3>(part.y);
+      if (li != si) continue;
+      const float2 ap = make_float2(((px[0] + px[1]) + px[2]) + px[3], ((py[0] + py[1]) + py[2]) + py[3]);
+      const int slot = b.act[si];
+      const double sc = in_scale(b, slot);
+      double2 yp = make_double2(sc * (double)ap.x, sc * (double)ap.y);
+      if (b.pen != 0.0) {  // penalized continuity block -pen Mp p
+        const float2 xp = pil[(int64_t)A * b.nact + si];
+        const double w = b.pen * ma.Mp[A] * sc;
+        yp.x -= w * (double)xp.x;
+        yp.y -= w * (double)xp.y;
+      }
+      y.at(slot)[(int64_t)D * ma.n2 + A] = cvt2<YT>(yp);
+    }
+  }
+}
+
 // Lumped outlets: after the operator kernel, y += s * sc * Z_o(w) (b_o^T x) b_o on the
 // free momentum rows of every outlet o, s = +1 for y = A x and -1 for y = f - A x and
 // for the right-hand side (where x is the Dirichlet lift and b_o^T x runs over the
@@ -867,6 +1003,12 @@ void full_launch_il(Profiler* prof, const MeshArgs& ma, const S2SellArgs* sa, co
   ProfScope ps(prof, s, sizeof(R) == 4 ? "k_full_apply32" : "k_full_apply",
                mat + b.nact * ndof * (2.0 * vb + (double)sizeof(YT)));
   if constexpr (sizeof(R) == 4) {
+    if (sa && (b.nact * D) % 2 == 0 && b.nact * D > 4 && b.nact * D <= 8) {  // four lanes, two pairs each
+      const unsigned nbs = (unsigned)((sa->nslot + 63) / 64);
+      k_full_sell4<D, YT><<<nbs, 256, 0, s>>>(ma, *sa, b, xil, y);
+      launch_check(s);
+      return;
+    }
     if (sa) {  // sliced rows: W lanes per row (a power of two >= the systems, <= 64)
       int W = 1;
       while (W < b.nact && W < 64) W <<= 1;
