@@ -10,6 +10,12 @@ Workloads (N=1):
   and high modes, and the steps run through the waves in turn.
 * pipe: straight pipe R=1, L=10 with ~200k curved quadratic tets (~0.88M
   complex unknowns per mode), 16 harmonics plus the mean; one step = all 17.
+* ybatch: 4 Y-bifurcations of about 0.3/0.6/1.2/2.4M tets, 12 cases of 32
+  harmonics plus the mean on each, every case with its own period: 1,584
+  systems in one step (`run_ybatch`).
+* ylearn: the learned warm start on the 1.2M-tet Y, one POD basis and network
+  per harmonic, zero-guess against warm-started solves of held-out waveforms
+  (`run_ylearn`).
 
 Per-mesh setup (ingest, assembly of the mode-independent matrices, the
 preconditioner's multigrid hierarchies) runs once and is reported separately.
@@ -48,10 +54,11 @@ def parse(argv=None):
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=["tree", "pipe", "ybatch"], default="tree",
+    ap.add_argument("--workload", choices=["tree", "pipe", "ybatch", "ylearn"], default="tree",
                     help="tree: the default; pipe: the 200k-tet pipe; ybatch: the batching workload "
                          "(4 Y-bifurcations of 0.3/0.6/1.2/2.4M tets, 12 cases of 32 harmonics each; "
-                         "one step solves all 1,584 systems)")
+                         "one step solves all 1,584 systems); ylearn: the learned warm start on the "
+                         "1.2M-tet Y (per-harmonic POD and MLP, held-out waveforms)")
     ap.add_argument("--ymesh", type=int, choices=[0, 1, 2, 3], default=None,
                     help="ybatch: run only the k-th mesh (0.3/0.6/1.2/2.4M tets)")
     ap.add_argument("--tets", type=int, default=None, help="default: 12,000,000 (tree), 200,000 (pipe)")
@@ -106,6 +113,10 @@ def parse(argv=None):
                     help="skip the learned-warm-start leg (pipe workload; reported beside the headline)")
     ap.add_argument("--ws-periods", type=int, default=4,
                     help="training periods for the warm start (each gives one solve per harmonic)")
+    ap.add_argument("--ws-snapshots", type=int, default=16,
+                    help="ylearn: training periods per harmonic solved for its POD (its rank)")
+    ap.add_argument("--ws-heldout", type=int, default=4,
+                    help="ylearn: held-out waveforms timed (all harmonics of each)")
     ap.add_argument("--no-error-check", action="store_true",
                     help="skip the tight-tolerance FP64 reference solve that estimates the error")
     ap.add_argument("--verbose", action="store_true")
@@ -113,20 +124,21 @@ def parse(argv=None):
                     help="only run plain 1 GiB device copies (for scaling rocprofv3 byte counters)")
     a = ap.parse_args(argv)
     tree = a.workload == "tree"
+    ylearn = a.workload == "ylearn"
     if a.tets is None:
-        a.tets = 12_000_000 if tree else 200_000
+        a.tets = 12_000_000 if tree else 1_200_000 if ylearn else 200_000
     if a.harmonics is None:
-        a.harmonics = 64 if tree else 16
+        a.harmonics = 64 if tree else 32 if ylearn else 16
     if a.ntimes is None:
         a.ntimes = 16 if tree else 64
     if a.rtol is None:
         a.rtol = 4e-12 if a.workload == "pipe" else 2e-12
     if a.mg_ratio is None:
-        a.mg_ratio = 4.0 if a.workload == "ybatch" else 10.0
+        a.mg_ratio = 4.0 if a.workload in ("ybatch", "ylearn") else 10.0
     if a.mg_post0 is None:
         a.mg_post0 = 1 if tree else 0
     if a.batch is None:
-        a.batch = 2 if tree else 0
+        a.batch = 2 if tree else 16 if ylearn else 0
     if a.compare_systems is None:
         a.compare_systems = 2 if tree else 0
     return a
@@ -384,6 +396,146 @@ def run_ybatch(args):
                       "converged": conv, "per_mesh": per}), flush=True)
 
 
+def run_ylearn(args):
+    """The learned-warm-start workload on the Y-bifurcation of about 1.2M tets:
+    2,000 training and 200 held-out waveforms of 32 harmonics (amplitudes
+    N(0,1)/k^2, phases U[0, 2pi)), each with its own period T ~ U[0.8, 1.2].
+    Mode k of a waveform is its coefficient times the unit-amplitude response at
+    w = 2 pi k / T, so what a model learns is that response as a function of w.
+    Setup (untimed, reported): for each harmonic, unit responses at
+    `--ws-snapshots` of the training periods (the shortest, the longest and evenly
+    spaced order statistics between), their POD (one basis per harmonic) and the
+    harmonic's MLP (4 layers of width 256) trained on the GPU. Timed, on the first
+    `--ws-heldout` held-out waveforms (all 32 harmonics each): the zero-guess solve,
+    the network's guess and solve, and the guess with its subspace correction and
+    solve, all to the same tolerance. The steady mode is left out: its unit
+    response does not depend on the period, so its guess would be exact. Prints one
+    JSON line."""
+    import torch
+    from paper_2009_06725_amd import scvs
+    from workloads.meshes import y_bifurcation_mesh_for_tets
+    from workloads.waveforms import harmonic_coefficients, period_set
+    n_harm, n_train, n_held = args.harmonics, 2000, 200
+    t0 = time.perf_counter()
+    c = cases.vessel_case(y_bifurcation_mesh_for_tets(args.tets), n_harm, 5, 1.0)
+    ctx = scvs.Context(0)
+    m = scvs.Mesh.from_workload(ctx, c["mesh"])
+    m.set_bc(c["bc"])
+    m.assemble(c["rho"], c["mu"])
+    info = m.info
+    nodes = m.export(scvs.X_DIRNODES)
+    xyz = m.export(scvs.X_NODEXYZ)[nodes]
+    opts = solver_opts(args)
+    opts.steady_schur_omega = 2.0 * np.pi * n_harm / 0.8
+    opts.max_batch = args.batch  # the same slot count for the three timed solves
+    m.mg_info(0)
+    t_setup = time.perf_counter() - t0
+    log(f"ylearn mesh {c['mesh'].name}: {c['mesh'].nc} tets, {info.ndof} unknowns ({t_setup:.1f}s)")
+    t_train = np.sort(period_set(n_train, seed=61))
+    _ = harmonic_coefficients(n_harm, 62, n_waves=n_train)  # training coefficients: scale only, by linearity
+    S = args.ws_snapshots
+    ts = t_train[np.round(np.linspace(0, n_train - 1, S)).astype(int)]
+    ks = np.repeat(np.arange(1, n_harm + 1), S)
+    om_s = 2.0 * np.pi * ks / np.tile(ts, n_harm)
+
+    def dirichlet(om, amp):
+        return torch.from_numpy(np.stack([a * c["inlet"](xyz, float(w)) for w, a in zip(om, amp)])).to("cuda")
+
+    snap_opts = solver_opts(args)
+    snap_opts.steady_schur_omega = opts.steady_schur_omega
+    snap_opts.rtol = 1e-10
+    mws = scvs.ModeWarmStarts(m, rank=S, width=256, layers=4, seed=7)
+    t0 = time.perf_counter()
+    t_pod, snap_conv, per_call = 0.0, True, 4  # harmonics per snapshot solve call
+    for k0 in range(1, n_harm + 1, per_call):
+        kk = np.arange(k0, min(n_harm, k0 + per_call - 1) + 1)
+        sel = np.isin(ks, kk)
+        us, ps, reps = m.solve(om_s[sel], np.zeros((int(sel.sum()), 0), np.complex128),
+                               dirichlet(om_s[sel], np.ones(int(sel.sum()))), opts=snap_opts)
+        snap_conv = snap_conv and all(x.status == 0 for x in reps)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for j, k in enumerate(kk):
+            r = slice(j * S, (j + 1) * S)
+            mws.add(int(k), om_s[ks == k], torch.cat([us[r].reshape(S, -1), ps[r]], dim=1).contiguous())
+        del us, ps
+        torch.cuda.empty_cache()
+        torch.cuda.synchronize()
+        t_pod += time.perf_counter() - t1
+        log(f"ylearn: snapshots and POD of harmonics {kk[0]}..{kk[-1]} done at {time.perf_counter() - t0:.1f}s, "
+            f"iterations {sum(x.iterations for x in reps)}")
+    t_snap = time.perf_counter() - t0 - t_pod
+    t0 = time.perf_counter()
+    losses = mws.train([(4000, 3e-3), (4000, 1e-3), (4000, 3e-4), (4000, 1e-4)])
+    torch.cuda.synchronize()
+    t_fit = time.perf_counter() - t0
+    sig = mws.sigma()
+    log(f"ylearn: POD {t_pod:.1f}s, training {t_fit:.1f}s")
+    # held-out systems, ordered by harmonic (k outer, waveform inner)
+    H = args.ws_heldout
+    th = period_set(n_held, seed=63)
+    coef = harmonic_coefficients(n_harm, 64, n_waves=n_held)
+    hk = np.repeat(np.arange(1, n_harm + 1), H)
+    hw = np.tile(np.arange(H), n_harm)
+    om = 2.0 * np.pi * hk / th[hw]
+    amp = coef[hw, hk]
+    tr = np.zeros((om.size, 0), np.complex128)
+    g = dirichlet(om, amp)
+    # the corrections' A(0) Phi and its slope are formed on a model's first call (setup)
+    first = np.arange(0, om.size, H)
+    mws.refine(hk[first], om[first], tr[first], g[first].contiguous(), mws.predict(hk[first], om[first], amp[first]))
+    torch.cuda.synchronize()
+    ns = om.size
+
+    def timed(kind):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        x0 = None
+        if kind != "zero":
+            x0 = mws.predict(hk, om, amp)
+            if kind == "corrected":
+                mws.refine(hk, om, tr, g, x0)
+        u_, p_, rep = m.solve(om, tr, g, x0=x0, opts=opts)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        its = np.array([x.iterations for x in rep])
+        log(f"ylearn {kind}: {dt:.1f}s, iterations {its.sum()}")
+        return u_, p_, {"mode_solves_per_s": ns / dt, "seconds": round(dt, 2), "iterations_sum": int(its.sum()),
+                        "iterations_per_harmonic": [float(its[hk == k].mean()) for k in range(1, n_harm + 1)],
+                        "warm": int(sum(x.warm for x in rep)), "converged": all(x.status == 0 for x in rep)}
+
+    u0, p0, r0 = timed("zero")
+    u1, p1, r1 = timed("network")
+    del u1, p1
+    u2, p2, r2 = timed("corrected")
+    eu, ep = rel_mass_l2(m, u2 - u0, p2 - p0, u0, p0)
+    r2["rel_diff_vs_zero_guess"] = {"max_u": float(eu.max()), "max_p": float(ep.max())}
+    mws.close()
+    print(json.dumps({
+        "metric": "mode-solves/s", "value": r2["mode_solves_per_s"], "unit": "mode-solves/s", "n_gpus": 1,
+        "steps": 1, "warmup": 0, "ms_per_step": r2["seconds"] * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "c64 operator and preconditioner / c128 Krylov basis, Schur scaling, "
+        "refinement; MLP bf16 products, fp32 accumulate", "data": "synthetic",
+        "config": {"workload": f"learned warm start on a Y-bifurcation of {c['mesh'].nc} tets: {n_train} training and "
+                   f"{n_held} held-out waveforms of {n_harm} harmonics, own period each; timed on {H} held-out "
+                   f"waveforms ({ns} systems)", "ndof": int(info.ndof), "rtol": opts.rtol,
+                   "snapshot_periods": [round(float(x), 4) for x in ts], "pod_rank_per_harmonic": S,
+                   "mlp": {"layers": 4, "width": 256, "epochs": 16000},
+                   "heldout_periods": [round(float(x), 4) for x in th[:H]]},
+        "zero_guess": r0, "network_only": r1, "network_and_subspace_correction": r2,
+        "network_iterations_vs_zero_guess": r1["iterations_sum"] / max(1, r0["iterations_sum"]),
+        "setup_seconds": {"mesh_assembly_hierarchies": round(t_setup, 1), "snapshot_solves": round(t_snap, 1),
+                          "pod": round(t_pod, 1), "training": round(t_fit, 1)},
+        "snapshots_converged": snap_conv,
+        "training_loss": {"initial_max": max(a for a, _ in losses.values()),
+                          "final_max": max(b for _, b in losses.values())},
+        # singular values below about 1e-8 sigma_0 are under the Gram matrix's rounding floor
+        # (reported as 0): a harmonic whose count stays below the rank is resolved by its snapshots
+        "pod_values_above_1e-7_sigma0": {int(k): int((s > 1e-7 * s[0]).sum()) for k, s in sig.items()},
+        "pod_sigma_over_sigma0": {int(k): [float(f"{x / sig[k][0]:.3g}") for x in sig[k]] for k in (1, n_harm // 2, n_harm)},
+    }), flush=True)
+
+
 def rel_mass_l2(m, du, dp, ur, pr):
     """Relative L2(Omega) errors per mode (mass-weighted: u^H (I x M) u, p^H Mp p)."""
     dun, dpn = m.mode_norms(du, dp)
@@ -402,6 +554,9 @@ def main():
         return
     if args.workload == "ybatch":
         run_ybatch(args)
+        return
+    if args.workload == "ylearn":
+        run_ylearn(args)
         return
     tree = args.workload == "tree"
     t_start = time.perf_counter()

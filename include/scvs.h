@@ -388,16 +388,20 @@ int scvs_synthesize(scvs_ctx ctx, int64_t nk, const double* omega, const void* m
  * modes, and an MLP with `layers` layers of width `width` (tanh hidden
  * layers) from the features (w, sqrt w, w^2) of w = omega/max|omega| to the
  * rank complex POD coefficients. With the Gram eigenpairs (sigma_i^2, W_i)
- * of the snapshots, snapshot s equals sum_i sigma_i conj(W_si) phi_i; the
- * network's targets are t_si = sigma_i conj(W_si) / sigma_0 (real parts, then
- * imaginary parts), so the squared error weighs each coefficient by its
- * share of the solution. Matrix products of the MLP run on BF16 matrix cores
+ * of the snapshots, snapshot s equals sum_i sigma_i conj(W_si) phi_i, so its
+ * coefficients relative to sigma_0 are t_si = sigma_i conj(W_si) / sigma_0
+ * (real parts, then imaginary parts). Each of these 2*rank outputs is
+ * standardized over the snapshots: the network's targets are
+ * (t_so - tmean_o) / tscale_o, with tmean_o the mean and tscale_o the RMS
+ * deviation (1 for an output that does not vary), so every coefficient is
+ * fitted to the same relative accuracy. Matrix products of the MLP run on BF16 matrix cores
  * with FP32 accumulation and FP32 master weights. The model keeps its own
  * copy of the basis.
  *   scvs_ws_train    epochs of full-batch Adam (lr; beta 0.9/0.999, eps 1e-8);
  *                    *loss = mean-squared error before the last epoch's update
  *                    (epochs == 0: the current loss, no update)
- *   scvs_ws_predict  x0[s] = amp[s] sigma_0 sum_i t_i(omega[s]) phi_i   (device c128 [n][ndof])
+ *   scvs_ws_predict  x0[s] = amp[s] sigma_0 sum_i t_i(omega[s]) phi_i   (device c128 [n][ndof]),
+ *                    t_o = tmean_o + tscale_o * (network output o)
  * Pass the predictions as x0 to scvs_solve; it falls back to the zero guess
  * for any system whose initial residual is not below ||f||.
  *   scvs_ws_refine   optional correction of guesses x0 (device c128 [n][ndof],
@@ -421,12 +425,15 @@ int scvs_ws_destroy(scvs_ws ws);
 /* Test/inspection hooks (host buffers unless stated):
  *  SCVS_WS_SIGMA double[rank]; SCVS_WS_BASIS device c128[rank][ndof];
  *  SCVS_WS_PARAMS float[nparam] (per layer W [out][in] row-major, then b);
- *  SCVS_WS_TARGETS float[nsnap][2*rank]; SCVS_WS_NPARAM int64 */
+ *  SCVS_WS_TARGETS float[nsnap][2*rank] (standardized); SCVS_WS_NPARAM int64;
+ *  SCVS_WS_TMEAN, SCVS_WS_TSCALE double[2*rank] */
 #define SCVS_WS_SIGMA 0
 #define SCVS_WS_BASIS 1
 #define SCVS_WS_PARAMS 2
 #define SCVS_WS_TARGETS 3
 #define SCVS_WS_NPARAM 4
+#define SCVS_WS_TMEAN 5
+#define SCVS_WS_TSCALE 6
 int scvs_ws_export(scvs_ws ws, int which, void* out);
 int scvs_ws_set_params(scvs_ws ws, const float* params);
 /* Loss and gradients of the MLP on given inputs x[n][3] and targets t[n][2*rank] (host). */

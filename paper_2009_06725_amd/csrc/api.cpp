@@ -644,6 +644,8 @@ int scvs_ws_export(scvs_ws ws, int which, void* out) {
       case SCVS_WS_PARAMS: scvs::download((float*)out, ws->net.p.p, ws->net.nparam, s); break;
       case SCVS_WS_TARGETS: memcpy(out, ws->targets.data(), sizeof(float) * ws->targets.size()); break;
       case SCVS_WS_NPARAM: *(int64_t*)out = ws->net.nparam; break;
+      case SCVS_WS_TMEAN: memcpy(out, ws->tmean.data(), sizeof(double) * ws->tmean.size()); break;
+      case SCVS_WS_TSCALE: memcpy(out, ws->tscale.data(), sizeof(double) * ws->tscale.size()); break;
       default: fail(SCVS_E_INVALID, "unknown export selector");
     }
   });

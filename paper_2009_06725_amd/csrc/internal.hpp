@@ -545,7 +545,9 @@ struct scvs_ws_s {
   scvs::DBuf<double> sigma_d;     // [r]
   std::vector<double> sigma;      // [r]
   std::vector<double> omega;      // [S] snapshot frequencies
-  std::vector<float> targets;     // [S][2r] POD coefficients sigma_i conj(W_si) / sigma_0
+  std::vector<float> targets;     // [S][2r] standardized POD coefficients (t - tmean) / tscale
+  std::vector<double> tmean, tscale;  // [2r] per output, over the snapshots
+  scvs::DBuf<double> tstd_d;      // [4r] tmean then tscale on the device
   scvs::Mlp net;
   scvs::MlpWork work;
   scvs::DBuf<float> X, T;         // training inputs/targets on the device

@@ -332,14 +332,17 @@ __global__ void k_features(const double* __restrict__ omega, int n, double wmax,
   x[i * 3 + 2] = (float)(w * w);
 }
 
-// coef[s][i] = amp_s * sigma_0 * (out[s][i] + j out[s][r+i])
+// coef[s][i] = amp_s * sigma_0 * (t_i + j t_{r+i}) with t_o = tmean_o + tscale_o out[s][o]
+// (ts: tmean [2r] then tscale [2r])
 __global__ void k_ws_coef(const float* __restrict__ out, int n, int r, double sigma0,
-                          const double2* __restrict__ amp, double2* __restrict__ coef) {
+                          const double* __restrict__ ts, const double2* __restrict__ amp,
+                          double2* __restrict__ coef) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= n * r) return;
   const int s = e / r, i = e % r;
-  const double2 c = make_double2(sigma0 * out[(int64_t)s * 2 * r + i], sigma0 * out[(int64_t)s * 2 * r + r + i]);
-  coef[e] = cmul(amp[s], c);
+  const double re = ts[i] + ts[2 * r + i] * (double)out[(int64_t)s * 2 * r + i];
+  const double im = ts[r + i] + ts[3 * r + i] * (double)out[(int64_t)s * 2 * r + r + i];
+  coef[e] = cmul(amp[s], make_double2(sigma0 * re, sigma0 * im));
 }
 
 inline unsigned nb256(int64_t n) { return (unsigned)((n + 255) / 256); }
@@ -446,24 +449,45 @@ void ws_build(scvs_ws w, int64_t S, const double* omega, const double2* snaps, i
   std::vector<std::complex<double>> A = cross(w->mesh->ctx, snaps, (int)S, snaps, (int)S, N, "k_gram"), V;
   std::vector<double> lam;
   herm_eig((int)S, A, lam, V);
-  // basis coefficients C[s][i] = W_si / sigma_i; snapshot s = sum_i sigma_i conj(W_si) phi_i, so the
-  // targets are sigma_i conj(W_si) / sigma_0: the loss weighs each coefficient by its share of the solution
+  // basis coefficients C[s][i] = W_si / sigma_i; snapshot s = sum_i sigma_i conj(W_si) phi_i, so its
+  // coefficients relative to sigma_0 are t_si = sigma_i conj(W_si) / sigma_0 (real parts, then
+  // imaginary parts). Each of the 2r outputs is standardized over the snapshots (mean removed,
+  // divided by the RMS deviation; an output that does not vary keeps scale 1), so the network
+  // fits every coefficient to the same relative accuracy. Without it the trailing coefficients,
+  // small but on the basis vectors the operator amplifies most, carry the network's absolute error.
   w->sigma.resize(r);
   const double sig0 = S > 0 ? std::sqrt(std::max(lam[0], 0.0)) : 0.0;
   w->sigma0 = sig0;
   std::vector<std::complex<double>> C((size_t)S * r);
-  w->targets.assign((size_t)S * 2 * r, 0.f);
+  std::vector<double> t((size_t)S * 2 * r, 0.0);
   for (int i = 0; i < r; ++i) {
     const double sg = i < S ? std::sqrt(std::max(lam[i], 0.0)) : 0.0;
     w->sigma[i] = sg;
     for (int64_t sn = 0; sn < S; ++sn) {
       const std::complex<double> wsi = i < S ? V[(size_t)sn * S + i] : 0.0;
       C[(size_t)sn * r + i] = sg > 0 ? wsi / sg : 0.0;
-      const std::complex<double> t = sig0 > 0 ? std::conj(wsi) * (sg / sig0) : 0.0;
-      w->targets[(size_t)sn * 2 * r + i] = (float)t.real();
-      w->targets[(size_t)sn * 2 * r + r + i] = (float)t.imag();
+      const std::complex<double> ti = sig0 > 0 ? std::conj(wsi) * (sg / sig0) : 0.0;
+      t[(size_t)sn * 2 * r + i] = ti.real();
+      t[(size_t)sn * 2 * r + r + i] = ti.imag();
     }
   }
+  w->tmean.assign(2 * r, 0.0);
+  w->tscale.assign(2 * r, 1.0);
+  w->targets.assign((size_t)S * 2 * r, 0.f);
+  for (int o = 0; o < 2 * r; ++o) {
+    double mu = 0.0, var = 0.0;
+    for (int64_t sn = 0; sn < S; ++sn) mu += t[(size_t)sn * 2 * r + o];
+    mu /= (double)std::max<int64_t>(S, 1);
+    for (int64_t sn = 0; sn < S; ++sn) var += (t[(size_t)sn * 2 * r + o] - mu) * (t[(size_t)sn * 2 * r + o] - mu);
+    const double sd = std::sqrt(var / (double)std::max<int64_t>(S, 1));
+    w->tmean[o] = mu;
+    w->tscale[o] = sd > 0.0 ? sd : 1.0;
+    for (int64_t sn = 0; sn < S; ++sn)
+      w->targets[(size_t)sn * 2 * r + o] = (float)((t[(size_t)sn * 2 * r + o] - mu) / w->tscale[o]);
+  }
+  std::vector<double> ts(w->tmean);  // host copy lives until the synchronize below
+  ts.insert(ts.end(), w->tscale.begin(), w->tscale.end());
+  w->tstd_d.upload(ts.data(), ts.size(), s);
   DBuf<double2> Cd;
   Cd.upload(reinterpret_cast<double2*>(C.data()), C.size(), s);
   w->basis.alloc((size_t)r * N);
@@ -509,7 +533,7 @@ void ws_predict(scvs_ws w, int64_t n, const double* omega, const double* amp, do
   w->work.ensure(w->net, (int)std::max<int64_t>(n, w->S));
   const float* y = mlp_forward(w->net, w->work, X, (int)n, s);
   coef.alloc((size_t)n * w->r);
-  k_ws_coef<<<nb256(n * w->r), 256, 0, s>>>(y, (int)n, w->r, w->sigma0, a, coef);
+  k_ws_coef<<<nb256(n * w->r), 256, 0, s>>>(y, (int)n, w->r, w->sigma0, w->tstd_d, a, coef);
   {
     ProfScope ps(&w->mesh->ctx->prof, s, "k_ws_combine", (double)w->ndof * 16.0 * (w->r + n));
     k_ws_combine<<<dim3(512, (unsigned)n), 256, 0, s>>>(w->basis, w->ndof, w->r, coef, x0, 0);

@@ -30,7 +30,7 @@ EXPORTED = [
     "scvs_ws_create", "scvs_ws_train", "scvs_ws_predict", "scvs_ws_refine", "scvs_ws_destroy", "scvs_ws_export",
     "scvs_ws_set_params", "scvs_ws_loss_grad", "scvs_herm_eig", "scvs_probe_mfma_bf16",
 ]
-WS_SIGMA, WS_BASIS, WS_PARAMS, WS_TARGETS, WS_NPARAM = range(5)
+WS_SIGMA, WS_BASIS, WS_PARAMS, WS_TARGETS, WS_NPARAM, WS_TMEAN, WS_TSCALE = range(7)
 
 
 class ScvsError(RuntimeError):
@@ -518,6 +518,8 @@ class WarmStart:
     def export(self, which: int):
         if which == WS_SIGMA:
             out = np.zeros(self.rank)
+        elif which in (WS_TMEAN, WS_TSCALE):
+            out = np.zeros(2 * self.rank)
         elif which == WS_PARAMS:
             out = np.zeros(self.nparam(), np.float32)
         elif which == WS_TARGETS:
@@ -555,6 +557,83 @@ class WarmStart:
             self.close()
         except Exception:
             pass
+
+
+class ModeWarmStarts:
+    """One WarmStart per harmonic index (a POD basis per mode). Model k is built
+    from unit-amplitude solutions of harmonic k at several periods, so its network
+    only has to cover that harmonic's band of frequencies. `models` maps k to
+    (omega [S], snaps device c128 [S, ndof]); systems are routed to the model of
+    their harmonic. A group of systems whose rows are contiguous is passed as a
+    view; otherwise its rows are gathered and scattered back."""
+
+    def __init__(self, mesh: Mesh, models: dict | None = None, rank: int = 16, width: int = 256, layers: int = 4,
+                 seed: int = 0):
+        self.mesh, self.rank, self.width, self.layers, self.seed = mesh, rank, width, layers, seed
+        self.ws = {}
+        for k, (om, snaps) in (models or {}).items():
+            self.add(k, om, snaps)
+
+    def add(self, k: int, omega, snaps):
+        """Model of harmonic k from its snapshots (the library copies the basis)."""
+        if int(k) in self.ws:
+            raise ScvsError(E_INVALID, f"harmonic {int(k)} already has a model")
+        self.ws[int(k)] = WarmStart(self.mesh, omega, snaps, rank=min(self.rank, len(omega)), width=self.width,
+                                    layers=self.layers, seed=self.seed + int(k))
+
+    def train(self, schedule) -> dict:
+        """schedule: [(epochs, lr), ...]; returns {k: (initial loss, final loss)}."""
+        out = {}
+        for k, w in self.ws.items():
+            l0 = loss = w.train(0)
+            for ep, lr in schedule:
+                loss = w.train(ep, lr)
+            out[k] = (l0, loss)
+        return out
+
+    def _groups(self, modes):
+        modes = np.asarray(modes, np.int64)
+        for k in np.unique(modes):
+            if int(k) not in self.ws:
+                raise ScvsError(E_INVALID, f"no model for harmonic {int(k)}")
+            rows = np.nonzero(modes == k)[0]
+            contiguous = rows[-1] - rows[0] + 1 == rows.size
+            yield self.ws[int(k)], rows, (slice(int(rows[0]), int(rows[-1]) + 1) if contiguous else None)
+
+    def predict(self, modes, omega, amp, out=None):
+        import torch
+        om = np.asarray(omega, np.float64)
+        a = np.asarray(amp, np.complex128)
+        if out is None:
+            out = torch.empty((om.size, self.mesh.info.ndof), dtype=torch.complex128,
+                              device=torch.device("cuda", self.mesh.ctx.device))
+        for w, rows, sl in self._groups(modes):
+            if sl is not None:
+                w.predict(om[rows], a[rows], out=out[sl])
+            else:
+                out[torch.from_numpy(rows).to(out.device)] = w.predict(om[rows], a[rows])
+        return out
+
+    def refine(self, modes, omega, traction, g, x0):
+        import torch
+        om = np.asarray(omega, np.float64)
+        tr = np.asarray(traction, np.complex128).reshape(om.size, -1)
+        for w, rows, sl in self._groups(modes):
+            gk = None if g is None else (g[sl] if sl is not None else g[torch.from_numpy(rows).to(g.device)].contiguous())
+            if sl is not None:
+                w.refine(om[rows], tr[rows], gk, x0[sl])
+            else:
+                idx = torch.from_numpy(rows).to(x0.device)
+                x0[idx] = w.refine(om[rows], tr[rows], gk, x0[idx].contiguous())
+        return x0
+
+    def sigma(self) -> dict:
+        return {k: w.export(WS_SIGMA) for k, w in self.ws.items()}
+
+    def close(self):
+        for w in self.ws.values():
+            w.close()
+        self.ws = {}
 
 
 def herm_eig(a: np.ndarray):

@@ -76,9 +76,17 @@ def test_pod_matches_oracle(pipe):
     P2 = Phi_o[:, :k] @ Phi_o[:, :k].conj().T
     assert np.abs(P1 - P2).max() < tol
     assert np.abs(Phi[:, :k].conj().T @ Phi[:, :k] - np.eye(k)).max() < 1e-10
-    # targets and basis rebuild the projection of every snapshot:
-    # sigma_0 sum_i t_si phi_i = Phi Phi^H x_s
-    T = ws.export(scvs.WS_TARGETS).astype(np.float64)
+    # the network's targets are standardized per output: zero mean and unit RMS
+    # over the snapshots
+    Z = ws.export(scvs.WS_TARGETS).astype(np.float64)
+    mu, sc = ws.export(scvs.WS_TMEAN), ws.export(scvs.WS_TSCALE)
+    assert np.abs(Z.mean(0)).max() < 1e-6
+    varies = sc != 1.0  # an output that does not vary keeps scale 1 and target 0
+    assert np.abs(np.sqrt((Z[:, varies] ** 2).mean(0)) - 1.0).max() < 1e-5
+    assert np.all(Z[:, ~varies] == 0.0)
+    # de-standardized, targets and basis rebuild the projection of every
+    # snapshot: sigma_0 sum_i t_si phi_i = Phi Phi^H x_s
+    T = mu[None, :] + sc[None, :] * Z
     coef = sig_o[0] * (T[:, :r] + 1j * T[:, r:])
     rec = Phi @ coef.T
     proj = Phi @ (Phi.conj().T @ Xh)
