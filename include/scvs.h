@@ -73,6 +73,16 @@ const char* scvs_version(void);
 int scvs_ctx_create(int device, void* stream, scvs_ctx* out);
 int scvs_ctx_destroy(scvs_ctx ctx);
 
+/* Memory cap of a context: the device bytes that one scvs_solve (or one group of
+ * scvs_solve_groups) may take for its pool of Krylov slots, on top of its inputs,
+ * outputs and the mesh's own matrices and hierarchies. The modes are independent
+ * (section 2.4, step 3), so the cap only decides how many are solved at once: the
+ * pool holds min(nsys, max_batch, what fits) slots and refills them from the
+ * remaining systems. 0 (the default) = 90% of the free device memory at the call;
+ * a nonzero cap is used when it is smaller than that. A cap below one system's
+ * workspace makes the solve fail with SCVS_E_NOMEM. */
+int scvs_ctx_set_mem_cap(scvs_ctx ctx, uint64_t bytes);
+
 /* ---- a1: mesh ingest, numbering, sparsity (section 2.3, Eq. shape_fun) ----
  * dim 2 (triangles) or 3 (tets). Host inputs, copied:
  *   xyz    double[nv][dim]    vertex coordinates
@@ -320,14 +330,18 @@ int scvs_solve_groups(int n, const scvs_solve_group* groups);
 /* ---- a8: autotuner ----
  * Times candidate solver settings on the caller's own systems (the same
  * arguments as scvs_solve, no initial guesses) and returns the fastest in
- * `best` (and its solve time in *best_ms, may be NULL). The candidates vary the
- * restart length (160, 220), the pressure and velocity Chebyshev degrees
- * (30/50, 10/12); every other field, including the precision, the tolerance and
- * the orthogonalization, comes from `base` (NULL: the defaults). A candidate
- * counts only if all systems converge. Each candidate is one full solve, so a
- * call costs about 8 solves; the choice is cached in the context per (mesh,
- * assembly, number of systems, precision, rtol) and later calls return it at
- * once. Reassembly or new boundary conditions start a new entry. */
+ * `best` (and its solve time in *best_ms, may be NULL). With the Chebyshev
+ * velocity block (vel_block = 0) the candidates vary the restart length (160,
+ * 220) and the pressure and velocity Chebyshev degrees (30/50, 10/12); with the
+ * multigrid velocity block (vel_block = 1) they vary the restart length (30,
+ * 40, 60), the smoothing steps (1, 2) and the smoother interval ratio (4, 10).
+ * Every other field, including the precision, the tolerance and the
+ * orthogonalization, comes from `base` (NULL: the defaults). A candidate counts
+ * only if all systems converge. Each candidate is one full solve, so a call
+ * costs 8 or 12 solves; the choice is cached in the context per (mesh,
+ * assembly, number of systems, every option that is not tuned) and later calls
+ * return it at once, the tuned fields over the caller's other options.
+ * Reassembly or new boundary conditions start a new entry. */
 int scvs_autotune(scvs_mesh mesh, int64_t nsys, const double* omega, const double* traction, const void* g,
                   const scvs_solve_opts* base, scvs_solve_opts* best, double* best_ms);
 

@@ -66,11 +66,21 @@ scvs_solve_opts checked_opts(const scvs_solve_opts* opts) {
 }
 
 // Every option the autotuner does not choose (and that changes the solve), as a key.
-std::string untuned_key(const scvs_solve_opts& o) {
+std::string untuned_key(const scvs_solve_opts& oin) {
+  scvs_solve_opts o = oin;
+  o.restart = 0;
+  if (o.vel_block == 1) {  // tuned with the multigrid velocity block
+    o.mg_smooth = 0;
+    o.mg_ratio = 0.0;
+  } else {  // tuned with the Chebyshev velocity block
+    o.cheb_vel = 0;
+    o.cheb_pres = 0;
+  }
   char buf[512];
-  snprintf(buf, sizeof buf, "%.17g|%d|%.17g|%d|%d|%d|%d|%.17g|%.17g|%.17g|%d|%d|%d|%.17g|%.17g|%d", o.rtol,
+  snprintf(buf, sizeof buf, "%.17g|%d|%.17g|%d|%d|%d|%d|%.17g|%.17g|%.17g|%d|%d|%d|%.17g|%.17g|%d|%d|%d", o.rtol,
            o.max_iters, o.cheb_ratio, o.max_batch, o.use_graph, o.precision, o.orth, o.cheb_ratio_pres, o.penalty,
-           o.inner_rtol, o.vel_block, o.pres_block, o.mg_smooth, o.mg_ratio, o.steady_schur_omega, o.mg_post0);
+           o.inner_rtol, o.vel_block, o.pres_block, o.mg_smooth, o.mg_ratio, o.steady_schur_omega, o.mg_post0,
+           o.cheb_vel, o.cheb_pres);
   return buf;
 }
 
@@ -101,6 +111,13 @@ int scvs_ctx_create(int device, void* stream, scvs_ctx* out) {
       fail(SCVS_E_HIP, "hipStreamCreateWithFlags failed");
     }
     *out = c;
+  });
+}
+
+int scvs_ctx_set_mem_cap(scvs_ctx ctx, uint64_t bytes) {
+  return guarded([&] {
+    SCVS_REQUIRE(ctx, SCVS_E_INVALID, "ctx is null");
+    ctx->mem_cap = bytes;
   });
 }
 
@@ -446,28 +463,40 @@ int scvs_autotune(scvs_mesh m, int64_t nsys, const double* omega, const double* 
       u.alloc((size_t)nsys * m->n2 * m->dim);
       p.alloc((size_t)nsys * m->nv);
       std::vector<scvs_report> rep(nsys);
-      scvs_ctx_s::Tuned pick{b.restart, b.cheb_vel, b.cheb_pres, -1.0};
-      const int ms_[] = {160, 220};
-      const int kp_[] = {30, 50};
-      const int kv_[] = {10, 12};
-      for (int mm : ms_)
-        for (int kp : kp_)
-          for (int kv : kv_) {
-            scvs_solve_opts c = b;
-            c.restart = std::min(mm, SCVS_MMAX);
-            c.cheb_pres = kp;
-            c.cheb_vel = kv;
-            const auto t0 = std::chrono::steady_clock::now();
-            scvs::solve_systems(m, nsys, omega, traction, m->ndir ? g : nullptr, nullptr, u.p, p.p, &c, rep.data());
-            const double ms =
-                std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-            bool ok = true;
-            for (const auto& r : rep) ok = ok && r.status == 0;
-            if (b.verbose)
-              fprintf(stderr, "[scvs] autotune m %d Chebyshev %d/%d: %.1f ms%s\n", c.restart, kv, kp, ms,
-                      ok ? "" : " (not converged)");
-            if (ok && (pick.ms < 0.0 || ms < pick.ms)) pick = {c.restart, kv, kp, ms};
-          }
+      scvs_ctx_s::Tuned pick{b.restart, b.cheb_vel, b.cheb_pres, b.mg_smooth, b.mg_ratio, -1.0};
+      std::vector<scvs_solve_opts> cand;
+      if (b.vel_block == 1) {
+        for (int mm : {30, 40, 60})
+          for (int sm : {1, 2})
+            for (double rt : {4.0, 10.0}) {
+              scvs_solve_opts c = b;
+              c.restart = mm;
+              c.mg_smooth = sm;
+              c.mg_ratio = rt;
+              cand.push_back(c);
+            }
+      } else {
+        for (int mm : {160, 220})
+          for (int kp : {30, 50})
+            for (int kv : {10, 12}) {
+              scvs_solve_opts c = b;
+              c.restart = std::min(mm, SCVS_MMAX);
+              c.cheb_pres = kp;
+              c.cheb_vel = kv;
+              cand.push_back(c);
+            }
+      }
+      for (const scvs_solve_opts& c : cand) {
+        const auto t0 = std::chrono::steady_clock::now();
+        scvs::solve_systems(m, nsys, omega, traction, m->ndir ? g : nullptr, nullptr, u.p, p.p, &c, rep.data());
+        const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        bool ok = true;
+        for (const auto& r : rep) ok = ok && r.status == 0;
+        if (b.verbose)
+          fprintf(stderr, "[scvs] autotune m %d Chebyshev %d/%d multigrid %d steps ratio %g: %.1f ms%s\n", c.restart,
+                  c.cheb_vel, c.cheb_pres, c.mg_smooth, c.mg_ratio, ms, ok ? "" : " (not converged)");
+        if (ok && (pick.ms < 0.0 || ms < pick.ms)) pick = {c.restart, c.cheb_vel, c.cheb_pres, c.mg_smooth, c.mg_ratio, ms};
+      }
       SCVS_REQUIRE(pick.ms >= 0.0, SCVS_E_STATE, "no candidate configuration converged");
       hit = m->ctx->tuned.emplace(key, pick).first;
     }
@@ -476,6 +505,8 @@ int scvs_autotune(scvs_mesh m, int64_t nsys, const double* omega, const double* 
     best->restart = hit->second.restart;
     best->cheb_vel = hit->second.cheb_vel;
     best->cheb_pres = hit->second.cheb_pres;
+    best->mg_smooth = hit->second.mg_smooth;
+    best->mg_ratio = hit->second.mg_ratio;
     if (best_ms) *best_ms = hit->second.ms;
   });
 }

@@ -133,12 +133,13 @@ struct scvs_ctx_s {
   int device = 0;
   hipStream_t stream = nullptr;   // caller's stream: all work runs here
   hipStream_t capture = nullptr;  // private stream used only to record graphs
+  uint64_t mem_cap = 0;           // bytes a solve's Krylov slot pool may take (0: 90% of free memory)
   scvs::Profiler prof;
   // autotuner results, keyed by (mesh id, operator generation, systems, every caller option
   // that the tuner does not choose); only the tuned fields are kept
   struct Tuned {
-    int restart, cheb_vel, cheb_pres;
-    double ms;
+    int restart, cheb_vel, cheb_pres, mg_smooth;
+    double mg_ratio, ms;
   };
   std::map<std::tuple<uint64_t, uint64_t, int64_t, std::string>, Tuned> tuned;
 };

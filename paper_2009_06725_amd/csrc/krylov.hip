@@ -1075,8 +1075,9 @@ int solve_systems(scvs_mesh m, int64_t nsys, const double* omega, const double* 
   P.ld = (ndof + 63) / 64 * 64;
   P.DN = DN;
   P.nv = m->nv;
-  // batch size from free memory (keep 10% spare); a long restart that would leave
-  // room for fewer than min(nsys, 8) systems is shortened (not below 30) first
+  // batch size from free memory (keep 10% spare), or from the context's memory cap if that
+  // is smaller; a long restart that would leave room for fewer than min(nsys, 8) systems
+  // is shortened (not below 30) first
   size_t fr = 0, tot = 0;
   SCVS_HIP(hipMemGetInfo(&fr, &tot));
   const int nch_max = choose_nch(1, ndof);
@@ -1100,18 +1101,24 @@ int solve_systems(scvs_mesh m, int64_t nsys, const double* omega, const double* 
                (pmg ? (size_t)m->nv * sizeof(double2) : 0) + mg_buffer_bytes(m, 1, esz, vmg, pmg) +
                sizeof(double) * mg_levels(m, true);
   }
+  double budget = (double)fr * 0.9;
+  if (m->ctx->mem_cap > 0) budget = std::min(budget, (double)m->ctx->mem_cap);
   int mk = o->restart;
   const int64_t want = std::min<int64_t>(nsys, 8);
-  while (mk > 30 && (int64_t)((double)fr * 0.9 /
-                              (double)(slot_bytes(P.ld, mk, DN, m->nv, nch_max, mixed, P.v32) + mg_extra)) < want)
+  while (mk > 30 &&
+         (int64_t)(budget / (double)(slot_bytes(P.ld, mk, DN, m->nv, nch_max, mixed, P.v32) + mg_extra)) < want)
     mk = std::max(30, mk * 3 / 4);
   if (o->verbose && mk != o->restart) fprintf(stderr, "[scvs] restart shortened to %d to fit memory\n", mk);
   P.m = mk;
   const size_t per = slot_bytes(P.ld, mk, DN, m->nv, nch_max, mixed, P.v32) + mg_extra;
-  int64_t fit = (int64_t)((double)fr * 0.9 / (double)per);
-  SCVS_REQUIRE(fit >= 1, SCVS_E_NOMEM, "not enough device memory for one system's Krylov workspace");
+  int64_t fit = (int64_t)(budget / (double)per);
+  SCVS_REQUIRE(fit >= 1, SCVS_E_NOMEM,
+               "not enough device memory (or memory cap) for one system's Krylov workspace of " +
+                   std::to_string(per) + " bytes");
   int B = (int)std::min<int64_t>(nsys, fit);
   if (o->max_batch > 0) B = std::min(B, o->max_batch);
+  if (o->verbose)
+    fprintf(stderr, "[scvs] slot pool: %d slots of %zu bytes (budget %.0f bytes)\n", B, per, budget);
   P.slots = B;
   P.V.alloc(P.v32 ? ((size_t)B * (mk + 1) * P.ld + 1) / 2 : (size_t)B * (mk + 1) * P.ld);
   P.W.alloc((size_t)B * 4 * P.ld);

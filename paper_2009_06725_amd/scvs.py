@@ -21,7 +21,8 @@ BC_FREE, BC_WALL, BC_DIRICHLET, BC_TRACTION = 0, 1, 2, 3
  X_C21COL) = range(14)
 
 EXPORTED = [
-    "scvs_last_error", "scvs_version", "scvs_ctx_create", "scvs_ctx_destroy", "scvs_mesh_create",
+    "scvs_last_error", "scvs_version", "scvs_ctx_create", "scvs_ctx_destroy", "scvs_ctx_set_mem_cap",
+    "scvs_mesh_create",
     "scvs_mesh_destroy", "scvs_mesh_info", "scvs_mesh_set_midside", "scvs_mesh_set_bc", "scvs_mesh_set_windkessel",
     "scvs_assemble",
     "scvs_mesh_export", "scvs_spmv", "scvs_rhs", "scvs_solve_opts_default", "scvs_solve",
@@ -86,6 +87,7 @@ def lib() -> C.CDLL:
         L.scvs_version.restype = C.c_char_p
         L.scvs_ctx_create.argtypes = [C.c_int, vp, C.POINTER(vp)]
         L.scvs_ctx_destroy.argtypes = [vp]
+        L.scvs_ctx_set_mem_cap.argtypes = [vp, C.c_uint64]
         L.scvs_mesh_create.argtypes = [vp, C.c_int, i64, vp, i64, vp, i64, vp, vp, C.POINTER(vp)]
         L.scvs_mesh_destroy.argtypes = [vp]
         L.scvs_mesh_info.argtypes = [vp, C.POINTER(MeshInfo)]
@@ -140,6 +142,7 @@ def _host(a, dtype):
 
 
 E_INVALID = -1
+E_NOMEM = -3
 SCVS_NOALLOC_MAX_SYSTEMS = 256  # include/scvs.h
 
 
@@ -188,6 +191,10 @@ class Context:
         h = C.c_void_p()
         _check(lib().scvs_ctx_create(device, C.c_void_p(stream.cuda_stream), C.byref(h)))
         self.h = h
+
+    def set_mem_cap(self, nbytes: int):
+        """Device bytes a solve's Krylov slot pool may take (0: 90% of free memory)."""
+        _check(lib().scvs_ctx_set_mem_cap(self.h, int(nbytes)))
 
     def profile(self, on: bool):
         """Time every library kernel launch with HIP events on this context's stream."""

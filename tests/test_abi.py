@@ -40,6 +40,7 @@ def test_version_and_errors_without_gpu(lib):
     # null out-pointer: rejected before touching any device
     assert lib.scvs_ctx_create(0, None, None) == -1
     assert b"null" in lib.scvs_last_error()
+    assert lib.scvs_ctx_set_mem_cap(None, C.c_uint64(1 << 30)) == -1
     # null mesh: rejected by validation
     assert lib.scvs_mesh_info(None, None) == -1
     o = scvs.default_opts()

@@ -351,6 +351,34 @@ def test_autotune_keeps_caller_options(ctx):
     assert (best0b.restart, best0b.cheb_vel, best0b.cheb_pres) == (best0.restart, best0.cheb_vel, best0.cheb_pres)
 
 
+def test_autotune_multigrid_blocks(ctx):
+    """With the multigrid velocity block the autotuner picks the restart, the
+    smoothing steps and the smoother interval ratio from its candidates, serves
+    the cached choice to a caller whose own values of those three differ, and
+    the choice solves to the mixed path's LU accuracy."""
+    from paper_2009_06725_amd import scvs
+    c = cases.y_bifurcation_case(h=0.45, n_harm=3)
+    m = gpu_mesh(ctx, c)
+    g = gpu_dirichlet(m, c, torch)
+    kw = dict(rtol=1e-12, precision=1, vel_block=1, pres_block=1)
+    base = scvs.default_opts(**kw)
+    best, ms = m.autotune(c["omega"], c["traction"], g, base=base)
+    print(f"[gpu] multigrid autotune: m {best.restart}, {best.mg_smooth} steps, ratio {best.mg_ratio}: {ms:.1f} ms",
+          flush=True)
+    assert best.restart in (30, 40, 60) and best.mg_smooth in (1, 2) and best.mg_ratio in (4.0, 10.0) and ms > 0
+    assert best.vel_block == 1 and best.precision == 1 and best.cheb_pres == base.cheb_pres
+    other = scvs.default_opts(restart=99, mg_smooth=3, mg_ratio=7.0, **kw)
+    best2, ms2 = m.autotune(c["omega"], c["traction"], g, base=other)
+    assert (best2.restart, best2.mg_smooth, best2.mg_ratio, ms2) == (best.restart, best.mg_smooth, best.mg_ratio, ms)
+    asm, loads, wall, dirn, gv = case_setup(c)
+    u_o, p_o, _, _ = solve_modes(asm, loads, wall, dirn, c["omega"], c["rho"], c["mu"], c["traction"], gv)
+    u, p, rep = m.solve(c["omega"], c["traction"], g, opts=best)
+    assert all(r.status == 0 for r in rep)
+    for s in range(len(c["omega"])):
+        eu, ep = rel_l2(asm, u[s].cpu().numpy(), u_o[s], p[s].cpu().numpy(), p_o[s])
+        assert eu <= 1e-8 and ep <= 1e-8
+
+
 def test_solve_groups_equal_single_solves():
     """Several meshes solved concurrently (one context and stream each) give the
     same modes, bit for bit, as their separate solves."""
