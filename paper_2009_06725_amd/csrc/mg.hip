@@ -1074,43 +1074,54 @@ __global__ void k_zero_slots(double* a, const int* act, int n) {
 
 // k_mg_bound on level 0 in sliced rows: one lane per (row, system), the same sums in
 // the same entry order, FP64 accumulation of the sliced values (FP32 values on the
-// mixed path).
+// mixed path). The blocks stride over the row blocks; each lane keeps the largest ratio
+// of its system over the rows it visits, the wavefront reduces over the lanes of the
+// same system (lane mod W), and one lane per system issues the atomic. A maximum does
+// not depend on the order, so the bound is the same as with one atomic per (row, system),
+// without tens of millions of atomics on a few addresses. Systems beyond the W lanes of
+// a row are taken in further passes of W.
 template <class R>
 __global__ void __launch_bounds__(256) k_mg_bound_sell(LevelArgs<double> la, SellArgs<R> sa, Batch b, int W, int RW,
                                                        unsigned long long* __restrict__ out) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int64_t q = (row_block() * 4 + wave) * RW + lane / W;
-  if (q >= sa.nslot) return;
-  const int32_t i = sa.row[q];
-  if (i < 0) return;
-  if (la.dmask && la.dmask[i] != 0) return;
-  const int64_t sl = q / SELL_C, e0 = sa.off[sl] + q % SELL_C;
-  const int len = (int)((sa.off[sl + 1] - sa.off[sl]) / SELL_C);
-  for (int si = lane & (W - 1); si < b.nact; si += W) {
-    const int slot = b.act[si];
-    const double wr = b.omega[slot] * la.rho;
-    double sum = 0.0;
-    for (int t = 0; t < len; t += 4) {
-      int32_t c[4];
-      double k[4], m[4];
+  const int64_t nrb = (sa.nslot + 4 * RW - 1) / (4 * RW);
+  for (int s0 = 0; s0 < b.nact; s0 += W) {
+    const int si = s0 + (lane & (W - 1));
+    const int slot = si < b.nact ? b.act[si] : -1;
+    const double wr = slot >= 0 ? b.omega[slot] * la.rho : 0.0;
+    double vmax = 0.0;
+    for (int64_t rb = blockIdx.x; rb < nrb; rb += gridDim.x) {
+      const int64_t q = (rb * 4 + wave) * RW + lane / W;
+      if (slot < 0 || q >= sa.nslot) continue;
+      const int32_t i = sa.row[q];
+      if (i < 0 || (la.dmask && la.dmask[i] != 0)) continue;
+      const int64_t sl = q / SELL_C, e0 = sa.off[sl] + q % SELL_C;
+      const int len = (int)((sa.off[sl + 1] - sa.off[sl]) / SELL_C);
+      double sum = 0.0;
+      for (int t = 0; t < len; t += 4) {
+        int32_t c[4];
+        double k[4], m[4];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const bool v = t + u < len;
-        const int64_t e = e0 + (int64_t)(t + u) * SELL_C;
-        c[u] = v ? sa.col[e] : -1;
-        k[u] = v ? (double)sa.K[e] : 0.0;
-        m[u] = v ? (double)sa.M[e] : 0.0;
-      }
+        for (int u = 0; u < 4; ++u) {
+          const bool v = t + u < len;
+          const int64_t e = e0 + (int64_t)(t + u) * SELL_C;
+          c[u] = v ? sa.col[e] : -1;
+          k[u] = v ? (double)sa.K[e] : 0.0;
+          m[u] = v ? (double)sa.M[e] : 0.0;
+        }
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        if (c[u] < 0 || (la.dmask && la.dmask[c[u]] != 0)) continue;
-        const double re = la.mu * k[u], im = wr * m[u];
-        sum += sqrt(re * re + im * im);
+        for (int u = 0; u < 4; ++u) {
+          if (c[u] < 0 || (la.dmask && la.dmask[c[u]] != 0)) continue;
+          const double re = la.mu * k[u], im = wr * m[u];
+          sum += sqrt(re * re + im * im);
+        }
       }
+      const double dr = la.mu * la.Kd[i], di = wr * la.Md[i];
+      vmax = fmax(vmax, sum / sqrt(dr * dr + di * di));
     }
-    const double dr = la.mu * la.Kd[i], di = wr * la.Md[i];
-    const double v = sum / sqrt(dr * dr + di * di);
-    atomicMax(&out[slot], (unsigned long long)__double_as_longlong(v));
+    // every lane reaches this point; offsets of W and above keep lane mod W
+    for (int off = W; off < 64; off <<= 1) vmax = fmax(vmax, __shfl_xor(vmax, off));
+    if (lane < W && slot >= 0) atomicMax(&out[slot], (unsigned long long)__double_as_longlong(vmax));
   }
 }
 
@@ -1720,10 +1731,14 @@ void mg_prepare(scvs_mesh m, const Batch& b, double* lam, int slots, double2* in
     k_zero_slots<<<(b.nact + 63) / 64, 64, 0, s>>>(lam + l * slots, b.act, b.nact);
     unsigned long long* o = reinterpret_cast<unsigned long long*>(lam + l * slots);
     // level 0 from its sliced rows in the cycle's precision when they are there
+    // sliced level 0: at most 2048 blocks striding over the row blocks (one atomic per
+    // wavefront and system at the end)
     if (l == 0 && inv32 && s32.off)
-      k_mg_bound_sell<float><<<(unsigned)((s32.nslot + 4 * RW - 1) / (4 * RW)), 256, 0, s>>>(las[0], s32, b, W, RW, o);
+      k_mg_bound_sell<float><<<(unsigned)std::min<int64_t>(2048, (s32.nslot + 4 * RW - 1) / (4 * RW)), 256, 0, s>>>(
+          las[0], s32, b, W, RW, o);
     else if (l == 0 && !inv32 && s64.off)
-      k_mg_bound_sell<double><<<(unsigned)((s64.nslot + 4 * RW - 1) / (4 * RW)), 256, 0, s>>>(las[0], s64, b, W, RW, o);
+      k_mg_bound_sell<double><<<(unsigned)std::min<int64_t>(2048, (s64.nslot + 4 * RW - 1) / (4 * RW)), 256, 0, s>>>(
+          las[0], s64, b, W, RW, o);
     else
       k_mg_bound<true><<<row_blocks(las[l].n, lm), 256, 0, s>>>(las[l], b, lm, o);
     launch_check(s);
