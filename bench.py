@@ -117,6 +117,8 @@ def parse(argv=None):
                     help="ylearn: training periods per harmonic solved for its POD (its rank)")
     ap.add_argument("--ws-heldout", type=int, default=4,
                     help="ylearn: held-out waveforms timed (all harmonics of each)")
+    ap.add_argument("--no-graph-leg", action="store_true",
+                    help="skip re-running the first two waves with the event profiler off (graph replay on)")
     ap.add_argument("--no-error-check", action="store_true",
                     help="skip the tight-tolerance FP64 reference solve that estimates the error")
     ap.add_argument("--verbose", action="store_true")
@@ -665,9 +667,12 @@ def main():
     t0 = time.perf_counter()
     reps = []
     solved = 0
+    step_s = []
     for i in range(args.steps):
+        ts = time.perf_counter()
         rep, sel = step(i)
         torch.cuda.synchronize()
+        step_s.append(time.perf_counter() - ts)
         reps.append((rep, sel))
         solved += len(sel)
         log(f"step {i} done at {time.perf_counter() - t0:.2f}s systems {list(sel)} "
@@ -676,6 +681,23 @@ def main():
     dt = time.perf_counter() - t0
     stats = ctx.profile_read()
     ctx.profile(False)
+    graph_leg = None
+    if not args.no_graph_leg:
+        # the first waves again with the event profiler off, so the solver records and
+        # replays its graphs of Arnoldi chunks: what the event pairs of the timed steps cost
+        nw = min(2, args.steps)
+        log(f"graph leg: waves 0..{nw - 1} with graph replay ...")
+        tg = []
+        for i in range(nw):
+            ts = time.perf_counter()
+            rep_g, _ = step(i)
+            torch.cuda.synchronize()
+            tg.append(time.perf_counter() - ts)
+        graph_leg = {"waves": nw, "seconds_with_events": [round(x, 3) for x in step_s[:nw]],
+                     "seconds_with_graphs": [round(x, 3) for x in tg],
+                     "ratio": sum(tg) / sum(step_s[:nw]),
+                     "same_iterations": [r.iterations for r in rep_g] == [r.iterations for r in reps[nw - 1][0]]}
+        log(f"graph leg: {graph_leg}")
     conv = all(r.status == 0 for rep, _ in reps for r in rep)
     iters_by_system = {}
     for rep, sel in reps:
@@ -739,6 +761,7 @@ def main():
         "iterations": [iters_by_system[k] for k in sorted(iters_by_system)],
         "iterations_systems": sorted(iters_by_system),
         "kernels": kernels,
+        "graph_replay": graph_leg,
     }
     # mode selection on this workload: a-priori truncation error of the boundary data
     # (Eq. mode_error); the a-posteriori increments need every mode (one-wave workloads)
