@@ -433,8 +433,9 @@ def run_ylearn(args):
     m.mg_info(0)
     t_setup = time.perf_counter() - t0
     log(f"ylearn mesh {c['mesh'].name}: {c['mesh'].nc} tets, {info.ndof} unknowns ({t_setup:.1f}s)")
+    # training periods; the training waveforms' coefficients only scale their modes (linearity)
+    # and so never enter the snapshots, the POD or the networks
     t_train = np.sort(period_set(n_train, seed=61))
-    _ = harmonic_coefficients(n_harm, 62, n_waves=n_train)  # training coefficients: scale only, by linearity
     S = args.ws_snapshots
     ts = t_train[np.round(np.linspace(0, n_train - 1, S)).astype(int)]
     ks = np.repeat(np.arange(1, n_harm + 1), S)
