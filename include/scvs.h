@@ -210,7 +210,8 @@ typedef struct {
   double rtol;        /* stop when ||f - A x||_2 <= rtol ||f||_2 (true residual) */
   int32_t restart;    /* Krylov dimension m per cycle, 1..256 (shortened, not below 30, when
                          memory would hold fewer than min(nsys, 8) systems' workspaces) */
-  int32_t max_iters;  /* cap on Arnoldi steps per system */
+  int32_t max_iters;  /* cap on Arnoldi steps per system, applied at restart boundaries: a system
+                         stops (status 1) after the first cycle that reaches it */
   int32_t cheb_vel;   /* Chebyshev degree of the velocity block, >= 1 */
   int32_t cheb_pres;  /* Chebyshev degree of the pressure Laplacian, >= 1; 0 drops the j w rho L^-1
                          term (Schur block = mu Mp^-1, the pressure mass alone) */

@@ -202,3 +202,24 @@ def test_midside_after_bc_needs_new_bc(ctx):
     u1, p1, _ = m.solve(c["omega"], c["traction"], g, opts=o)
     u2, p2, _ = ref.solve(c["omega"], c["traction"], g, opts=o)
     assert torch.equal(u1, u2) and torch.equal(p1, p2)
+
+
+def test_non_finite_omega_and_iteration_cap(ctx):
+    """A non-finite frequency is a call error; a cap on the Arnoldi steps ends
+    the solve with status 1 (iteration cap) and finite modes, not an error. The
+    cap is applied at restart boundaries, so with restart 5 and cap 1 every
+    system stops after its first cycle of 5 steps."""
+    from paper_2009_06725_amd import scvs
+    c = cases.channel_case(n_harm=2)
+    m = gpu_mesh(ctx, c)
+    g = gpu_dirichlet(m, c, torch)
+    for bad in (np.nan, np.inf):
+        om = np.array(c["omega"], np.float64)
+        om[1] = bad
+        with pytest.raises(scvs.ScvsError) as e:
+            m.solve(om, c["traction"], g)
+        assert e.value.code == scvs.E_INVALID
+    u, p, rep = m.solve(c["omega"], c["traction"], g, opts=scvs.default_opts(rtol=1e-12, restart=5, max_iters=1))
+    print(f"[gpu] iteration cap: {[(r.status, r.iterations, r.restarts, r.rel_residual) for r in rep]}", flush=True)
+    assert all(r.status == 1 and 1 <= r.iterations <= 5 and r.rel_residual > 1e-12 for r in rep)
+    assert bool(torch.isfinite(torch.view_as_real(u)).all()) and bool(torch.isfinite(torch.view_as_real(p)).all())
